@@ -1,0 +1,294 @@
+"""ctypes binding of libpc.so (the C ABI declared in include/pc.h).
+
+Argument marshalling only: every step of the skeleton runs in the library's HIP kernels. PyTorch
+provides device memory and the stream. There is no CPU fallback: if libpc.so is missing the import
+of the binding fails.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpc.so")
+
+PC_MAX_LEVEL = 13
+
+PC_OK = 0
+PC_WARN_SAMPLE_LIMIT = 1
+PC_WARN_LEVEL_CAP = 2
+PC_ERR_INVALID_ARG = -1
+PC_ERR_SHAPE = -2
+PC_ERR_CONSTANT_COLUMN = -3
+PC_ERR_NONFINITE = -4
+PC_ERR_WORKSPACE = -5
+PC_ERR_HIP = -6
+PC_ERR_UNSUPPORTED = -7
+PC_ERR_SEPSET_CAPACITY = -8
+
+PC_PREC_FP64 = 0
+PC_PREC_FP32 = 1
+PC_PREC_BF16X3 = 2
+PRECISIONS = {"fp64": PC_PREC_FP64, "fp32": PC_PREC_FP32, "bf16x3": PC_PREC_BF16X3}
+
+
+class pc_options(ct.Structure):
+    _fields_ = [("precision", ct.c_int32), ("max_level", ct.c_int32), ("margin_scale", ct.c_float),
+                ("force_recheck_all", ct.c_int32), ("lds_budget", ct.c_int32),
+                ("ranks_per_lane", ct.c_int32), ("grid", ct.c_int32), ("timing", ct.c_int32),
+                ("recheck_cap", ct.c_int64)]
+
+
+class pc_sep_rec(ct.Structure):
+    _fields_ = [("i", ct.c_int32), ("j", ct.c_int32), ("level", ct.c_int32),
+                ("S", ct.c_int32 * PC_MAX_LEVEL)]
+
+
+class pc_sepset(ct.Structure):
+    _fields_ = [("recs", ct.c_void_p), ("cap", ct.c_int64), ("count", ct.c_void_p)]
+
+
+_NL = PC_MAX_LEVEL + 1
+
+
+class pc_run_stats(ct.Structure):
+    _fields_ = [("tests", ct.c_int64 * _NL), ("removed", ct.c_int64 * _NL),
+                ("rechecks", ct.c_int64 * _NL), ("items", ct.c_int64 * _NL),
+                ("audit_violations", ct.c_int64 * _NL), ("max_degree", ct.c_int32 * _NL),
+                ("levels_run", ct.c_int32), ("pad", ct.c_int32), ("corr_ms", ct.c_float),
+                ("compact_ms", ct.c_float * _NL), ("level_ms", ct.c_float * _NL),
+                ("wall_ms", ct.c_double)]
+
+    def as_dict(self) -> dict:
+        k = max(1, self.levels_run)
+        return {
+            "levels_run": self.levels_run,
+            "tests": list(self.tests[:k]),
+            "removed": list(self.removed[:k]),
+            "rechecks": list(self.rechecks[:k]),
+            "items": list(self.items[:k]),
+            "audit_violations": list(self.audit_violations[:k]),
+            "max_degree": list(self.max_degree[:k]),
+            "corr_ms": self.corr_ms,
+            "compact_ms": list(self.compact_ms[:k]),
+            "level_ms": list(self.level_ms[:k]),
+            "wall_ms": self.wall_ms,
+        }
+
+
+class PCError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+
+
+_lib = None
+
+
+def lib() -> ct.CDLL:
+    """Loads libpc.so; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1812_08491_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        vp, i64 = ct.c_void_p, ct.c_int64
+        L.pc_create.argtypes = [ct.POINTER(vp), vp, ct.POINTER(pc_options)]
+        L.pc_create.restype = ct.c_int
+        L.pc_destroy.argtypes = [vp]
+        L.pc_destroy.restype = None
+        L.pc_default_options.argtypes = [ct.POINTER(pc_options)]
+        L.pc_default_options.restype = ct.c_int
+        L.pc_workspace_bytes.argtypes = [i64, i64, ct.POINTER(pc_options)]
+        L.pc_workspace_bytes.restype = ct.c_size_t
+        L.pc_corr.argtypes = [vp, vp, i64, i64, ct.c_double, vp, ct.c_size_t, vp, vp]
+        L.pc_corr.restype = ct.c_int
+        L.pc_level.argtypes = [vp, ct.c_int, i64, i64, ct.c_double, vp, ct.POINTER(pc_sepset),
+                               ct.POINTER(pc_run_stats), vp, ct.c_size_t]
+        L.pc_level.restype = ct.c_int
+        L.pc_skeleton.argtypes = [vp, vp, i64, i64, ct.c_double, ct.c_int, vp, ct.POINTER(pc_sepset),
+                                  ct.POINTER(pc_run_stats), vp, ct.c_size_t]
+        L.pc_skeleton.restype = ct.c_int
+        L.pc_sync_status.argtypes = [vp, vp, ct.c_size_t]
+        L.pc_sync_status.restype = ct.c_int
+        L.pc_comb_unrank.argtypes = [ct.c_int32, ct.c_int32, ct.c_uint64, ct.c_int32,
+                                     ct.POINTER(ct.c_int32)]
+        L.pc_comb_unrank.restype = ct.c_int
+        L.pc_threshold.argtypes = [ct.c_double, ct.c_double, ct.c_int]
+        L.pc_threshold.restype = ct.c_double
+        L.pc_abi_size.argtypes = [ct.c_int]
+        L.pc_abi_size.restype = ct.c_size_t
+        L.pc_status_str.argtypes = [ct.c_int]
+        L.pc_status_str.restype = ct.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["pc_create", "pc_destroy", "pc_default_options", "pc_workspace_bytes", "pc_corr",
+            "pc_level", "pc_skeleton", "pc_sync_status", "pc_comb_unrank", "pc_threshold",
+            "pc_abi_size", "pc_status_str"]
+
+
+def check_abi() -> None:
+    """Raises if a ctypes struct disagrees in size with the library's."""
+    for k, cls in enumerate([pc_options, pc_sep_rec, pc_sepset, pc_run_stats]):
+        want = int(lib().pc_abi_size(k))
+        if ct.sizeof(cls) != want:
+            raise ImportError(f"{cls.__name__}: ctypes size {ct.sizeof(cls)} != library size {want}")
+
+
+def status_str(status: int) -> str:
+    return lib().pc_status_str(status).decode()
+
+
+def _check(status: int, what: str, allow_warn: bool = True) -> int:
+    if status < 0 or (status > 0 and not allow_warn):
+        raise PCError(status, what)
+    return status
+
+
+# ------------------------------------------------------------------------------------------------
+# Host-only helpers (no GPU)
+# ------------------------------------------------------------------------------------------------
+def pc_comb_unrank(d: int, l: int, t: int, skip: int = -1) -> list:
+    out = (ct.c_int32 * max(1, l))()
+    _check(lib().pc_comb_unrank(d, l, t, skip, out), "pc_comb_unrank")
+    return [int(out[k]) for k in range(l)]
+
+
+def pc_threshold(alpha: float, m: float, level: int) -> float:
+    return lib().pc_threshold(alpha, m, level)
+
+
+def default_options(**kw) -> pc_options:
+    o = pc_options()
+    _check(lib().pc_default_options(ct.byref(o)), "pc_default_options")
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def pc_workspace_bytes(n: int, m: int, opt: pc_options | None = None) -> int:
+    return int(lib().pc_workspace_bytes(n, m, ct.byref(opt) if opt is not None else None))
+
+
+# ------------------------------------------------------------------------------------------------
+# Device calls (torch tensors on the current HIP device)
+# ------------------------------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def words_per_row(n: int) -> int:
+    return (n + 63) // 64
+
+
+class Context:
+    """A pc_ctx bound to a torch stream (default: the current stream)."""
+
+    def __init__(self, stream=None, **options):
+        torch = _torch()
+        self.opt = default_options(**options)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ct.c_void_p()
+        _check(lib().pc_create(ct.byref(h), ct.c_void_p(stream.cuda_stream), ct.byref(self.opt)),
+               "pc_create", allow_warn=False)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers ---------------------------------------------------------------------------
+    def workspace(self, n: int, m: int):
+        torch = _torch()
+        nbytes = pc_workspace_bytes(n, m, self.opt)
+        return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+    @staticmethod
+    def adjacency(n: int):
+        torch = _torch()
+        return torch.zeros((n, words_per_row(n)), dtype=torch.int64, device="cuda")
+
+    @staticmethod
+    def sepsets(cap: int):
+        torch = _torch()
+        recs = torch.empty((max(1, cap), 3 + PC_MAX_LEVEL), dtype=torch.int32, device="cuda")
+        count = torch.zeros(1, dtype=torch.int64, device="cuda")
+        return recs, count
+
+    # -- entry points --------------------------------------------------------------------------
+    def pc_corr(self, X, alpha: float, ws, C_out=None, adj_out=None) -> int:
+        m, n = X.shape
+        assert X.is_cuda and X.dtype == _torch().float64 and X.is_contiguous()
+        return _check(lib().pc_corr(self.h, ct.c_void_p(X.data_ptr()), m, n, alpha,
+                                    ct.c_void_p(ws.data_ptr()), ws.numel(),
+                                    ct.c_void_p(C_out.data_ptr()) if C_out is not None else None,
+                                    ct.c_void_p(adj_out.data_ptr()) if adj_out is not None else None),
+                      "pc_corr")
+
+    def pc_level(self, level: int, n: int, m: int, alpha: float, adj, recs, count, ws,
+                 stats: pc_run_stats | None = None) -> int:
+        sep = pc_sepset(recs.data_ptr(), recs.shape[0], count.data_ptr())
+        return _check(lib().pc_level(self.h, level, n, m, alpha, ct.c_void_p(adj.data_ptr()),
+                                     ct.byref(sep), ct.byref(stats) if stats is not None else None,
+                                     ct.c_void_p(ws.data_ptr()), ws.numel()), "pc_level")
+
+    def pc_skeleton(self, X, alpha: float, adj, recs, count, ws, max_level: int = -1,
+                    stats: pc_run_stats | None = None) -> int:
+        m, n = X.shape
+        assert X.is_cuda and X.dtype == _torch().float64 and X.is_contiguous()
+        sep = pc_sepset(recs.data_ptr(), recs.shape[0], count.data_ptr())
+        return _check(lib().pc_skeleton(self.h, ct.c_void_p(X.data_ptr()), m, n, alpha, max_level,
+                                        ct.c_void_p(adj.data_ptr()), ct.byref(sep),
+                                        ct.byref(stats) if stats is not None else None,
+                                        ct.c_void_p(ws.data_ptr()), ws.numel()), "pc_skeleton")
+
+    def pc_sync_status(self, ws=None) -> int:
+        return _check(lib().pc_sync_status(self.h, ct.c_void_p(ws.data_ptr()) if ws is not None else None,
+                                           ws.numel() if ws is not None else 0), "pc_sync_status")
+
+
+# ------------------------------------------------------------------------------------------------
+# Result decoding (host)
+# ------------------------------------------------------------------------------------------------
+def bits_to_dense(adj_words: np.ndarray, n: int) -> np.ndarray:
+    """n x W little-endian uint64 bit matrix -> n x n uint8 adjacency."""
+    w = np.ascontiguousarray(adj_words).view(np.uint64).reshape(n, -1)
+    b = np.unpackbits(w.view(np.uint8), axis=1, bitorder="little")
+    return b[:, :n].astype(np.uint8)
+
+
+def dense_to_bits(G: np.ndarray) -> np.ndarray:
+    """n x n 0/1 adjacency -> n x W uint64 bit matrix (as int64 for torch)."""
+    n = G.shape[0]
+    W = words_per_row(n)
+    padded = np.zeros((n, W * 64), np.uint8)
+    padded[:, :n] = G != 0
+    packed = np.packbits(padded, axis=1, bitorder="little")
+    return packed.view(np.uint64).reshape(n, W).view(np.int64)
+
+
+def decode_sepsets(recs: np.ndarray, count: int) -> dict:
+    """(i, j) -> (level, S tuple) from the record table (first `count` rows)."""
+    out = {}
+    for r in recs[:count]:
+        i, j, l = int(r[0]), int(r[1]), int(r[2])
+        out[(i, j)] = (l, tuple(int(x) for x in r[3:3 + l]))
+    return out

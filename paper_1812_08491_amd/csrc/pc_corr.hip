@@ -1,0 +1,312 @@
+// Correlation matrix C = Z^T Z on MFMA, with the level-0 CI test fused into the epilogue.
+//
+// Level 0 (Sec. 3.2, Algorithm 3) tests every pair i < j with S = {} and, as Sec. 4.3 notes,
+// reduces to comparing the Fisher z of C[V_i,V_j] with tau_0 (Eq. 5-6). Here that test runs on the
+// 64 x 64 output tile while it is still in registers, and the tile's adjacency bits are packed
+// into the bit matrix, so no separate level-0 kernel or n x n adjacency pass exists.
+//
+// Only upper-triangle tiles are computed (C is symmetric); each writes its tile and the mirror.
+// Precision paths:
+//   FP64   : v_mfma_f64_16x16x4f64, exact FP64 decision |atanh(c)| <= tau_0.
+//   FP32   : v_mfma_f32_16x16x4f32 on the FP32 copy of Z.
+//   BF16x3 : v_mfma_f32_16x16x32_bf16 on hi*hi + hi*lo + lo*hi, FP32 accumulation.
+// On the two low-precision paths a pair whose |c| lies within eps_c of tanh(tau_0) is re-done in
+// FP64 as a dot product of the FP64 standardized columns, so every level-0 decision equals the
+// FP64 one.
+#include "pc_dev.h"
+
+namespace pcg {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Fisher z of Eq. 5; +inf for |r| >= 1.
+__device__ inline double fisher_z(double r) {
+    if (!(fabs(r) < 1.0)) return INFINITY;
+    return fabs(0.5 * log((1.0 + r) / (1.0 - r)));
+}
+
+template <int PREC> struct Tr;
+template <> struct Tr<PC_PREC_FP32> {
+    using T = float;
+    using acc_t = floatx4;
+    static constexpr int BK = 16;
+};
+template <> struct Tr<PC_PREC_FP64> {
+    using T = double;
+    using acc_t = doublex4;
+    static constexpr int BK = 16;
+};
+template <> struct Tr<PC_PREC_BF16X3> {
+    using T = float;
+    using acc_t = floatx4;
+    static constexpr int BK = 32;
+};
+
+constexpr int kT = 64;  // output tile edge
+
+template <int PREC>
+struct Smem;
+template <> struct Smem<PC_PREC_FP32> {
+    float A[16][kT + 4];
+    float B[16][kT + 4];
+};
+template <> struct Smem<PC_PREC_FP64> {
+    double A[16][kT + 2];
+    double B[16][kT + 2];
+};
+template <> struct Smem<PC_PREC_BF16X3> {
+    uint16_t Ahi[kT][40], Alo[kT][40], Bhi[kT][40], Blo[kT][40];
+};
+
+template <int PREC>
+__device__ inline void load_tiles(Smem<PREC> &sm, const CorrArgs &a, int64_t a0, int64_t b0,
+                                  int64_t k0, int tid) {
+    const int row = tid >> 2;
+    if constexpr (PREC == PC_PREC_FP32) {
+        const int kq = (tid & 3) * 4;
+        const float *z = static_cast<const float *>(a.za);
+        float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
+        if (a0 + row < a.n) va = *reinterpret_cast<const float4 *>(z + (a0 + row) * a.mp + k0 + kq);
+        if (b0 + row < a.n) vb = *reinterpret_cast<const float4 *>(z + (b0 + row) * a.mp + k0 + kq);
+        sm.A[kq + 0][row] = va.x; sm.A[kq + 1][row] = va.y;
+        sm.A[kq + 2][row] = va.z; sm.A[kq + 3][row] = va.w;
+        sm.B[kq + 0][row] = vb.x; sm.B[kq + 1][row] = vb.y;
+        sm.B[kq + 2][row] = vb.z; sm.B[kq + 3][row] = vb.w;
+    } else if constexpr (PREC == PC_PREC_FP64) {
+        const int kq = (tid & 3) * 4;
+        const double *z = a.zt64;
+        double2 va0 = make_double2(0.0, 0.0), va1 = va0, vb0 = va0, vb1 = va0;
+        if (a0 + row < a.n) {
+            const double2 *p = reinterpret_cast<const double2 *>(z + (a0 + row) * a.mp + k0 + kq);
+            va0 = p[0];
+            va1 = p[1];
+        }
+        if (b0 + row < a.n) {
+            const double2 *p = reinterpret_cast<const double2 *>(z + (b0 + row) * a.mp + k0 + kq);
+            vb0 = p[0];
+            vb1 = p[1];
+        }
+        sm.A[kq + 0][row] = va0.x; sm.A[kq + 1][row] = va0.y;
+        sm.A[kq + 2][row] = va1.x; sm.A[kq + 3][row] = va1.y;
+        sm.B[kq + 0][row] = vb0.x; sm.B[kq + 1][row] = vb0.y;
+        sm.B[kq + 2][row] = vb1.x; sm.B[kq + 3][row] = vb1.y;
+    } else {
+        const int k8 = (tid & 3) * 8;
+        const uint16_t *zh = static_cast<const uint16_t *>(a.za);
+        const uint16_t *zl = static_cast<const uint16_t *>(a.zb);
+        uint4 ah = make_uint4(0, 0, 0, 0), al = ah, bh = ah, bl = ah;
+        if (a0 + row < a.n) {
+            ah = *reinterpret_cast<const uint4 *>(zh + (a0 + row) * a.mp + k0 + k8);
+            al = *reinterpret_cast<const uint4 *>(zl + (a0 + row) * a.mp + k0 + k8);
+        }
+        if (b0 + row < a.n) {
+            bh = *reinterpret_cast<const uint4 *>(zh + (b0 + row) * a.mp + k0 + k8);
+            bl = *reinterpret_cast<const uint4 *>(zl + (b0 + row) * a.mp + k0 + k8);
+        }
+        *reinterpret_cast<uint4 *>(&sm.Ahi[row][k8]) = ah;
+        *reinterpret_cast<uint4 *>(&sm.Alo[row][k8]) = al;
+        *reinterpret_cast<uint4 *>(&sm.Bhi[row][k8]) = bh;
+        *reinterpret_cast<uint4 *>(&sm.Blo[row][k8]) = bl;
+    }
+}
+
+template <int PREC>
+__device__ inline void mma_step(const Smem<PREC> &sm, typename Tr<PREC>::acc_t (&acc)[2][2],
+                                int lane, int wr, int wc) {
+    const int li = lane & 15, lk = lane >> 4;
+    if constexpr (PREC == PC_PREC_FP32) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            float af[2], bf[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                af[x] = sm.A[kk * 4 + lk][wr * 32 + x * 16 + li];
+                bf[x] = sm.B[kk * 4 + lk][wc * 32 + x * 16 + li];
+            }
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < 2; ++nj)
+                    acc[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mi], bf[nj], acc[mi][nj], 0, 0, 0);
+        }
+    } else if constexpr (PREC == PC_PREC_FP64) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            double af[2], bf[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                af[x] = sm.A[kk * 4 + lk][wr * 32 + x * 16 + li];
+                bf[x] = sm.B[kk * 4 + lk][wc * 32 + x * 16 + li];
+            }
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < 2; ++nj)
+                    acc[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[nj], acc[mi][nj], 0, 0, 0);
+        }
+    } else {
+        bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            ah[x] = *reinterpret_cast<const bf16x8 *>(&sm.Ahi[wr * 32 + x * 16 + li][lk * 8]);
+            al[x] = *reinterpret_cast<const bf16x8 *>(&sm.Alo[wr * 32 + x * 16 + li][lk * 8]);
+            bh[x] = *reinterpret_cast<const bf16x8 *>(&sm.Bhi[wc * 32 + x * 16 + li][lk * 8]);
+            bl[x] = *reinterpret_cast<const bf16x8 *>(&sm.Blo[wc * 32 + x * 16 + li][lk * 8]);
+        }
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < 2; ++nj) {
+                acc[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[nj], acc[mi][nj], 0, 0, 0);
+                acc[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[nj], acc[mi][nj], 0, 0, 0);
+                acc[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[nj], acc[mi][nj], 0, 0, 0);
+            }
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_corr(CorrArgs a) {
+    using T = typename Tr<PREC>::T;
+    using acc_t = typename Tr<PREC>::acc_t;
+    constexpr int BK = Tr<PREC>::BK;
+    const int tj = blockIdx.x, ti = blockIdx.y;
+    if (ti > tj) return;
+    const int64_t a0 = (int64_t)ti * kT, b0 = (int64_t)tj * kT;
+    const bool diag = ti == tj;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+
+    __shared__ Smem<PREC> sm;
+    __shared__ unsigned long long rowbits[kT], colbits[kT];
+    __shared__ unsigned int blist[kT * kT];
+    __shared__ int bcount;
+    __shared__ int wg_removed, wg_rechecks;
+    if (tid < kT) { rowbits[tid] = 0ull; colbits[tid] = 0ull; }
+    if (tid == 0) { bcount = 0; wg_removed = 0; wg_rechecks = 0; }
+
+    acc_t acc[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[mi][nj][v] = 0;
+
+    for (int64_t k0 = 0; k0 < a.mp; k0 += BK) {
+        load_tiles<PREC>(sm, a, a0, b0, k0, tid);
+        __syncthreads();
+        mma_step<PREC>(sm, acc, lane, wr, wc);
+        __syncthreads();
+    }
+
+    // Epilogue: store C (tile and mirror), level-0 decisions, adjacency bits.
+    T *C = static_cast<T *>(a.C);
+    int removed = 0;
+    const int li = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) {
+            const int bl = wc * 32 + nj * 16 + li;
+            const int64_t b = b0 + bl;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // Accumulator register v of lane (lg, li) holds row lg*4 + v of the 16 x 16 block
+                // for the FP32/BF16 instructions and row lg + 4*v for v_mfma_f64_16x16x4f64.
+                const int al = wr * 32 + mi * 16 + (PREC == PC_PREC_FP64 ? lg + 4 * v : lg * 4 + v);
+                const int64_t ar = a0 + al;
+                if (ar >= a.n || b >= a.n || ar > b) continue;  // a > b: written as the mirror
+                if (ar == b) {
+                    C[ar * a.n + b] = (T)1;
+                    continue;
+                }
+                // Only (a < b) is stored from the accumulator; its mirror gets the same value, so C
+                // is exactly symmetric (inside diagonal tiles (a,b) and (b,a) accumulate the BF16
+                // cross terms in different orders).
+                const T val = (T)acc[mi][nj][v];
+                C[ar * a.n + b] = val;
+                C[b * a.n + ar] = val;
+                bool keep, border = false;
+                if constexpr (PREC == PC_PREC_FP64) {
+                    keep = !(fisher_z((double)val) <= a.tau0);
+                } else {
+                    double x = fabs((double)val);
+                    keep = x > a.t0 + a.eps_c;
+                    border = !keep && x >= a.t0 - a.eps_c;
+                    if (a.force_recheck) border = true;
+                }
+                if (border) {
+                    int k = atomicAdd(&bcount, 1);
+                    blist[k] = ((unsigned)al << 8) | (unsigned)bl;
+                } else if (keep) {
+                    atomicOr(&rowbits[al], 1ull << bl);
+                    atomicOr(&colbits[bl], 1ull << al);
+                } else {
+                    ++removed;
+                }
+            }
+        }
+    if (removed) atomicAdd(&wg_removed, removed);
+    __syncthreads();
+
+    if constexpr (PREC != PC_PREC_FP64) {
+        // FP64 re-check of band pairs: one wave per pair, dot product of the FP64 columns.
+        const int nb = bcount;
+        for (int k = wave; k < nb; k += 4) {
+            const unsigned e = blist[k];
+            const int al = (int)(e >> 8), bl = (int)(e & 255u);
+            const double *za = a.zt64 + (a0 + al) * a.mp;
+            const double *zb = a.zt64 + (b0 + bl) * a.mp;
+            double s = 0.0;
+            for (int64_t r = lane; r < a.m; r += 64) s += za[r] * zb[r];
+            s = wave_sum(s);
+            if (lane == 0) {
+                const bool keep = !(fisher_z(s) <= a.tau0);
+                if (keep) {
+                    atomicOr(&rowbits[al], 1ull << bl);
+                    atomicOr(&colbits[bl], 1ull << al);
+                } else {
+                    atomicAdd(&wg_removed, 1);
+                }
+                atomicAdd(&wg_rechecks, 1);
+            }
+        }
+        __syncthreads();
+    }
+
+    const int64_t W = a.W;
+    if (tid < kT) {
+        const int64_t r = a0 + tid;
+        if (r < a.n) a.adj[r * W + tj] = rowbits[tid] | (diag ? colbits[tid] : 0ull);
+    } else if (tid < 2 * kT && !diag) {
+        const int64_t r = b0 + (tid - kT);
+        if (r < a.n) a.adj[r * W + ti] = colbits[tid - kT];
+    }
+    if (tid == 0) {
+        if (wg_removed) add_ll(&a.st->removed[0], (long long)wg_removed);
+        if (wg_rechecks) add_ll(&a.st->rechecks[0], (long long)wg_rechecks);
+        if (ti == 0 && tj == 0) a.st->tests[0] = (long long)(a.n * (a.n - 1) / 2);
+    }
+}
+
+hipError_t launch_corr(hipStream_t s, const CorrArgs &a, int prec) {
+    const unsigned T = (unsigned)((a.n + kT - 1) / kT);
+    dim3 grid(T, T);
+    if (prec == PC_PREC_FP64)
+        hipLaunchKernelGGL(k_corr<PC_PREC_FP64>, grid, dim3(256), 0, s, a);
+    else if (prec == PC_PREC_FP32)
+        hipLaunchKernelGGL(k_corr<PC_PREC_FP32>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_corr<PC_PREC_BF16X3>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace pcg

@@ -1,0 +1,120 @@
+"""CPU checks of libpc.so: it loads, exports what include/pc.h declares, its ABI structs match the
+binding, and its host-only helpers match the paper's printed examples and scipy. No GPU needed."""
+import itertools
+import math
+import os
+import re
+
+import pytest
+from scipy import stats
+
+import paper_1812_08491_amd as pc
+from paper_1812_08491_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "pc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pc.lib()
+    declared = _declared_functions()
+    assert "pc_skeleton" in declared and "pc_level" in declared and "pc_corr" in declared
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(_lib.EXPORTED)
+
+
+def test_abi_struct_sizes():
+    _lib.check_abi()
+    assert pc.lib().pc_abi_size(1) == 4 * (3 + pc.PC_MAX_LEVEL)
+
+
+def test_status_strings():
+    for s in range(-8, 3):
+        assert pc.status_str(s) and "unknown" not in pc.status_str(s)
+
+
+def _golden_lines(name):
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            yield line
+
+
+def test_comb_unrank_matches_paper_examples():
+    """Sec. 4.2, Fig. 3 and Fig. 4 of the paper (tests/golden/parcomb_examples.txt)."""
+    seen = 0
+    for line in _golden_lines("parcomb_examples.txt"):
+        lhs, rhs = line.split("->")
+        kind, *args = lhs.split()
+        kv = dict(a.split("=") for a in args if "=" in a)
+        l = int(kv["l"])
+        seen += 1
+        if kind == "comb":
+            got = pc.pc_comb_unrank(int(kv["n"]), l, int(kv["t"]))
+            assert [g + 1 for g in got] == [int(x) for x in rhs.split()]     # paper is 1-based
+        else:
+            row = [int(x) for x in kv["row"].split(",")]
+            skip = int(kv["p"]) if kind == "edge" else -1
+            pool = len(row) - (1 if kind == "edge" else 0)
+            if "count" in args:
+                assert math.comb(pool, l) == int(rhs)
+                continue
+            P = pc.pc_comb_unrank(len(row), l, int(kv["t"]), skip)
+            toks = rhs.split()
+            if kind == "edge":
+                assert P == [int(toks[1]), int(toks[2])]
+                assert [row[p] for p in P] == [int(toks[4]), int(toks[5])]
+            else:
+                S = [row[p] for p in P]
+                assert S == [int(toks[1]), int(toks[2])]
+                if "J" in toks:
+                    J = [int(x) for x in toks[toks.index("J") + 1:]]
+                    assert [v for v in row if v not in S] == J
+    assert seen == 8
+
+
+@pytest.mark.parametrize("d,l", [(1, 1), (5, 1), (6, 2), (9, 3), (11, 4), (13, 6), (14, 13)])
+def test_comb_unrank_is_lexicographic(d, l):
+    for t, ref in enumerate(itertools.combinations(range(d), l)):
+        assert pc.pc_comb_unrank(d, l, t) == list(ref)
+    with pytest.raises(pc.PCError):
+        pc.pc_comb_unrank(d, l, math.comb(d, l))
+
+
+@pytest.mark.parametrize("d,l,skip", [(6, 2, 4), (8, 3, 0), (8, 3, 7), (10, 1, 5)])
+def test_comb_unrank_edge_form(d, l, skip):
+    cand = [p for p in range(d) if p != skip]
+    for t, ref in enumerate(itertools.combinations(cand, l)):
+        assert pc.pc_comb_unrank(d, l, t, skip) == list(ref)
+
+
+def test_threshold_matches_scipy():
+    for alpha in (1e-6, 0.001, 0.01, 0.05, 0.2, 0.5, 0.9):
+        z = stats.norm.isf(alpha / 2)          # upper tail without forming 1 - alpha/2
+        for m, l in ((10, 0), (500, 0), (1000, 3), (1e20, 2)):
+            got = pc.pc_threshold(alpha, m, l)
+            assert got == pytest.approx(z / math.sqrt(m - l - 3), rel=2e-15)
+    assert math.isnan(pc.pc_threshold(0.05, 5, 2))
+
+
+def test_workspace_bytes_grow_with_problem():
+    a = pc.pc_workspace_bytes(100, 100)
+    b = pc.pc_workspace_bytes(1000, 500)
+    c = pc.pc_workspace_bytes(1000, 500, pc.default_options(precision="bf16x3"))
+    assert 0 < a < b and c > 0
+    assert pc.pc_workspace_bytes(0, 10) == 0
+
+
+def test_bit_packing_round_trip():
+    import numpy as np
+    rng = np.random.default_rng(0)
+    for n in (1, 63, 64, 65, 130):
+        G = (rng.random((n, n)) < 0.3).astype(np.uint8)
+        assert np.array_equal(pc.bits_to_dense(pc.dense_to_bits(G), n), G)
