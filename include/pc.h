@@ -66,7 +66,9 @@ typedef struct {
                                   (default 65536; 0 forces the global-memory gather path) */
     int32_t ranks_per_lane;    /* conditioning sets per lane in one work item (0 = automatic) */
     int32_t grid;              /* work-groups of the persistent level kernel (0 = automatic) */
-    int32_t timing;            /* 1: time phases with HIP events into pc_run_stats */
+    int32_t timing;            /* bit mask of phases timed with HIP events into pc_run_stats:
+                                  1 = correlation kernel (incl. level 0), 2 = level kernels,
+                                  4 = compaction, 8 = FP64 re-check, 16 = standardization */
     int64_t recheck_cap;       /* capacity of the FP64 re-check queue in tests per level
                                   (0 = 1<<20); a level that needs more returns PC_ERR_WORKSPACE */
 } pc_options;
@@ -96,12 +98,18 @@ typedef struct {
     int64_t items[PC_MAX_LEVEL + 1];     /* work items planned for the level */
     int64_t audit_violations[PC_MAX_LEVEL + 1]; /* force_recheck_all: FP32 decisions made outside
                                                    the error band that FP64 reversed (must be 0) */
+    int64_t probe_tests[PC_MAX_LEVEL + 1];   /* ordered runs: tests of the probe pass (included in
+                                                tests) */
+    int64_t probe_removed[PC_MAX_LEVEL + 1]; /* ordered runs: edges the probe pass removed (included
+                                                in removed) */
     int32_t max_degree[PC_MAX_LEVEL + 1];/* max degree of G' at the start of the level (0 at level 0) */
     int32_t levels_run;                  /* levels executed, level 0 included */
     int32_t pad;
-    float corr_ms;                       /* standardize + correlation + level 0 (timing = 1) */
-    float compact_ms[PC_MAX_LEVEL + 1];  /* compaction + planning of level l (timing = 1) */
-    float level_ms[PC_MAX_LEVEL + 1];    /* level kernel of level l (timing = 1) */
+    float prep_ms;                       /* column statistics + standardization (timing & 16) */
+    float corr_ms;                       /* correlation GEMM with the level-0 test (timing & 1) */
+    float compact_ms[PC_MAX_LEVEL + 1];  /* compaction + planning of level l (timing & 4) */
+    float level_ms[PC_MAX_LEVEL + 1];    /* level kernel of level l (timing & 2) */
+    float recheck_ms[PC_MAX_LEVEL + 1];  /* FP64 re-check kernel of level l (timing & 8) */
     double wall_ms;                      /* host wall time of the call */
 } pc_run_stats;
 
@@ -158,6 +166,111 @@ pc_status pc_skeleton(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double
                       int max_level, uint64_t *adj_out, const pc_sepset *sep, pc_run_stats *st,
                       void *ws, size_t ws_bytes);
 
+/* One dataset of a batch (Sec. 5 of the paper runs one dataset at a time; a batch runs many
+ * independent skeletons together, their work items tagged by dataset).
+ *   X        device m x n FP64 row-major data.
+ *   alpha    significance level in (0, 1); max_level as for pc_skeleton.
+ *   adj_out  device bit matrix (n x ceil(n/64) uint64): the skeleton.
+ *   sep      SepSet table of this dataset (count is zeroed by the run). */
+typedef struct {
+    const double *X;
+    int64_t m, n;
+    double alpha;
+    int32_t max_level;
+    int32_t pad;
+    uint64_t *adj_out;
+    pc_sepset sep;
+} pc_problem;
+
+/* Bytes of device workspace for a batch (the same workspace serves pc_batch_skeleton and
+ * pc_batch_capture). Returns 0 for an invalid batch. */
+size_t pc_batch_workspace_bytes(const pc_problem *probs, int count, const pc_options *opt);
+
+/* Runs the skeletons of `count` independent datasets together: every kernel launch serves all of
+ * them (correlation tiles, rows and work items of all datasets share one index space), and the
+ * level loop runs on the device until no dataset has work left (or every cap is reached).
+ *   probs    host array of count problem descriptors (their buffers are device memory).
+ *   st       optional host array of count statistics; status optional host array of count
+ *            per-dataset results (PC_OK, a warning, or an error as for pc_skeleton).
+ * Synchronises the stream. Returns PC_OK if every dataset succeeded or only warned, else the first
+ * error. */
+pc_status pc_batch_skeleton(pc_ctx *ctx, const pc_problem *probs, int count, pc_run_stats *st,
+                            pc_status *status, void *ws, size_t ws_bytes);
+
+/* A captured batch: the whole batched skeleton (standardize, correlation, and every level up to the
+ * largest cap of the batch, each kernel exiting at once when no work is left) recorded once as a
+ * hipGraph and replayed with pc_graph_launch. The graph keeps the pointers it was captured with:
+ * new data is run by writing it into the same X buffers. The context's stream must not be the
+ * null stream. */
+typedef struct pc_graph pc_graph;
+pc_status pc_batch_capture(pc_ctx *ctx, const pc_problem *probs, int count, void *ws,
+                           size_t ws_bytes, pc_graph **out);
+/* Enqueues one replay on the context's stream (asynchronous). */
+pc_status pc_graph_launch(pc_graph *g);
+/* Waits for the last replay and reports per-dataset statistics and results (as pc_batch_skeleton). */
+pc_status pc_graph_results(pc_graph *g, pc_run_stats *st, pc_status *status);
+void pc_graph_destroy(pc_graph *g);
+
+/* ---------------------------------------------------------------------------------------------
+ * Learned conditioning-set ordering.
+ *
+ * PC-stable's skeleton does not depend on the order in which conditioning sets are tried (Sec. 2.4),
+ * so a level may first test, for every edge (i,j), the subsets of the candidates k in
+ * adj(i,G')\{j} that a model ranks highest, then run the plain enumeration on the same G'. The
+ * model is an MLP 8 -> 64 -> 64 -> 1 (ReLU) on the candidate features
+ *   |C_ij|, |C_ik|, |C_jk|, |rho_ij.k|, d_i/64, d_j/64, d_k/64, level/8
+ * (rho_ij.k the level-1 partial correlation, degrees in G'). Parameters are PC_MLP_PARAMS FP32
+ * values laid out as W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3 (weights row = output).
+ * ------------------------------------------------------------------------------------------- */
+#define PC_MLP_IN 8
+#define PC_MLP_HID 64
+#define PC_MLP_PARAMS 4801
+
+typedef struct {
+    const float *params;  /* device, PC_MLP_PARAMS values */
+    int32_t min_level;    /* first level that runs the probe pass (1..8; default 2) */
+    int32_t top;          /* candidates kept per edge direction (1..8); the probe tests their
+                             C(top, level) subsets */
+    int64_t max_rows;     /* feature rows per level (sum over rows of d_i (d_i - 1)); a level that
+                             needs more runs without the probe */
+} pc_order;
+
+/* Workspace of pc_skeleton_ordered (pc_workspace_bytes plus the feature and score buffers). */
+size_t pc_ordered_workspace_bytes(int64_t n, int64_t m, const pc_options *opt, const pc_order *order);
+
+/* pc_skeleton with the probe pass before every level l in [order->min_level, 8]. The adjacency
+ * after every level and the skeleton are those of pc_skeleton; SepSets may differ (any separating
+ * S is valid). Statistics report the probe's tests and removals separately. */
+pc_status pc_skeleton_ordered(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alpha,
+                              int max_level, const pc_order *order, uint64_t *adj_out,
+                              const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes);
+
+/* Candidate features of level `level` for the snapshot adj (device bit matrix, not modified), for
+ * training data: rows ordered by i, then j = N_i[p], then k in N_i\{j}, as the ordered run uses them.
+ *   feats    device rows x 8 FP32; meta device rows x 3 int32 (i, j, k); cap = rows they hold.
+ *   rows_out host: number of rows (returned even when it exceeds cap, with PC_ERR_WORKSPACE).
+ *   ws       workspace of a preceding pc_corr on the same data. Synchronises the stream. */
+pc_status pc_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, const uint64_t *adj,
+                      float *feats, int32_t *meta, int64_t cap, int64_t *rows_out, void *ws,
+                      size_t ws_bytes);
+
+/* MLP kernels (stream ordered, asynchronous), exported for training and gradient checks.
+ *   forward : scores[r] = MLP(X[r]) for rows x 8 inputs; act (optional, rows x 128) keeps the
+ *             hidden activations for backward.
+ *   backward: grads = d(sum_r dscore[r] * score[r]) / d(params); partial is device scratch of
+ *             ceil(rows/64) * PC_MLP_PARAMS floats (the per-tile sums, added in a fixed order).
+ *   bce     : loss = mean_r [w y softplus(-s) + (1-y) softplus(s)] (device double) and
+ *             dscore = dloss/ds.
+ *   adam    : one Adam step (step counts from 1) on params with moment buffers m1, m2. */
+pc_status pc_mlp_forward(pc_ctx *ctx, const float *params, const float *X, int64_t rows, float *scores,
+                         float *act);
+pc_status pc_mlp_backward(pc_ctx *ctx, const float *params, const float *X, int64_t rows, const float *act,
+                          const float *dscore, float *grads, float *partial);
+pc_status pc_mlp_bce(pc_ctx *ctx, const float *scores, const float *labels, int64_t rows, float pos_weight,
+                     float *dscore, double *loss);
+pc_status pc_mlp_adam(pc_ctx *ctx, float *params, const float *grads, float *m1, float *m2, int step,
+                      float lr, float beta1, float beta2, float eps);
+
 /* Waits for the context's stream and reports device-detected input errors of pc_corr. */
 pc_status pc_sync_status(pc_ctx *ctx, void *ws, size_t ws_bytes);
 
@@ -173,7 +286,8 @@ pc_status pc_comb_unrank(int32_t d, int32_t l, uint64_t t, int32_t skip, int32_t
 double pc_threshold(double alpha, double m, int level);
 
 /* Host-only helper: sizeof of the ABI structs, so bindings can check their layouts.
- * which: 0 pc_options, 1 pc_sep_rec, 2 pc_sepset, 3 pc_run_stats; other values return 0. */
+ * which: 0 pc_options, 1 pc_sep_rec, 2 pc_sepset, 3 pc_run_stats, 4 pc_problem, 5 pc_order;
+ * other values return 0. */
 size_t pc_abi_size(int which);
 
 /* Text of a status code (static storage). */

@@ -5,11 +5,11 @@ convenience wrapper, :func:`skeleton`, that allocates the buffers with torch and
 """
 from __future__ import annotations
 
-from ._lib import (PC_MAX_LEVEL, PCError, Context, bits_to_dense, decode_sepsets, default_options,
-                   dense_to_bits, lib, pc_comb_unrank, pc_run_stats, pc_threshold,
+from ._lib import (PC_MAX_LEVEL, PC_MLP_PARAMS, PCError, Context, bits_to_dense, decode_sepsets,
+                   default_options, dense_to_bits, lib, pc_comb_unrank, pc_run_stats, pc_threshold,
                    pc_workspace_bytes, status_str)
 
-__all__ = ["PC_MAX_LEVEL", "PCError", "Context", "bits_to_dense", "decode_sepsets",
+__all__ = ["PC_MAX_LEVEL", "PC_MLP_PARAMS", "PCError", "Context", "bits_to_dense", "decode_sepsets",
            "default_options", "dense_to_bits", "lib", "pc_comb_unrank", "pc_run_stats",
            "pc_threshold", "pc_workspace_bytes", "status_str", "skeleton"]
 

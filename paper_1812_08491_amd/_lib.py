@@ -50,15 +50,33 @@ class pc_sepset(ct.Structure):
     _fields_ = [("recs", ct.c_void_p), ("cap", ct.c_int64), ("count", ct.c_void_p)]
 
 
+PC_MLP_IN = 8
+PC_MLP_HID = 64
+PC_MLP_PARAMS = 4801
+
+
+class pc_order(ct.Structure):
+    _fields_ = [("params", ct.c_void_p), ("min_level", ct.c_int32), ("top", ct.c_int32),
+                ("max_rows", ct.c_int64)]
+
+
+class pc_problem(ct.Structure):
+    _fields_ = [("X", ct.c_void_p), ("m", ct.c_int64), ("n", ct.c_int64), ("alpha", ct.c_double),
+                ("max_level", ct.c_int32), ("pad", ct.c_int32), ("adj_out", ct.c_void_p),
+                ("sep", pc_sepset)]
+
+
 _NL = PC_MAX_LEVEL + 1
 
 
 class pc_run_stats(ct.Structure):
     _fields_ = [("tests", ct.c_int64 * _NL), ("removed", ct.c_int64 * _NL),
                 ("rechecks", ct.c_int64 * _NL), ("items", ct.c_int64 * _NL),
-                ("audit_violations", ct.c_int64 * _NL), ("max_degree", ct.c_int32 * _NL),
-                ("levels_run", ct.c_int32), ("pad", ct.c_int32), ("corr_ms", ct.c_float),
-                ("compact_ms", ct.c_float * _NL), ("level_ms", ct.c_float * _NL),
+                ("audit_violations", ct.c_int64 * _NL), ("probe_tests", ct.c_int64 * _NL),
+                ("probe_removed", ct.c_int64 * _NL), ("max_degree", ct.c_int32 * _NL),
+                ("levels_run", ct.c_int32), ("pad", ct.c_int32), ("prep_ms", ct.c_float),
+                ("corr_ms", ct.c_float), ("compact_ms", ct.c_float * _NL),
+                ("level_ms", ct.c_float * _NL), ("recheck_ms", ct.c_float * _NL),
                 ("wall_ms", ct.c_double)]
 
     def as_dict(self) -> dict:
@@ -70,10 +88,14 @@ class pc_run_stats(ct.Structure):
             "rechecks": list(self.rechecks[:k]),
             "items": list(self.items[:k]),
             "audit_violations": list(self.audit_violations[:k]),
+            "probe_tests": list(self.probe_tests[:k]),
+            "probe_removed": list(self.probe_removed[:k]),
             "max_degree": list(self.max_degree[:k]),
+            "prep_ms": self.prep_ms,
             "corr_ms": self.corr_ms,
             "compact_ms": list(self.compact_ms[:k]),
             "level_ms": list(self.level_ms[:k]),
+            "recheck_ms": list(self.recheck_ms[:k]),
             "wall_ms": self.wall_ms,
         }
 
@@ -118,25 +140,67 @@ def lib() -> ct.CDLL:
         L.pc_comb_unrank.restype = ct.c_int
         L.pc_threshold.argtypes = [ct.c_double, ct.c_double, ct.c_int]
         L.pc_threshold.restype = ct.c_double
+        L.pc_batch_workspace_bytes.argtypes = [ct.POINTER(pc_problem), ct.c_int, ct.POINTER(pc_options)]
+        L.pc_batch_workspace_bytes.restype = ct.c_size_t
+        L.pc_batch_skeleton.argtypes = [vp, ct.POINTER(pc_problem), ct.c_int, ct.POINTER(pc_run_stats),
+                                        ct.POINTER(ct.c_int), vp, ct.c_size_t]
+        L.pc_batch_skeleton.restype = ct.c_int
+        L.pc_batch_capture.argtypes = [vp, ct.POINTER(pc_problem), ct.c_int, vp, ct.c_size_t,
+                                       ct.POINTER(vp)]
+        L.pc_batch_capture.restype = ct.c_int
+        L.pc_graph_launch.argtypes = [vp]
+        L.pc_graph_launch.restype = ct.c_int
+        L.pc_graph_results.argtypes = [vp, ct.POINTER(pc_run_stats), ct.POINTER(ct.c_int)]
+        L.pc_graph_results.restype = ct.c_int
+        L.pc_graph_destroy.argtypes = [vp]
+        L.pc_graph_destroy.restype = None
+        fp, dp_ = ct.c_void_p, ct.c_void_p
+        L.pc_ordered_workspace_bytes.argtypes = [i64, i64, ct.POINTER(pc_options), ct.POINTER(pc_order)]
+        L.pc_ordered_workspace_bytes.restype = ct.c_size_t
+        L.pc_skeleton_ordered.argtypes = [vp, vp, i64, i64, ct.c_double, ct.c_int, ct.POINTER(pc_order), vp,
+                                          ct.POINTER(pc_sepset), ct.POINTER(pc_run_stats), vp, ct.c_size_t]
+        L.pc_skeleton_ordered.restype = ct.c_int
+        L.pc_features.argtypes = [vp, ct.c_int, i64, i64, ct.c_double, vp, fp, vp, i64, ct.POINTER(i64), vp,
+                                  ct.c_size_t]
+        L.pc_features.restype = ct.c_int
+        L.pc_mlp_forward.argtypes = [vp, fp, fp, i64, fp, fp]
+        L.pc_mlp_forward.restype = ct.c_int
+        L.pc_mlp_backward.argtypes = [vp, fp, fp, i64, fp, fp, fp, fp]
+        L.pc_mlp_backward.restype = ct.c_int
+        L.pc_mlp_bce.argtypes = [vp, fp, fp, i64, ct.c_float, fp, dp_]
+        L.pc_mlp_bce.restype = ct.c_int
+        L.pc_mlp_adam.argtypes = [vp, fp, fp, fp, fp, ct.c_int, ct.c_float, ct.c_float, ct.c_float, ct.c_float]
+        L.pc_mlp_adam.restype = ct.c_int
         L.pc_abi_size.argtypes = [ct.c_int]
         L.pc_abi_size.restype = ct.c_size_t
         L.pc_status_str.argtypes = [ct.c_int]
         L.pc_status_str.restype = ct.c_char_p
+        _check_abi(L)
         _lib = L
     return _lib
 
 
 EXPORTED = ["pc_create", "pc_destroy", "pc_default_options", "pc_workspace_bytes", "pc_corr",
             "pc_level", "pc_skeleton", "pc_sync_status", "pc_comb_unrank", "pc_threshold",
-            "pc_abi_size", "pc_status_str"]
+            "pc_abi_size", "pc_status_str", "pc_batch_workspace_bytes", "pc_batch_skeleton",
+            "pc_batch_capture", "pc_graph_launch", "pc_graph_results", "pc_graph_destroy",
+            "pc_ordered_workspace_bytes", "pc_skeleton_ordered", "pc_features", "pc_mlp_forward",
+            "pc_mlp_backward", "pc_mlp_bce", "pc_mlp_adam"]
+
+
+def _check_abi(L: ct.CDLL) -> None:
+    # A library built from a different include/pc.h than these structs would write past the
+    # caller's buffers (statistics arrays are filled with the library's stride), so refuse it.
+    for k, cls in enumerate([pc_options, pc_sep_rec, pc_sepset, pc_run_stats, pc_problem, pc_order]):
+        want = int(L.pc_abi_size(k))
+        if ct.sizeof(cls) != want:
+            raise ImportError(f"{LIB_PATH}: {cls.__name__} is {want} bytes in the library but "
+                              f"{ct.sizeof(cls)} in the binding; rebuild the library")
 
 
 def check_abi() -> None:
     """Raises if a ctypes struct disagrees in size with the library's."""
-    for k, cls in enumerate([pc_options, pc_sep_rec, pc_sepset, pc_run_stats]):
-        want = int(lib().pc_abi_size(k))
-        if ct.sizeof(cls) != want:
-            raise ImportError(f"{cls.__name__}: ctypes size {ct.sizeof(cls)} != library size {want}")
+    _check_abi(lib())
 
 
 def status_str(status: int) -> str:
@@ -260,9 +324,146 @@ class Context:
                                         ct.byref(stats) if stats is not None else None,
                                         ct.c_void_p(ws.data_ptr()), ws.numel()), "pc_skeleton")
 
+    # -- batches ---------------------------------------------------------------------------------
+    @staticmethod
+    def problems(items) -> "ct.Array":
+        """items: iterable of (X, alpha, max_level, adj, recs, count) torch tensors on the device."""
+        items = list(items)
+        arr = (pc_problem * len(items))()
+        for k, (X, alpha, max_level, adj, recs, count) in enumerate(items):
+            assert X.is_cuda and X.dtype == _torch().float64 and X.is_contiguous()
+            m, n = X.shape
+            arr[k] = pc_problem(X.data_ptr(), m, n, alpha, max_level, 0, adj.data_ptr(),
+                                pc_sepset(recs.data_ptr(), recs.shape[0], count.data_ptr()))
+        return arr
+
+    def batch_workspace(self, probs):
+        torch = _torch()
+        nbytes = int(lib().pc_batch_workspace_bytes(probs, len(probs), ct.byref(self.opt)))
+        if nbytes == 0:
+            raise PCError(PC_ERR_INVALID_ARG, "pc_batch_workspace_bytes")
+        return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+    def pc_batch_skeleton(self, probs, ws, stats=None):
+        count = len(probs)
+        status = (ct.c_int * count)()
+        r = lib().pc_batch_skeleton(self.h, probs, count, stats, status, ct.c_void_p(ws.data_ptr()),
+                                    ws.numel())
+        return r, [int(x) for x in status]
+
+    def pc_batch_capture(self, probs, ws) -> "Graph":
+        g = ct.c_void_p()
+        _check(lib().pc_batch_capture(self.h, probs, len(probs), ct.c_void_p(ws.data_ptr()), ws.numel(),
+                                      ct.byref(g)), "pc_batch_capture", allow_warn=False)
+        return Graph(g, len(probs), keep=(probs, ws, self))
+
+    # -- learned ordering ----------------------------------------------------------------------
+    @staticmethod
+    def order(params, min_level: int = 2, top: int = 4, max_rows: int = 1 << 23) -> pc_order:
+        assert params.is_cuda and params.dtype == _torch().float32 and params.numel() == PC_MLP_PARAMS
+        return pc_order(params.data_ptr(), min_level, top, max_rows)
+
+    def ordered_workspace(self, n: int, m: int, order: pc_order):
+        torch = _torch()
+        nbytes = int(lib().pc_ordered_workspace_bytes(n, m, ct.byref(self.opt), ct.byref(order)))
+        if nbytes == 0:
+            raise PCError(PC_ERR_INVALID_ARG, "pc_ordered_workspace_bytes")
+        return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+    def pc_skeleton_ordered(self, X, alpha: float, adj, recs, count, ws, order: pc_order,
+                            max_level: int = -1, stats: pc_run_stats | None = None) -> int:
+        m, n = X.shape
+        assert X.is_cuda and X.dtype == _torch().float64 and X.is_contiguous()
+        sep = pc_sepset(recs.data_ptr(), recs.shape[0], count.data_ptr())
+        return _check(lib().pc_skeleton_ordered(self.h, ct.c_void_p(X.data_ptr()), m, n, alpha, max_level,
+                                                ct.byref(order), ct.c_void_p(adj.data_ptr()), ct.byref(sep),
+                                                ct.byref(stats) if stats is not None else None,
+                                                ct.c_void_p(ws.data_ptr()), ws.numel()), "pc_skeleton_ordered")
+
+    def pc_features(self, level: int, n: int, m: int, alpha: float, adj, feats, meta, ws) -> int:
+        assert feats.is_cuda and feats.dtype == _torch().float32 and feats.shape[1:] == (PC_MLP_IN,)
+        assert meta is None or (meta.is_cuda and meta.dtype == _torch().int32 and meta.numel() >= 3 * feats.shape[0])
+        rows = ct.c_int64()
+        r = lib().pc_features(self.h, level, n, m, alpha, ct.c_void_p(adj.data_ptr()),
+                              ct.c_void_p(feats.data_ptr()),
+                              ct.c_void_p(meta.data_ptr()) if meta is not None else None,
+                              feats.shape[0], ct.byref(rows), ct.c_void_p(ws.data_ptr()), ws.numel())
+        if r == PC_ERR_WORKSPACE:
+            return -int(rows.value)          # negative: the capacity needed
+        _check(r, "pc_features")
+        return int(rows.value)
+
+    @staticmethod
+    def _mlp_shapes(params, X, **bufs):
+        # Device buffers carry no size across the C ABI: check them here, before any launch.
+        torch = _torch()
+        rows = X.shape[0]
+        assert params.is_cuda and params.dtype == torch.float32 and params.numel() == PC_MLP_PARAMS
+        assert X.is_cuda and X.dtype == torch.float32 and X.is_contiguous() and X.shape[1:] == (PC_MLP_IN,)
+        need = {"scores": rows, "dscore": rows, "labels": rows, "act": rows * 2 * PC_MLP_HID,
+                "grads": PC_MLP_PARAMS, "partial": (rows + 63) // 64 * PC_MLP_PARAMS}
+        for name, t in bufs.items():
+            if t is None:
+                continue
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), name
+            assert t.numel() >= need[name], f"{name}: {t.numel()} < {need[name]} floats"
+        return rows
+
+    def pc_mlp_forward(self, params, X, scores, act=None) -> int:
+        self._mlp_shapes(params, X, scores=scores, act=act)
+        return _check(lib().pc_mlp_forward(self.h, params.data_ptr(), X.data_ptr(), X.shape[0], scores.data_ptr(),
+                                           act.data_ptr() if act is not None else None), "pc_mlp_forward")
+
+    def pc_mlp_backward(self, params, X, act, dscore, grads, partial) -> int:
+        self._mlp_shapes(params, X, act=act, dscore=dscore, grads=grads, partial=partial)
+        return _check(lib().pc_mlp_backward(self.h, params.data_ptr(), X.data_ptr(), X.shape[0], act.data_ptr(),
+                                            dscore.data_ptr(), grads.data_ptr(), partial.data_ptr()),
+                      "pc_mlp_backward")
+
+    def pc_mlp_bce(self, scores, labels, pos_weight, dscore, loss) -> int:
+        torch = _torch()
+        rows = scores.shape[0]
+        for name, t in (("labels", labels), ("dscore", dscore)):
+            assert t.is_cuda and t.dtype == torch.float32 and t.numel() >= rows, name
+        assert loss.is_cuda and loss.dtype == torch.float64 and loss.numel() >= 1
+        return _check(lib().pc_mlp_bce(self.h, scores.data_ptr(), labels.data_ptr(), scores.shape[0], pos_weight,
+                                       dscore.data_ptr(), loss.data_ptr()), "pc_mlp_bce")
+
+    def pc_mlp_adam(self, params, grads, m1, m2, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> int:
+        for t in (params, grads, m1, m2):
+            assert t.is_cuda and t.dtype == _torch().float32 and t.numel() == PC_MLP_PARAMS
+        return _check(lib().pc_mlp_adam(self.h, params.data_ptr(), grads.data_ptr(), m1.data_ptr(), m2.data_ptr(),
+                                        step, lr, beta1, beta2, eps), "pc_mlp_adam")
+
     def pc_sync_status(self, ws=None) -> int:
         return _check(lib().pc_sync_status(self.h, ct.c_void_p(ws.data_ptr()) if ws is not None else None,
                                            ws.numel() if ws is not None else 0), "pc_sync_status")
+
+
+class Graph:
+    """A captured batch (pc_graph)."""
+
+    def __init__(self, h, count, keep):
+        self.h, self.count, self._keep = h, count, keep
+
+    def pc_graph_launch(self) -> int:
+        return _check(lib().pc_graph_launch(self.h), "pc_graph_launch")
+
+    def pc_graph_results(self, stats=None):
+        status = (ct.c_int * self.count)()
+        r = lib().pc_graph_results(self.h, stats, status)
+        return r, [int(x) for x in status]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pc_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------------------------------------

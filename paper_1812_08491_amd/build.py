@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpc.so")
-SOURCES = ["pc_prep.hip", "pc_corr.hip", "pc_level.hip", "pc_api.cpp"]
+SOURCES = ["pc_prep.hip", "pc_corr.hip", "pc_level.hip", "pc_mlp.hip", "pc_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I" + os.path.join(ROOT, "include"),

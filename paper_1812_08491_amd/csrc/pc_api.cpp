@@ -1,11 +1,19 @@
-// C ABI of libpc.so: argument checks, workspace planning and the host level loop (Algorithm 2).
+// C ABI of libpc.so: argument checks, workspace planning and the level loop (Algorithm 2).
+//
+// Every call builds a table of problems (one for pc_corr / pc_level / pc_skeleton, many for the
+// batch calls), uploads it into the workspace, and enqueues the kernels of pc_prep.hip,
+// pc_corr.hip and pc_level.hip. The level loop needs no host decision between levels: a planning
+// pass that finds no work sets a device flag and every later kernel exits at once, so a whole
+// skeleton is one stream of launches (and can be captured as one hipGraph).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "pc.h"
 #include "pc_comb.h"
@@ -18,8 +26,25 @@ struct pc_ctx {
     pc_options opt;
     int device;
     int num_cu;
-    DevState *host_state;   // pinned, read back after each level
-    hipEvent_t ev[2 * (PC_MAX_LEVEL + 2) + 2];
+    unsigned long long *binom;      // device binomial table, binom_rows x kBinomCols
+    int64_t binom_rows;
+    void *staging;                  // pinned host staging of problem tables
+    size_t staging_bytes;
+    hipEvent_t staging_done;        // recorded after each upload; waited on before reuse
+    bool staging_pending;
+    // Event pairs of the timed phases: prep, corr, and per level compact / level / re-check.
+    hipEvent_t ev_prep[2], ev_corr[2];
+    hipEvent_t ev_compact[kLevels][2], ev_level[kLevels][2], ev_recheck[kLevels][2];
+};
+
+struct pc_graph {
+    pc_ctx *ctx;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    unsigned char *ws;
+    int count;
+    size_t table_off, st_off;
+    std::vector<Prob> host_probs;
 };
 
 namespace {
@@ -57,7 +82,7 @@ bool valid_options(const pc_options &o) {
 int64_t rq_cap_of(const pc_options &o) { return o.recheck_cap > 0 ? o.recheck_cap : (int64_t)1 << 20; }
 
 // Standard normal CDF from erfc, and its inverse by Halley's method started from the rational
-// approximation of Abramowitz & Stegun 26.2.23 (|error| < 4.5e-4); three Halley steps reach full
+// approximation of Abramowitz & Stegun 26.2.23 (|error| < 4.5e-4); a few Halley steps reach full
 // double precision. Only the lower tail is evaluated (p <= 0.5), so no cancellation occurs.
 double phi_cdf(double x) { return 0.5 * std::erfc(-x / std::sqrt(2.0)); }
 
@@ -91,25 +116,187 @@ double eps_c_of(int prec, int64_t mp) {
     return 0.0;
 }
 
-struct Ws {
-    Layout L;
-    unsigned char *base;
-    DevState *st() const { return reinterpret_cast<DevState *>(base + L.state); }
-    template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
-};
-
-pc_status check_ws(const pc_ctx *ctx, int64_t n, int64_t m, void *ws, size_t ws_bytes, Ws &out) {
-    if (!ws) return PC_ERR_INVALID_ARG;
-    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return PC_ERR_INVALID_ARG;
-    out.L = Layout::make(n, m, ctx->opt.precision, rq_cap_of(ctx->opt));
-    if (ws_bytes < out.L.total) return PC_ERR_WORKSPACE;
-    out.base = static_cast<unsigned char *>(ws);
+pc_status check_shape(int64_t n, int64_t m) {
+    if (n < 2 || m < 4) return PC_ERR_SHAPE;
+    if (n > (int64_t)1 << 16 || m > (int64_t)1 << 26) return PC_ERR_SHAPE;
     return PC_OK;
 }
 
-pc_status check_shape(int64_t n, int64_t m) {
-    if (n < 2 || m < 4) return PC_ERR_SHAPE;
-    if (n > (int64_t)1 << 20 || m > (int64_t)1 << 28) return PC_ERR_SHAPE;
+// ---------------------------------------------------------------------------------------------
+// Workspace layout of a batch
+// ---------------------------------------------------------------------------------------------
+struct Region {
+    size_t mu, inv, zt64, zlo, zhi, c, adj, nbr, deg;
+};
+
+struct Plan {
+    int count = 0;
+    int prec = PC_PREC_FP32;
+    size_t st = 0, table = 0, table_bytes = 0, nitems = 0, item_off = 0, rq = 0, total = 0;
+    int64_t rq_cap = 0;
+    long long total_rows = 0, cs_blocks = 0, st_blocks = 0, tiles = 0;
+    int64_t max_n = 0;
+    size_t foff = 0, skip = 0, feats = 0, scores = 0;   // learned-ordering buffers (if any)
+    long long order_rows = 0;
+    std::vector<Region> reg;
+    std::vector<long long> row_base, cs_base, st_base, tile_base;
+};
+
+// (n, m) of each problem; prec and rq_cap from the options; order_rows > 0 adds the buffers of
+// the learned ordering (feature rows per level).
+Plan make_plan(const int64_t *ns, const int64_t *ms, int count, const pc_options &o, long long order_rows = 0) {
+    Plan L;
+    L.count = count;
+    L.prec = o.precision;
+    L.rq_cap = rq_cap_of(o);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
+    L.st = take(sizeof(DevState));
+    L.table_bytes = sizeof(Prob) * count + 4 * sizeof(long long) * (count + 1);
+    L.table = take(L.table_bytes);
+    L.row_base.assign(count + 1, 0);
+    L.cs_base.assign(count + 1, 0);
+    L.st_base.assign(count + 1, 0);
+    L.tile_base.assign(count + 1, 0);
+    for (int d = 0; d < count; ++d) {
+        const int64_t n = ns[d], mp = pad_m(ms[d]);
+        L.row_base[d + 1] = L.row_base[d] + n;
+        L.cs_base[d + 1] = L.cs_base[d] + cs_blocks(n);
+        L.st_base[d + 1] = L.st_base[d] + st_blocks(n, mp);
+        L.tile_base[d + 1] = L.tile_base[d] + corr_tiles(n);
+        L.max_n = std::max(L.max_n, n);
+    }
+    L.total_rows = L.row_base[count];
+    L.cs_blocks = L.cs_base[count];
+    L.st_blocks = L.st_base[count];
+    L.tiles = L.tile_base[count];
+    L.nitems = take(sizeof(long long) * (size_t)L.total_rows);
+    L.item_off = take(sizeof(long long) * (size_t)(L.total_rows + 1));
+    L.rq = take(sizeof(RqEntry) * (size_t)L.rq_cap);
+    L.reg.resize(count);
+    for (int d = 0; d < count; ++d) {
+        const size_t n = (size_t)ns[d], mp = (size_t)pad_m(ms[d]);
+        Region &r = L.reg[d];
+        r.mu = take(sizeof(double) * n);
+        r.inv = take(sizeof(double) * n);
+        r.zt64 = take(sizeof(double) * n * mp);
+        r.zlo = take(L.prec == PC_PREC_FP32 ? sizeof(float) * n * mp
+                     : L.prec == PC_PREC_BF16X3 ? sizeof(uint16_t) * n * mp : 0);
+        r.zhi = take(L.prec == PC_PREC_BF16X3 ? sizeof(uint16_t) * n * mp : 0);
+        r.c = take((L.prec == PC_PREC_FP64 ? sizeof(double) : sizeof(float)) * n * n);
+        r.adj = take(sizeof(unsigned long long) * n * (size_t)words_per_row((int64_t)n));
+        r.nbr = take(sizeof(int32_t) * n * n);
+        r.deg = take(sizeof(int32_t) * n);
+    }
+    if (order_rows > 0) {
+        L.order_rows = order_rows;
+        L.foff = take(sizeof(long long) * (size_t)(L.total_rows + 1));
+        L.skip = take(sizeof(int));
+        L.feats = take(sizeof(float) * PC_MLP_IN * (size_t)order_rows);
+        L.scores = take(sizeof(float) * (size_t)order_rows);
+    }
+    L.total = off;
+    return L;
+}
+
+// Host image of the problem table for the given workspace base.
+void fill_probs(const pc_ctx *ctx, const Plan &L, unsigned char *ws, const pc_problem *pp,
+                std::vector<Prob> &out) {
+    out.assign(L.count, Prob{});
+    for (int d = 0; d < L.count; ++d) {
+        Prob &P = out[d];
+        const Region &r = L.reg[d];
+        std::memset(&P, 0, sizeof(P));
+        P.n = pp[d].n;
+        P.m = pp[d].m;
+        P.mp = pad_m(P.m);
+        P.W = words_per_row(P.n);
+        P.X = pp[d].X;
+        P.mu = reinterpret_cast<double *>(ws + r.mu);
+        P.inv = reinterpret_cast<double *>(ws + r.inv);
+        P.zt64 = reinterpret_cast<double *>(ws + r.zt64);
+        P.zlo = ws + r.zlo;
+        P.zhi = ws + r.zhi;
+        P.C = ws + r.c;
+        P.adj = pp[d].adj_out ? reinterpret_cast<unsigned long long *>(pp[d].adj_out)
+                              : reinterpret_cast<unsigned long long *>(ws + r.adj);
+        P.nbr = reinterpret_cast<int *>(ws + r.nbr);
+        P.deg = reinterpret_cast<int *>(ws + r.deg);
+        P.recs = pp[d].sep.recs;
+        P.rec_cap = pp[d].sep.cap;
+        P.rec_count = reinterpret_cast<long long *>(pp[d].sep.count);
+        P.max_level = pp[d].max_level >= 0 ? std::min(pp[d].max_level, PC_MAX_LEVEL + 1) : PC_MAX_LEVEL + 1;
+        const double z = z_of_alpha(pp[d].alpha);
+        for (int l = 0; l < kLevels; ++l) {
+            P.tau[l] = tau_of(z, (double)P.m, l);
+            P.t[l] = std::isnan(P.tau[l]) ? 0.0f : (float)std::tanh(P.tau[l]);
+            const double eps = eps_c_of(L.prec, P.mp) + (4.0 * l + 16.0) * kU32;
+            P.band[l] = (float)((double)ctx->opt.margin_scale * eps);
+        }
+        P.t0 = std::tanh(P.tau[0]);
+        P.eps_c = eps_c_of(L.prec, P.mp);
+    }
+}
+
+Batch make_batch(const pc_ctx *ctx, const Plan &L, unsigned char *ws) {
+    Batch b{};
+    b.probs = reinterpret_cast<Prob *>(ws + L.table);
+    b.count = L.count;
+    b.prec = L.prec;
+    b.force_recheck = L.prec != PC_PREC_FP64 && ctx->opt.force_recheck_all;
+    const long long *bases = reinterpret_cast<const long long *>(ws + L.table + sizeof(Prob) * L.count);
+    b.row_base = bases;
+    b.cs_base = bases + (L.count + 1);
+    b.st_base = bases + 2 * (L.count + 1);
+    b.tile_base = bases + 3 * (L.count + 1);
+    b.nitems = reinterpret_cast<long long *>(ws + L.nitems);
+    b.item_off = reinterpret_cast<long long *>(ws + L.item_off);
+    b.binom = ctx->binom;
+    b.st = reinterpret_cast<DevState *>(ws + L.st);
+    b.rq = reinterpret_cast<RqEntry *>(ws + L.rq);
+    b.rq_cap = L.rq_cap;
+    b.total_rows = L.total_rows;
+    return b;
+}
+
+pc_status ensure_binom(pc_ctx *ctx, int64_t max_n) {
+    if (max_n + 1 <= ctx->binom_rows) return PC_OK;
+    const int64_t rows = std::max<int64_t>(max_n + 1, 2 * ctx->binom_rows);
+    unsigned long long *t = nullptr;
+    PC_HIP(hipStreamSynchronize(ctx->stream));
+    PC_HIP(hipMalloc(&t, sizeof(unsigned long long) * rows * kBinomCols));
+    if (ctx->binom) (void)hipFree(ctx->binom);
+    ctx->binom = t;
+    ctx->binom_rows = rows;
+    PC_HIP(launch_binom(ctx->stream, t, rows));
+    return PC_OK;
+}
+
+// Copies the problem table into the workspace (stream ordered, from pinned staging).
+pc_status upload_table(pc_ctx *ctx, const Plan &L, unsigned char *ws, const std::vector<Prob> &probs) {
+    if (ctx->staging_pending) {
+        PC_HIP(hipEventSynchronize(ctx->staging_done));
+        ctx->staging_pending = false;
+    }
+    if (L.table_bytes > ctx->staging_bytes) {
+        if (ctx->staging) (void)hipHostFree(ctx->staging);
+        ctx->staging = nullptr;
+        ctx->staging_bytes = 0;
+        const size_t want = std::max(L.table_bytes, (size_t)1 << 16);
+        PC_HIP(hipHostMalloc(&ctx->staging, want, hipHostMallocDefault));
+        ctx->staging_bytes = want;
+    }
+    unsigned char *h = static_cast<unsigned char *>(ctx->staging);
+    std::memcpy(h, probs.data(), sizeof(Prob) * L.count);
+    long long *bases = reinterpret_cast<long long *>(h + sizeof(Prob) * L.count);
+    const size_t nb = (size_t)L.count + 1;
+    std::memcpy(bases, L.row_base.data(), sizeof(long long) * nb);
+    std::memcpy(bases + nb, L.cs_base.data(), sizeof(long long) * nb);
+    std::memcpy(bases + 2 * nb, L.st_base.data(), sizeof(long long) * nb);
+    std::memcpy(bases + 3 * nb, L.tile_base.data(), sizeof(long long) * nb);
+    PC_HIP(hipMemcpyAsync(ws + L.table, h, L.table_bytes, hipMemcpyHostToDevice, ctx->stream));
+    PC_HIP(hipEventRecord(ctx->staging_done, ctx->stream));
+    ctx->staging_pending = true;
     return PC_OK;
 }
 
@@ -128,123 +315,201 @@ int level_lds_bytes(const pc_ctx *ctx) {
     return (int)(fixed + budget);
 }
 
-// Correlation + level 0 into adjacency `adj`.
-pc_status corr_impl(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alpha,
-                    const Ws &w, unsigned long long *adj, long long *zero_count) {
+bool timed(const pc_ctx *ctx, int bit, bool capturing) { return !capturing && (ctx->opt.timing & bit); }
+
+// Standardize + correlation + level 0 for every problem of the batch.
+pc_status enqueue_corr(pc_ctx *ctx, const Batch &b, const Plan &L, bool capturing) {
     hipStream_t s = ctx->stream;
-    const Layout &L = w.L;
-    const int prec = ctx->opt.precision;
-    PC_HIP(launch_init(s, w.st(), w.at<unsigned long long>(L.binom), n, zero_count));
-    PC_HIP(launch_colstats(s, X, m, n, w.at<double>(L.mu), w.at<double>(L.inv), w.st()));
-    PC_HIP(launch_standardize(s, X, m, n, L.mp, w.at<double>(L.mu), w.at<double>(L.inv),
-                              w.at<double>(L.zt64), w.base + L.zlo, w.base + L.zhi, prec));
-    CorrArgs a{};
-    a.zt64 = w.at<double>(L.zt64);
-    a.za = prec == PC_PREC_BF16X3 ? (const void *)(w.base + L.zhi) : (const void *)(w.base + L.zlo);
-    a.zb = w.base + L.zlo;
-    a.C = w.base + L.c;
-    a.adj = adj;
-    a.st = w.st();
-    a.n = n;
-    a.m = m;
-    a.mp = L.mp;
-    a.W = words_per_row(n);
-    const double z = z_of_alpha(alpha);
-    a.tau0 = tau_of(z, (double)m, 0);
-    a.t0 = std::tanh(a.tau0);
-    a.eps_c = eps_c_of(prec, L.mp);
-    a.force_recheck = ctx->opt.force_recheck_all;
-    PC_HIP(launch_corr(s, a, prec));
+    PC_HIP(launch_init(s, b));
+    if (timed(ctx, 16, capturing)) PC_HIP(hipEventRecord(ctx->ev_prep[0], s));
+    PC_HIP(launch_colstats(s, b, L.cs_blocks));
+    PC_HIP(launch_standardize(s, b, L.st_blocks));
+    if (timed(ctx, 16, capturing)) PC_HIP(hipEventRecord(ctx->ev_prep[1], s));
+    if (timed(ctx, 1, capturing)) PC_HIP(hipEventRecord(ctx->ev_corr[0], s));
+    PC_HIP(launch_corr(s, b, L.tiles));
+    if (timed(ctx, 1, capturing)) PC_HIP(hipEventRecord(ctx->ev_corr[1], s));
     return PC_OK;
 }
 
-// Launches compaction, the level kernel and the re-check of one level (no synchronisation).
-pc_status level_launch(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, const Ws &w,
-                       unsigned long long *adj, const pc_sepset *sep, bool run_tests,
-                       hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
+struct OrderRun {
+    const pc_order *order;
+    const Plan *L;
+    unsigned char *ws;
+};
+
+constexpr int kProbeMaxLevel = 8;
+
+// Compaction, planning, (probe pass,) CI tests and FP64 re-check of one level.
+pc_status enqueue_level(pc_ctx *ctx, const Batch &b, int level, bool capturing, const OrderRun *ord = nullptr) {
     hipStream_t s = ctx->stream;
-    const Layout &L = w.L;
-    const int prec = ctx->opt.precision;
-    const int64_t W = words_per_row(n);
-    const int R = ranks_per_item(ctx, level);
-    if (e0) PC_HIP(hipEventRecord(e0, s));
-    PC_HIP(launch_compact(s, adj, n, W, level, R, w.at<int>(L.nbr), w.at<int>(L.deg),
-                          w.at<long long>(L.nitems), w.at<long long>(L.item_off),
-                          w.at<unsigned long long>(L.binom), w.st()));
-    if (e1) PC_HIP(hipEventRecord(e1, s));
-    if (!run_tests) return PC_OK;
-    const double z = z_of_alpha(alpha);
-    const double tau = tau_of(z, (double)m, level);
-    LevelArgs a{};
-    a.C = w.base + L.c;
-    a.zt64 = w.at<double>(L.zt64);
-    a.adj = adj;
-    a.nbr = w.at<int>(L.nbr);
-    a.deg = w.at<int>(L.deg);
-    a.item_off = w.at<long long>(L.item_off);
-    a.binom = w.at<unsigned long long>(L.binom);
-    a.st = w.st();
-    a.recs = sep->recs;
-    a.rec_count = reinterpret_cast<long long *>(sep->count);
-    a.rec_cap = sep->cap;
-    a.n = n;
-    a.m = m;
-    a.mp = L.mp;
-    a.W = W;
-    a.level = level;
-    a.ranks_per_item = R;
-    a.lds_bytes = level_lds_bytes(ctx);
-    a.force_recheck = prec != PC_PREC_FP64 && ctx->opt.force_recheck_all;
-    a.tau = tau;
-    a.t = (float)std::tanh(tau);
-    const double eps = eps_c_of(prec, L.mp) + (4.0 * level + 16.0) * kU32;
-    a.band = (float)((double)ctx->opt.margin_scale * eps);
-    a.rq = w.at<pc_sep_rec>(L.rq);
-    a.rq_cap = L.rq_cap;
-    PC_HIP(launch_level(s, a, prec, auto_grid(ctx)));
-    RecheckArgs r{};
-    r.zt64 = prec == PC_PREC_FP64 ? nullptr : w.at<double>(L.zt64);
-    r.C64 = prec == PC_PREC_FP64 ? w.at<double>(L.c) : nullptr;
-    r.adj = adj;
-    r.st = w.st();
-    r.rq = a.rq;
-    r.rq_cap = a.rq_cap;
-    r.recs = a.recs;
-    r.rec_count = a.rec_count;
-    r.rec_cap = a.rec_cap;
-    r.n = n;
-    r.m = m;
-    r.mp = L.mp;
-    r.W = W;
-    r.level = level;
-    r.audit = a.force_recheck;
-    r.tau = tau;
-    PC_HIP(launch_recheck(s, r, auto_grid(ctx)));
-    if (e2) PC_HIP(hipEventRecord(e2, s));
+    const int R = ranks_per_item(ctx, level <= PC_MAX_LEVEL ? level : PC_MAX_LEVEL);
+    if (timed(ctx, 4, capturing)) PC_HIP(hipEventRecord(ctx->ev_compact[level][0], s));
+    PC_HIP(launch_compact(s, b, level, R));
+    PC_HIP(launch_plan(s, b, level));
+    if (timed(ctx, 4, capturing)) PC_HIP(hipEventRecord(ctx->ev_compact[level][1], s));
+    if (level > PC_MAX_LEVEL) return PC_OK;  // planning only: tells whether the cap stopped a run
+    if (ord && level >= ord->order->min_level && level <= kProbeMaxLevel) {
+        const Plan &L = *ord->L;
+        long long *foff = reinterpret_cast<long long *>(ord->ws + L.foff);
+        int *skip = reinterpret_cast<int *>(ord->ws + L.skip);
+        float *feats = reinterpret_cast<float *>(ord->ws + L.feats);
+        float *scores = reinterpret_cast<float *>(ord->ws + L.scores);
+        PC_HIP(launch_feat_plan(s, b, foff, L.order_rows, skip));
+        PC_HIP(launch_features(s, b, level, foff, feats, nullptr, skip));
+        PC_HIP(launch_mlp_forward(s, ord->order->params, feats, 0, foff + L.total_rows, L.order_rows, scores,
+                                  nullptr, skip, 4 * ctx->num_cu));
+        PC_HIP(launch_probe(s, b, level, foff, scores, ord->order->top, skip));
+    }
+    if (timed(ctx, 2, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][0], s));
+    PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx), auto_grid(ctx)));
+    if (timed(ctx, 2, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][1], s));
+    if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][0], s));
+    PC_HIP(launch_recheck(s, b, level, 4 * ctx->num_cu));
+    if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][1], s));
     return PC_OK;
 }
 
-pc_status read_state(pc_ctx *ctx, const Ws &w) {
-    PC_HIP(hipMemcpyAsync(ctx->host_state, w.st(), sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
+// Levels (after level 0) to enqueue: up to the largest cap of the batch; a cap above PC_MAX_LEVEL
+// adds one planning-only pass that tells whether the level cap stopped a problem.
+int levels_to_enqueue(const pc_problem *pp, int count) {
+    int top = 0;
+    for (int d = 0; d < count; ++d) {
+        const int cap = pp[d].max_level >= 0 ? std::min(pp[d].max_level, PC_MAX_LEVEL + 1) : PC_MAX_LEVEL + 1;
+        top = std::max(top, cap);
+    }
+    return top;
+}
+
+// Per-problem result from the device statistics (after the stream has completed). A problem ran
+// level l iff G' of l had a node with at least l + 1 neighbours and l was enabled (within its cap,
+// PC_MAX_LEVEL, and m - l - 3 > 0); the first level that did not run tells why it stopped.
+pc_status problem_result(const Prob &P, const DevState &ds, pc_run_stats *st) {
+    int levels_run = 1;
+    pc_status res = PC_OK;
+    for (int l = 1; l <= PC_MAX_LEVEL + 1; ++l) {
+        const bool enough = P.maxdeg[l] >= l + 1;
+        const bool enabled = l <= P.max_level && l <= PC_MAX_LEVEL && !std::isnan(P.tau[l]);
+        if (enough && enabled) {
+            levels_run = l + 1;
+            continue;
+        }
+        if (enough && l <= P.max_level) {
+            if (l > PC_MAX_LEVEL) res = PC_WARN_LEVEL_CAP;
+            else if (std::isnan(P.tau[l])) res = PC_WARN_SAMPLE_LIMIT;
+        }
+        break;
+    }
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        for (int l = 0; l <= PC_MAX_LEVEL; ++l) {
+            st->tests[l] = P.tests[l];
+            st->removed[l] = P.removed[l];
+            st->rechecks[l] = P.rechecks[l];
+            st->items[l] = P.items[l];
+            st->audit_violations[l] = P.audit_viol[l];
+            st->probe_tests[l] = P.probe_tests[l];
+            st->probe_removed[l] = P.probe_removed[l];
+            st->max_degree[l] = l == 0 ? 0 : P.maxdeg[l];
+        }
+        st->levels_run = levels_run;
+    }
+    if (P.err) return (pc_status)P.err;
+    if (ds.overflow) return PC_ERR_UNSUPPORTED;
+    if (ds.rq_overflow) return PC_ERR_WORKSPACE;
+    return res;
+}
+
+// Results of every problem from a downloaded table (SepSet counts are read per problem).
+pc_status results(const std::vector<Prob> &host, const DevState &ds, pc_run_stats *st, pc_status *status) {
+    pc_status first = PC_OK;
+    for (size_t d = 0; d < host.size(); ++d) {
+        pc_status r = problem_result(host[d], ds, st ? &st[d] : nullptr);
+        if (r >= 0 && host[d].rec_count) {
+            long long cnt = 0;
+            PC_HIP(hipMemcpy(&cnt, host[d].rec_count, sizeof(cnt), hipMemcpyDeviceToHost));
+            if (cnt > host[d].rec_cap) r = PC_ERR_SEPSET_CAPACITY;
+        }
+        if (status) status[d] = r;
+        if (r < 0 && first >= 0) first = r;
+        if (r > 0 && first == PC_OK) first = r;
+    }
+    return first;
+}
+
+// Copies the problem table and queue state back (synchronising) and fills per-problem results.
+pc_status collect(pc_ctx *ctx, size_t table_off, size_t st_off, int count, unsigned char *ws,
+                  pc_run_stats *st, pc_status *status, std::vector<Prob> &host) {
+    host.resize(count);
+    DevState ds;
+    PC_HIP(hipMemcpyAsync(host.data(), ws + table_off, sizeof(Prob) * count, hipMemcpyDeviceToHost, ctx->stream));
+    PC_HIP(hipMemcpyAsync(&ds, ws + st_off, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
     PC_HIP(hipStreamSynchronize(ctx->stream));
+    return results(host, ds, st, status);
+}
+
+void fill_times(pc_ctx *ctx, pc_run_stats *st, int top_level) {
+    if (!st || !ctx->opt.timing) return;
+    const int tm = ctx->opt.timing;
+    if (tm & 16) (void)hipEventElapsedTime(&st->prep_ms, ctx->ev_prep[0], ctx->ev_prep[1]);
+    if (tm & 1) (void)hipEventElapsedTime(&st->corr_ms, ctx->ev_corr[0], ctx->ev_corr[1]);
+    for (int l = 1; l <= std::min(top_level, PC_MAX_LEVEL); ++l) {
+        if (tm & 4) (void)hipEventElapsedTime(&st->compact_ms[l], ctx->ev_compact[l][0], ctx->ev_compact[l][1]);
+        if (tm & 2) (void)hipEventElapsedTime(&st->level_ms[l], ctx->ev_level[l][0], ctx->ev_level[l][1]);
+        if (tm & 8) (void)hipEventElapsedTime(&st->recheck_ms[l], ctx->ev_recheck[l][0], ctx->ev_recheck[l][1]);
+    }
+}
+
+pc_status check_ws(void *ws, size_t ws_bytes, const Plan &L) {
+    if (!ws) return PC_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return PC_ERR_INVALID_ARG;
+    if (ws_bytes < L.total) return PC_ERR_WORKSPACE;
     return PC_OK;
 }
 
-void fill_level_stats(pc_run_stats *st, const DevState &d, int level) {
-    if (!st || level > PC_MAX_LEVEL) return;
-    st->tests[level] = d.tests[level];
-    st->removed[level] = d.removed[level];
-    st->rechecks[level] = d.rechecks[level];
-    st->items[level] = d.items[level];
-    st->audit_violations[level] = d.audit_viol[level];
-    st->max_degree[level] = d.maxdeg[level];
+pc_status check_problem(const pc_problem &p) {
+    if (!p.X || !p.adj_out || !p.sep.count || (!p.sep.recs && p.sep.cap > 0)) return PC_ERR_INVALID_ARG;
+    if (!(p.alpha > 0.0 && p.alpha < 1.0)) return PC_ERR_INVALID_ARG;
+    return check_shape(p.n, p.m);
 }
 
-pc_status state_error(const DevState &d) {
-    if (d.err) return (pc_status)d.err;
-    if (d.overflow) return PC_ERR_UNSUPPORTED;
-    if (d.rq_overflow) return PC_ERR_WORKSPACE;
+Plan plan_of(const pc_problem *pp, int count, const pc_options &o) {
+    std::vector<int64_t> ns(count), ms(count);
+    for (int d = 0; d < count; ++d) { ns[d] = pp[d].n; ms[d] = pp[d].m; }
+    return make_plan(ns.data(), ms.data(), count, o);
+}
+
+// Every launch of the batched skeletons (the table must already be uploaded).
+pc_status enqueue_skeletons(pc_ctx *ctx, const pc_problem *pp, int count, const Plan &L,
+                            unsigned char *ws, bool capturing, const pc_order *order = nullptr) {
+    const Batch b = make_batch(ctx, L, ws);
+    pc_status s = enqueue_corr(ctx, b, L, capturing);
+    if (s != PC_OK) return s;
+    const OrderRun ord{order, &L, ws};
+    const int top = levels_to_enqueue(pp, count);
+    for (int l = 1; l <= top; ++l)
+        if ((s = enqueue_level(ctx, b, l, capturing, order ? &ord : nullptr)) != PC_OK) return s;
     return PC_OK;
+}
+
+bool valid_order(const pc_order *o) {
+    return o && o->params && o->min_level >= 1 && o->min_level <= kProbeMaxLevel && o->top >= 1 && o->top <= 8 &&
+           o->max_rows > 0;
+}
+
+// Validates a batch and prepares its table in the workspace.
+pc_status prepare(pc_ctx *ctx, const pc_problem *probs, int count, void *ws, size_t ws_bytes,
+                  Plan &L, std::vector<Prob> &table) {
+    pc_status s;
+    int64_t max_n = 0;
+    for (int d = 0; d < count; ++d) {
+        if ((s = check_problem(probs[d])) != PC_OK) return s;
+        max_n = std::max(max_n, probs[d].n);
+    }
+    L = plan_of(probs, count, ctx->opt);
+    if ((s = check_ws(ws, ws_bytes, L)) != PC_OK) return s;
+    if ((s = ensure_binom(ctx, max_n)) != PC_OK) return s;
+    fill_probs(ctx, L, static_cast<unsigned char *>(ws), probs, table);
+    return upload_table(ctx, L, static_cast<unsigned char *>(ws), table);
 }
 
 }  // namespace
@@ -255,6 +520,22 @@ pc_status pc_default_options(pc_options *opt) {
     if (!opt) return PC_ERR_INVALID_ARG;
     *opt = defaults();
     return PC_OK;
+}
+
+void pc_destroy(pc_ctx *ctx) {
+    if (!ctx) return;
+    auto rm = [](hipEvent_t e) { if (e) (void)hipEventDestroy(e); };
+    for (auto e : ctx->ev_prep) rm(e);
+    for (auto e : ctx->ev_corr) rm(e);
+    for (int l = 0; l < kLevels; ++l)
+        for (int k = 0; k < 2; ++k) { rm(ctx->ev_compact[l][k]); rm(ctx->ev_level[l][k]); rm(ctx->ev_recheck[l][k]); }
+    rm(ctx->staging_done);
+    if (ctx->binom) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->binom);
+    }
+    if (ctx->staging) (void)hipHostFree(ctx->staging);
+    delete ctx;
 }
 
 pc_status pc_create(pc_ctx **out, void *stream, const pc_options *opt) {
@@ -273,47 +554,66 @@ pc_status pc_create(pc_ctx **out, void *stream, const pc_options *opt) {
     c->opt = o;
     c->device = dev;
     c->num_cu = prop.multiProcessorCount;
-    if (hipHostMalloc(reinterpret_cast<void **>(&c->host_state), sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
-        delete c;
-        return PC_ERR_HIP;
+    bool ok = true;
+    auto mk = [&](hipEvent_t &e) { if (hipEventCreate(&e) != hipSuccess) { e = nullptr; ok = false; } };
+    for (auto &e : c->ev_prep) mk(e);
+    for (auto &e : c->ev_corr) mk(e);
+    for (int l = 0; l < kLevels; ++l)
+        for (int k = 0; k < 2; ++k) { mk(c->ev_compact[l][k]); mk(c->ev_level[l][k]); mk(c->ev_recheck[l][k]); }
+    if (hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming) != hipSuccess) {
+        c->staging_done = nullptr;
+        ok = false;
     }
-    std::memset(c->host_state, 0, sizeof(DevState));
-    for (auto &e : c->ev) {
-        if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+    if (ok && ensure_binom(c, 8191) != PC_OK) ok = false;
+    if (ok && hipStreamSynchronize(c->stream) != hipSuccess) ok = false;
+    if (!ok) {
+        pc_destroy(c);
+        return PC_ERR_HIP;
     }
     *out = c;
     return PC_OK;
 }
 
-void pc_destroy(pc_ctx *ctx) {
-    if (!ctx) return;
-    for (auto &e : ctx->ev)
-        if (e) (void)hipEventDestroy(e);
-    (void)hipHostFree(ctx->host_state);
-    delete ctx;
-}
-
 size_t pc_workspace_bytes(int64_t n, int64_t m, const pc_options *opt) {
     pc_options o = opt ? *opt : defaults();
     if (n < 1 || m < 1) return 0;
-    return Layout::make(n, m, o.precision, rq_cap_of(o)).total;
+    return make_plan(&n, &m, 1, o).total;
+}
+
+size_t pc_batch_workspace_bytes(const pc_problem *probs, int count, const pc_options *opt) {
+    pc_options o = opt ? *opt : defaults();
+    if (!probs || count < 1) return 0;
+    for (int d = 0; d < count; ++d)
+        if (probs[d].n < 1 || probs[d].m < 1) return 0;
+    return plan_of(probs, count, o).total;
 }
 
 pc_status pc_corr(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alpha, void *ws,
                   size_t ws_bytes, void *C_out, uint64_t *adj_out) {
     if (!ctx || !X) return PC_ERR_INVALID_ARG;
     if (!(alpha > 0.0 && alpha < 1.0)) return PC_ERR_INVALID_ARG;
-    pc_status st = check_shape(n, m);
-    if (st != PC_OK) return st;
-    Ws w;
-    if ((st = check_ws(ctx, n, m, ws, ws_bytes, w)) != PC_OK) return st;
-    unsigned long long *adj = w.at<unsigned long long>(w.L.adj);
-    if ((st = corr_impl(ctx, X, m, n, alpha, w, adj, nullptr)) != PC_OK) return st;
+    pc_status s = check_shape(n, m);
+    if (s != PC_OK) return s;
+    const Plan L = make_plan(&n, &m, 1, ctx->opt);
+    if ((s = check_ws(ws, ws_bytes, L)) != PC_OK) return s;
+    if ((s = ensure_binom(ctx, n)) != PC_OK) return s;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    pc_problem p{};
+    p.X = X;
+    p.m = m;
+    p.n = n;
+    p.alpha = alpha;
+    p.max_level = 0;
+    std::vector<Prob> probs;
+    fill_probs(ctx, L, w, &p, probs);
+    if ((s = upload_table(ctx, L, w, probs)) != PC_OK) return s;
+    const Batch b = make_batch(ctx, L, w);
+    if ((s = enqueue_corr(ctx, b, L, false)) != PC_OK) return s;
     const size_t esz = ctx->opt.precision == PC_PREC_FP64 ? sizeof(double) : sizeof(float);
-    if (C_out) PC_HIP(hipMemcpyAsync(C_out, w.base + w.L.c, esz * n * n, hipMemcpyDeviceToDevice, ctx->stream));
+    if (C_out) PC_HIP(hipMemcpyAsync(C_out, w + L.reg[0].c, esz * n * n, hipMemcpyDeviceToDevice, ctx->stream));
     if (adj_out)
-        PC_HIP(hipMemcpyAsync(adj_out, adj, sizeof(uint64_t) * n * words_per_row(n), hipMemcpyDeviceToDevice,
-                              ctx->stream));
+        PC_HIP(hipMemcpyAsync(adj_out, w + L.reg[0].adj, sizeof(uint64_t) * n * words_per_row(n),
+                              hipMemcpyDeviceToDevice, ctx->stream));
     return PC_OK;
 }
 
@@ -321,10 +621,12 @@ pc_status pc_sync_status(pc_ctx *ctx, void *ws, size_t ws_bytes) {
     if (!ctx) return PC_ERR_INVALID_ARG;
     PC_HIP(hipStreamSynchronize(ctx->stream));
     if (!ws) return PC_OK;
-    if (ws_bytes < sizeof(DevState)) return PC_ERR_WORKSPACE;
-    PC_HIP(hipMemcpyAsync(ctx->host_state, ws, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
-    PC_HIP(hipStreamSynchronize(ctx->stream));
-    return state_error(*ctx->host_state);
+    const size_t table = align256(sizeof(DevState));
+    if (ws_bytes < table + sizeof(Prob)) return PC_ERR_WORKSPACE;
+    int err = 0;
+    PC_HIP(hipMemcpy(&err, static_cast<unsigned char *>(ws) + table + offsetof(Prob, err), sizeof(int),
+                     hipMemcpyDeviceToHost));
+    return (pc_status)err;
 }
 
 pc_status pc_level(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, uint64_t *adj,
@@ -334,92 +636,259 @@ pc_status pc_level(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, u
     if (!(alpha > 0.0 && alpha < 1.0)) return PC_ERR_INVALID_ARG;
     pc_status s = check_shape(n, m);
     if (s != PC_OK) return s;
-    Ws w;
-    if ((s = check_ws(ctx, n, m, ws, ws_bytes, w)) != PC_OK) return s;
+    const Plan L = make_plan(&n, &m, 1, ctx->opt);
+    if ((s = check_ws(ws, ws_bytes, L)) != PC_OK) return s;
+    if ((s = ensure_binom(ctx, n)) != PC_OK) return s;
     const auto t0 = std::chrono::steady_clock::now();
-    const bool run_tests = (double)m - level - 3.0 > 0.0;
-    PC_HIP(launch_rearm(ctx->stream, w.st()));
-    hipEvent_t *ev = ctx->opt.timing ? ctx->ev : nullptr;
-    s = level_launch(ctx, level, n, m, alpha, w, reinterpret_cast<unsigned long long *>(adj), sep, run_tests,
-                     ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, ev ? ev[2] : nullptr);
-    if (s != PC_OK) return s;
-    if ((s = read_state(ctx, w)) != PC_OK) return s;
-    const DevState &d = *ctx->host_state;
-    if ((s = state_error(d)) != PC_OK) return s;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    pc_problem p{};
+    p.m = m;
+    p.n = n;
+    p.alpha = alpha;
+    p.max_level = level;
+    p.adj_out = adj;
+    p.sep = *sep;
+    std::vector<Prob> probs;
+    fill_probs(ctx, L, w, &p, probs);
+    if ((s = upload_table(ctx, L, w, probs)) != PC_OK) return s;
+    const Batch b = make_batch(ctx, L, w);
+    PC_HIP(launch_rearm(ctx->stream, b));
+    if ((s = enqueue_level(ctx, b, level, false)) != PC_OK) return s;
+    std::vector<Prob> host;
+    pc_status status = PC_OK;
+    const pc_status r = collect(ctx, L.table, L.st, 1, w, nullptr, &status, host);
+    if (r < 0 && r != PC_ERR_SEPSET_CAPACITY) return r;
+    const Prob &P = host[0];
     if (st) {
-        fill_level_stats(st, d, level);
-        if (ev && run_tests) {
-            (void)hipEventElapsedTime(&st->compact_ms[level], ev[0], ev[1]);
-            (void)hipEventElapsedTime(&st->level_ms[level], ev[1], ev[2]);
-        }
+        st->tests[level] = P.tests[level];
+        st->removed[level] = P.removed[level];
+        st->rechecks[level] = P.rechecks[level];
+        st->items[level] = P.items[level];
+        st->audit_violations[level] = P.audit_viol[level];
+        st->max_degree[level] = P.maxdeg[level];
+        const int tm = ctx->opt.timing;
+        if (tm & 4) (void)hipEventElapsedTime(&st->compact_ms[level], ctx->ev_compact[level][0], ctx->ev_compact[level][1]);
+        if (tm & 2) (void)hipEventElapsedTime(&st->level_ms[level], ctx->ev_level[level][0], ctx->ev_level[level][1]);
+        if (tm & 8) (void)hipEventElapsedTime(&st->recheck_ms[level], ctx->ev_recheck[level][0], ctx->ev_recheck[level][1]);
         st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
-    if (!run_tests && !d.done) return PC_WARN_SAMPLE_LIMIT;
-    long long cnt = 0;
-    PC_HIP(hipMemcpy(&cnt, sep->count, sizeof(cnt), hipMemcpyDeviceToHost));
-    if (cnt > sep->cap) return PC_ERR_SEPSET_CAPACITY;
+    if (r == PC_ERR_SEPSET_CAPACITY) return r;
+    if (std::isnan(P.tau[level]) && P.maxdeg[level] >= level + 1) return PC_WARN_SAMPLE_LIMIT;
     return PC_OK;
 }
 
 pc_status pc_skeleton(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alpha,
                       int max_level, uint64_t *adj_out, const pc_sepset *sep, pc_run_stats *st,
                       void *ws, size_t ws_bytes) {
-    if (!ctx || !X || !adj_out || !sep || !sep->count || (!sep->recs && sep->cap > 0))
-        return PC_ERR_INVALID_ARG;
-    if (!(alpha > 0.0 && alpha < 1.0)) return PC_ERR_INVALID_ARG;
+    if (!ctx || !sep) return PC_ERR_INVALID_ARG;
+    pc_problem p{};
+    p.X = X;
+    p.m = m;
+    p.n = n;
+    p.alpha = alpha;
+    p.max_level = max_level;
+    p.adj_out = adj_out;
+    p.sep = *sep;
+    const auto t0 = std::chrono::steady_clock::now();
+    Plan L;
+    std::vector<Prob> table;
+    pc_status s = prepare(ctx, &p, 1, ws, ws_bytes, L, table);
+    if (s != PC_OK) return s;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    if ((s = enqueue_skeletons(ctx, &p, 1, L, w, false)) != PC_OK) return s;
+    std::vector<Prob> host;
+    pc_status status = PC_OK;
+    const pc_status r = collect(ctx, L.table, L.st, 1, w, st, &status, host);
+    if (r == PC_ERR_HIP) return r;
+    if (st) {
+        fill_times(ctx, st, levels_to_enqueue(&p, 1));
+        st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+pc_status pc_batch_skeleton(pc_ctx *ctx, const pc_problem *probs, int count, pc_run_stats *st,
+                            pc_status *status, void *ws, size_t ws_bytes) {
+    if (!ctx || !probs || count < 1) return PC_ERR_INVALID_ARG;
+    const auto t0 = std::chrono::steady_clock::now();
+    Plan L;
+    std::vector<Prob> table;
+    pc_status s = prepare(ctx, probs, count, ws, ws_bytes, L, table);
+    if (s != PC_OK) return s;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    if ((s = enqueue_skeletons(ctx, probs, count, L, w, false)) != PC_OK) return s;
+    std::vector<Prob> host;
+    const pc_status r = collect(ctx, L.table, L.st, count, w, st, status, host);
+    if (st) {
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (int d = 0; d < count; ++d) st[d].wall_ms = ms;
+    }
+    return r;
+}
+
+pc_status pc_batch_capture(pc_ctx *ctx, const pc_problem *probs, int count, void *ws,
+                           size_t ws_bytes, pc_graph **out) {
+    if (!ctx || !probs || count < 1 || !out) return PC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (ctx->stream == nullptr) return PC_ERR_INVALID_ARG;  // the null stream cannot be captured
+    Plan L;
+    pc_graph *g = new (std::nothrow) pc_graph();
+    if (!g) return PC_ERR_HIP;
+    pc_status s = prepare(ctx, probs, count, ws, ws_bytes, L, g->host_probs);
+    if (s != PC_OK) { delete g; return s; }
+    g->ctx = ctx;
+    g->ws = static_cast<unsigned char *>(ws);
+    g->count = count;
+    g->table_off = L.table;
+    g->st_off = L.st;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) { delete g; return PC_ERR_HIP; }
+    if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        delete g;
+        return PC_ERR_HIP;
+    }
+    s = enqueue_skeletons(ctx, probs, count, L, g->ws, true);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
+    if (s != PC_OK || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        return s != PC_OK ? s : PC_ERR_HIP;
+    }
+    g->graph = graph;
+    if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return PC_ERR_HIP;
+    }
+    *out = g;
+    return PC_OK;
+}
+
+pc_status pc_graph_launch(pc_graph *g) {
+    if (!g) return PC_ERR_INVALID_ARG;
+    PC_HIP(hipGraphLaunch(g->exec, g->ctx->stream));
+    return PC_OK;
+}
+
+pc_status pc_graph_results(pc_graph *g, pc_run_stats *st, pc_status *status) {
+    if (!g) return PC_ERR_INVALID_ARG;
+    std::vector<Prob> host;
+    return collect(g->ctx, g->table_off, g->st_off, g->count, g->ws, st, status, host);
+}
+
+void pc_graph_destroy(pc_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+size_t pc_ordered_workspace_bytes(int64_t n, int64_t m, const pc_options *opt, const pc_order *order) {
+    pc_options o = opt ? *opt : defaults();
+    if (n < 1 || m < 1 || !order || order->max_rows <= 0) return 0;
+    return make_plan(&n, &m, 1, o, order->max_rows).total;
+}
+
+pc_status pc_skeleton_ordered(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alpha,
+                              int max_level, const pc_order *order, uint64_t *adj_out,
+                              const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes) {
+    if (!ctx || !sep || !valid_order(order)) return PC_ERR_INVALID_ARG;
+    pc_problem p{};
+    p.X = X;
+    p.m = m;
+    p.n = n;
+    p.alpha = alpha;
+    p.max_level = max_level;
+    p.adj_out = adj_out;
+    p.sep = *sep;
+    pc_status s = check_problem(p);
+    if (s != PC_OK) return s;
+    const Plan L = make_plan(&n, &m, 1, ctx->opt, order->max_rows);
+    if ((s = check_ws(ws, ws_bytes, L)) != PC_OK) return s;
+    if ((s = ensure_binom(ctx, n)) != PC_OK) return s;
+    const auto t0 = std::chrono::steady_clock::now();
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    std::vector<Prob> table;
+    fill_probs(ctx, L, w, &p, table);
+    if ((s = upload_table(ctx, L, w, table)) != PC_OK) return s;
+    if ((s = enqueue_skeletons(ctx, &p, 1, L, w, false, order)) != PC_OK) return s;
+    std::vector<Prob> host;
+    pc_status status = PC_OK;
+    const pc_status r = collect(ctx, L.table, L.st, 1, w, st, &status, host);
+    if (r == PC_ERR_HIP) return r;
+    if (st) {
+        fill_times(ctx, st, levels_to_enqueue(&p, 1));
+        st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+pc_status pc_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, const uint64_t *adj,
+                      float *feats, int32_t *meta, int64_t cap, int64_t *rows_out, void *ws,
+                      size_t ws_bytes) {
+    if (!ctx || !adj || !feats || !rows_out || cap < 0) return PC_ERR_INVALID_ARG;
+    if (level < 1 || level > PC_MAX_LEVEL || !(alpha > 0.0 && alpha < 1.0)) return PC_ERR_INVALID_ARG;
     pc_status s = check_shape(n, m);
     if (s != PC_OK) return s;
-    Ws w;
-    if ((s = check_ws(ctx, n, m, ws, ws_bytes, w)) != PC_OK) return s;
-    const auto t0 = std::chrono::steady_clock::now();
-    if (st) std::memset(st, 0, sizeof(*st));
-    unsigned long long *adj = reinterpret_cast<unsigned long long *>(adj_out);
-    hipEvent_t *ev = ctx->opt.timing ? ctx->ev : nullptr;
-    if (ev) PC_HIP(hipEventRecord(ev[2 * (PC_MAX_LEVEL + 2)], ctx->stream));
-    if ((s = corr_impl(ctx, X, m, n, alpha, w, adj, reinterpret_cast<long long *>(sep->count))) != PC_OK)
-        return s;
-    if (ev) PC_HIP(hipEventRecord(ev[2 * (PC_MAX_LEVEL + 2) + 1], ctx->stream));
-    pc_status result = PC_OK;
-    int levels_run = 1;
-    const int cap = max_level >= 0 ? max_level : PC_MAX_LEVEL + 1;
-    for (int level = 1; level <= cap && level <= PC_MAX_LEVEL + 1; ++level) {
-        const bool sample_ok = (double)m - level - 3.0 > 0.0;
-        const bool level_ok = level <= PC_MAX_LEVEL;
-        const bool run_tests = sample_ok && level_ok;
-        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-        if (ev && level <= PC_MAX_LEVEL) {
-            e0 = ev[2 * level];
-            e1 = ev[2 * level + 1];
-            e2 = ev[2 * (level + 1)];
-        }
-        if ((s = level_launch(ctx, level, n, m, alpha, w, adj, sep, run_tests, e0, e1, e2)) != PC_OK) return s;
-        if ((s = read_state(ctx, w)) != PC_OK) return s;
-        const DevState &d = *ctx->host_state;
-        if ((s = state_error(d)) != PC_OK) return s;
-        if (d.done) break;
-        if (!sample_ok) { result = PC_WARN_SAMPLE_LIMIT; break; }
-        if (!level_ok) { result = PC_WARN_LEVEL_CAP; break; }
-        levels_run = level + 1;
-        if (st && ev) {
-            (void)hipEventElapsedTime(&st->compact_ms[level], e0, e1);
-            (void)hipEventElapsedTime(&st->level_ms[level], e1, e2);
-        }
-    }
-    if ((s = read_state(ctx, w)) != PC_OK) return s;
-    const DevState &d = *ctx->host_state;
-    if ((s = state_error(d)) != PC_OK) return s;
-    if (st) {
-        for (int l = 0; l <= PC_MAX_LEVEL; ++l) fill_level_stats(st, d, l);
-        st->max_degree[0] = 0;
-        st->levels_run = levels_run;
-        if (ev) (void)hipEventElapsedTime(&st->corr_ms, ev[2 * (PC_MAX_LEVEL + 2)], ev[2 * (PC_MAX_LEVEL + 2) + 1]);
-    }
-    long long cnt = 0;
-    PC_HIP(hipMemcpy(&cnt, sep->count, sizeof(cnt), hipMemcpyDeviceToHost));
-    if (st)
-        st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (cnt > sep->cap) return PC_ERR_SEPSET_CAPACITY;
-    return result;
+    const Plan L = make_plan(&n, &m, 1, ctx->opt);
+    if ((s = check_ws(ws, ws_bytes, L)) != PC_OK) return s;
+    if ((s = ensure_binom(ctx, n)) != PC_OK) return s;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    // The snapshot is copied into the workspace's own bit matrix, so the caller's stays untouched.
+    PC_HIP(hipMemcpyAsync(w + L.reg[0].adj, adj, sizeof(uint64_t) * n * words_per_row(n), hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    pc_problem p{};
+    p.m = m;
+    p.n = n;
+    p.alpha = alpha;
+    p.max_level = level;
+    std::vector<Prob> probs;
+    fill_probs(ctx, L, w, &p, probs);
+    if ((s = upload_table(ctx, L, w, probs)) != PC_OK) return s;
+    const Batch b = make_batch(ctx, L, w);
+    PC_HIP(launch_rearm(ctx->stream, b));
+    PC_HIP(launch_compact(ctx->stream, b, level, ranks_per_item(ctx, level)));
+    // Feature offsets go to the level's item-offset buffer (free until the level runs).
+    long long *foff = reinterpret_cast<long long *>(w + L.item_off);
+    int *skip = reinterpret_cast<int *>(w + L.nitems);
+    PC_HIP(launch_feat_plan(ctx->stream, b, foff, cap, skip));
+    PC_HIP(launch_features(ctx->stream, b, level, foff, feats, meta, skip));
+    long long rows = 0;
+    PC_HIP(hipMemcpyAsync(&rows, foff + L.total_rows, sizeof(rows), hipMemcpyDeviceToHost, ctx->stream));
+    PC_HIP(hipStreamSynchronize(ctx->stream));
+    *rows_out = rows;
+    return rows > cap ? PC_ERR_WORKSPACE : PC_OK;
+}
+
+pc_status pc_mlp_forward(pc_ctx *ctx, const float *params, const float *X, int64_t rows, float *scores,
+                         float *act) {
+    if (!ctx || !params || !X || !scores || rows < 0) return PC_ERR_INVALID_ARG;
+    if (rows == 0) return PC_OK;
+    const long long tiles = (rows + 63) / 64;
+    const int grid = (int)std::min<long long>(tiles, 8LL * ctx->num_cu);
+    PC_HIP(launch_mlp_forward(ctx->stream, params, X, rows, nullptr, rows, scores, act, nullptr, grid));
+    return PC_OK;
+}
+
+pc_status pc_mlp_backward(pc_ctx *ctx, const float *params, const float *X, int64_t rows, const float *act,
+                          const float *dscore, float *grads, float *partial) {
+    if (!ctx || !params || !X || !act || !dscore || !grads || !partial || rows <= 0) return PC_ERR_INVALID_ARG;
+    PC_HIP(launch_mlp_backward(ctx->stream, params, X, rows, act, dscore, partial, grads));
+    return PC_OK;
+}
+
+pc_status pc_mlp_bce(pc_ctx *ctx, const float *scores, const float *labels, int64_t rows, float pos_weight,
+                     float *dscore, double *loss) {
+    if (!ctx || !scores || !labels || !dscore || !loss || rows <= 0) return PC_ERR_INVALID_ARG;
+    PC_HIP(launch_bce(ctx->stream, scores, labels, rows, pos_weight, dscore, loss));
+    return PC_OK;
+}
+
+pc_status pc_mlp_adam(pc_ctx *ctx, float *params, const float *grads, float *m1, float *m2, int step,
+                      float lr, float beta1, float beta2, float eps) {
+    if (!ctx || !params || !grads || !m1 || !m2 || step < 1) return PC_ERR_INVALID_ARG;
+    PC_HIP(launch_adam(ctx->stream, params, grads, m1, m2, step, lr, beta1, beta2, eps));
+    return PC_OK;
 }
 
 pc_status pc_comb_unrank(int32_t d, int32_t l, uint64_t t, int32_t skip, int32_t *out) {
@@ -463,6 +932,8 @@ size_t pc_abi_size(int which) {
         case 1: return sizeof(pc_sep_rec);
         case 2: return sizeof(pc_sepset);
         case 3: return sizeof(pc_run_stats);
+        case 4: return sizeof(pc_problem);
+        case 5: return sizeof(pc_order);
         default: return 0;
     }
 }

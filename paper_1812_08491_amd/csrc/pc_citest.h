@@ -1,0 +1,155 @@
+// The CI test of Eq. 3-6 for one conditioning set S shared across the j of a row (the sharing of
+// cuPC-S, Sec. 3.4), plus the edge-removal and queue helpers used by the level and probe kernels.
+#pragma once
+
+#include "pc_dev.h"
+
+namespace pcg {
+
+__device__ inline double fisher_z64(double r) {
+    if (!(fabs(r) < 1.0)) return INFINITY;
+    return fabs(0.5 * log((1.0 + r) / (1.0 - r)));
+}
+
+__device__ inline unsigned long long live_word(unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Clears edge (lo, hi) from G. Returns true for the one caller whose atomic AND on the canonical
+// bit (row lo, column hi) found it set: that caller owns the SepSet record.
+__device__ inline bool take_edge(unsigned long long *adj, int64_t W, int lo, int hi) {
+    const unsigned long long bit = 1ull << (hi & 63);
+    const unsigned long long old = atomicAnd(adj + (int64_t)lo * W + (hi >> 6), ~bit);
+    if (!(old & bit)) return false;
+    atomicAnd(adj + (int64_t)hi * W + (lo >> 6), ~(1ull << (lo & 63)));
+    return true;
+}
+
+__device__ inline void write_record(const Prob &P, int lo, int hi, int level, const int *S) {
+    const long long k = (long long)atomicAdd((unsigned long long *)P.rec_count, 1ull);
+    if (k < P.rec_cap) {
+        pc_sep_rec *rec = P.recs + k;
+        rec->i = lo;
+        rec->j = hi;
+        rec->level = level;
+        for (int c = 0; c < PC_MAX_LEVEL; ++c) rec->S[c] = c < level ? S[c] : -1;
+    }
+}
+
+// Pushes a test to the re-check queue; cls is the FP32 classification (0 dependent, 1 independent,
+// 2 inside the band).
+template <int L>
+__device__ inline void push_recheck(const Batch &b, int d, int row, int j, const int (&sid)[L], int cls) {
+    const unsigned long long k = atomicAdd(&b.st->rq_count, 1ull);
+    if (k >= (unsigned long long)b.rq_cap) {
+        atomicOr(&b.st->rq_overflow, 1);
+        return;
+    }
+    RqEntry *e = b.rq + k;
+    e->prob = d;
+    e->i = row;
+    e->j = j;
+    e->cls = cls;
+#pragma unroll
+    for (int c = 0; c < PC_MAX_LEVEL; ++c) e->S[c] = c < L ? sid[c] : -1;
+}
+
+// Factor of M2 = C[S,S] for one S (positions P into the row's neighbour list), shared by all j.
+template <typename T, int L>
+struct SetFactor {
+    T Lm[L * (L + 1) / 2];
+    T rd[L];
+    T y[L];
+    T h11;
+    float g2;   // (1 + sqrt(l tr(M2^-1)))^2: amplification of C errors into rho (FP32 band)
+    bool ok;    // all Cholesky pivots above the tolerance
+
+    // cs(p, q) = C[N_p, N_q] (1 on the diagonal), ci(p) = C[i, N_p].
+    template <class CS, class CI>
+    __device__ inline void build(const int (&P)[L], const CS &cs, const CI &ci) {
+        ok = true;
+#pragma unroll
+        for (int r = 0; r < L; ++r) {
+#pragma unroll
+            for (int c = 0; c <= r; ++c) {
+                T s = cs(P[r], P[c]);
+#pragma unroll
+                for (int e = 0; e < c; ++e) s -= Lm[r * (r + 1) / 2 + e] * Lm[c * (c + 1) / 2 + e];
+                if (r == c) {
+                    const T tol = sizeof(T) == 8 ? (T)1e-12 : (T)1e-4;
+                    if (!(s > tol)) ok = false;
+                    const T piv = s > tol ? s : (T)1;
+                    Lm[r * (r + 1) / 2 + r] = sqrt(piv);
+                    rd[r] = (T)1 / sqrt(piv);
+                } else {
+                    Lm[r * (r + 1) / 2 + c] = s * rd[c];
+                }
+            }
+        }
+        T yy = 0;
+#pragma unroll
+        for (int r = 0; r < L; ++r) {
+            T s = ci(P[r]);
+#pragma unroll
+            for (int e = 0; e < r; ++e) s -= Lm[r * (r + 1) / 2 + e] * y[e];
+            y[r] = s * rd[r];
+            yy += y[r] * y[r];
+        }
+        h11 = (T)1 - yy;
+        g2 = 4.0f;
+        if (sizeof(T) == 4 && L > 1) {
+            // g = 1 + sqrt(l tr(M2^-1)) bounds 1 + ||M2^-1 c||_1 for any c with c^T M2^-1 c <= 1,
+            // where tr(M2^-1) = ||L^-1||_F^2.
+            float tr = 0.0f;
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                float x[L];
+#pragma unroll
+                for (int r = 0; r < L; ++r) {
+                    if (r < k) { x[r] = 0.0f; continue; }
+                    float s = r == k ? 1.0f : 0.0f;
+#pragma unroll
+                    for (int e = 0; e < r; ++e) s -= (float)Lm[r * (r + 1) / 2 + e] * x[e];
+                    x[r] = s * (float)rd[r];
+                    tr += x[r] * x[r];
+                }
+            }
+            const float g = 1.0f + sqrtf((float)L * tr);
+            g2 = g * g;
+        }
+    }
+
+    // Test of edge (i, N_p) given S: 0 dependent, 1 independent, 2 to be re-checked in FP64
+    // (inside the FP32 error band, or M2 rank deficient).
+    template <class CS, class CI>
+    __device__ inline int test(const int (&P)[L], int p, const CS &cs, const CI &ci, double tau,
+                               float tl, float band) const {
+        T w[L];
+        T ww = 0, yw = 0;
+#pragma unroll
+        for (int r = 0; r < L; ++r) {
+            T s = cs(p, P[r]);
+#pragma unroll
+            for (int e = 0; e < r; ++e) s -= Lm[r * (r + 1) / 2 + e] * w[e];
+            w[r] = s * rd[r];
+            ww += w[r] * w[r];
+            yw += y[r] * w[r];
+        }
+        const T h22 = (T)1 - ww;
+        const T h12 = ci(p) - yw;
+        if (sizeof(T) == 8) {
+            if (!ok) return 2;  // rank-deficient M2: pseudo-inverse path of the re-check kernel
+            const double rho = (h11 > 0 && h22 > 0) ? (double)h12 / sqrt((double)h11 * (double)h22) : 0.0;
+            return fisher_z64(rho) <= tau ? 1 : 0;
+        }
+        const float fh11 = (float)h11, fh22 = (float)h22;
+        const float floor_ = 2.0f * band * g2;
+        if (!ok || fh11 <= floor_ || fh22 <= floor_) return 2;
+        const float inv = rsqrtf(fh11 * fh22);
+        const float ar = fabsf((float)h12 * inv);
+        const float err = band * g2 * (inv + 0.5f * ar * (1.0f / fh11 + 1.0f / fh22));
+        return ar <= tl - err ? 1 : (ar > tl + err ? 0 : 2);
+    }
+};
+
+}  // namespace pcg

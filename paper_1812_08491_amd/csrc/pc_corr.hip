@@ -5,7 +5,8 @@
 // 64 x 64 output tile while it is still in registers, and the tile's adjacency bits are packed
 // into the bit matrix, so no separate level-0 kernel or n x n adjacency pass exists.
 //
-// Only upper-triangle tiles are computed (C is symmetric); each writes its tile and the mirror.
+// Only upper-triangle tiles are launched (C is symmetric); each writes its tile and the mirror.
+// One launch serves a whole batch: blocks map to (problem, tile) through the tile offsets.
 // Precision paths:
 //   FP64   : v_mfma_f64_16x16x4f64, exact FP64 decision |atanh(c)| <= tau_0.
 //   FP32   : v_mfma_f32_16x16x4f32 on the FP32 copy of Z.
@@ -66,13 +67,21 @@ template <> struct Smem<PC_PREC_BF16X3> {
     uint16_t Ahi[kT][40], Alo[kT][40], Bhi[kT][40], Blo[kT][40];
 };
 
+// Operands of one problem, copied to registers once (a Prob lives in global memory, and every
+// barrier would otherwise force its fields to be reloaded).
+struct Operands {
+    int64_t n, mp;
+    const double *zt64;
+    const void *zlo, *zhi;
+};
+
 template <int PREC>
-__device__ inline void load_tiles(Smem<PREC> &sm, const CorrArgs &a, int64_t a0, int64_t b0,
+__device__ inline void load_tiles(Smem<PREC> &sm, const Operands &a, int64_t a0, int64_t b0,
                                   int64_t k0, int tid) {
     const int row = tid >> 2;
     if constexpr (PREC == PC_PREC_FP32) {
         const int kq = (tid & 3) * 4;
-        const float *z = static_cast<const float *>(a.za);
+        const float *z = static_cast<const float *>(a.zlo);
         float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
         if (a0 + row < a.n) va = *reinterpret_cast<const float4 *>(z + (a0 + row) * a.mp + k0 + kq);
         if (b0 + row < a.n) vb = *reinterpret_cast<const float4 *>(z + (b0 + row) * a.mp + k0 + kq);
@@ -100,8 +109,8 @@ __device__ inline void load_tiles(Smem<PREC> &sm, const CorrArgs &a, int64_t a0,
         sm.B[kq + 2][row] = vb1.x; sm.B[kq + 3][row] = vb1.y;
     } else {
         const int k8 = (tid & 3) * 8;
-        const uint16_t *zh = static_cast<const uint16_t *>(a.za);
-        const uint16_t *zl = static_cast<const uint16_t *>(a.zb);
+        const uint16_t *zh = static_cast<const uint16_t *>(a.zhi);
+        const uint16_t *zl = static_cast<const uint16_t *>(a.zlo);
         uint4 ah = make_uint4(0, 0, 0, 0), al = ah, bh = ah, bl = ah;
         if (a0 + row < a.n) {
             ah = *reinterpret_cast<const uint4 *>(zh + (a0 + row) * a.mp + k0 + k8);
@@ -173,12 +182,26 @@ __device__ inline void mma_step(const Smem<PREC> &sm, typename Tr<PREC>::acc_t (
 }
 
 template <int PREC>
-__global__ __launch_bounds__(256) void k_corr(CorrArgs a) {
+__global__ __launch_bounds__(256) void k_corr(Batch bt) {
     using T = typename Tr<PREC>::T;
     using acc_t = typename Tr<PREC>::acc_t;
     constexpr int BK = Tr<PREC>::BK;
-    const int tj = blockIdx.x, ti = blockIdx.y;
-    if (ti > tj) return;
+    const int d = find_base(bt.tile_base, bt.count, blockIdx.x);
+    const Prob &Pg = bt.probs[d];
+    struct {
+        int64_t n, m, mp, W;
+        double *zt64;
+        void *C;
+        unsigned long long *adj;
+        double t0, eps_c;
+    } a = {Pg.n, Pg.m, Pg.mp, Pg.W, Pg.zt64, Pg.C, Pg.adj, Pg.t0, Pg.eps_c};
+    const Operands ops = {Pg.n, Pg.mp, Pg.zt64, Pg.zlo, Pg.zhi};
+    const double tau0 = Pg.tau[0];
+    // Upper-triangle tile (ti <= tj) number k of this problem, rows of tiles taken in order.
+    const int ntiles = (int)((a.n + kT - 1) / kT);
+    int ti = 0, k = (int)(blockIdx.x - bt.tile_base[d]);
+    while (k >= ntiles - ti) { k -= ntiles - ti; ++ti; }
+    const int tj = ti + k;
     const int64_t a0 = (int64_t)ti * kT, b0 = (int64_t)tj * kT;
     const bool diag = ti == tj;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -201,7 +224,7 @@ __global__ __launch_bounds__(256) void k_corr(CorrArgs a) {
             for (int v = 0; v < 4; ++v) acc[mi][nj][v] = 0;
 
     for (int64_t k0 = 0; k0 < a.mp; k0 += BK) {
-        load_tiles<PREC>(sm, a, a0, b0, k0, tid);
+        load_tiles<PREC>(sm, ops, a0, b0, k0, tid);
         __syncthreads();
         mma_step<PREC>(sm, acc, lane, wr, wc);
         __syncthreads();
@@ -236,12 +259,12 @@ __global__ __launch_bounds__(256) void k_corr(CorrArgs a) {
                 C[b * a.n + ar] = val;
                 bool keep, border = false;
                 if constexpr (PREC == PC_PREC_FP64) {
-                    keep = !(fisher_z((double)val) <= a.tau0);
+                    keep = !(fisher_z((double)val) <= tau0);
                 } else {
                     double x = fabs((double)val);
                     keep = x > a.t0 + a.eps_c;
                     border = !keep && x >= a.t0 - a.eps_c;
-                    if (a.force_recheck) border = true;
+                    if (bt.force_recheck) border = true;
                 }
                 if (border) {
                     int k = atomicAdd(&bcount, 1);
@@ -269,7 +292,7 @@ __global__ __launch_bounds__(256) void k_corr(CorrArgs a) {
             for (int64_t r = lane; r < a.m; r += 64) s += za[r] * zb[r];
             s = wave_sum(s);
             if (lane == 0) {
-                const bool keep = !(fisher_z(s) <= a.tau0);
+                const bool keep = !(fisher_z(s) <= tau0);
                 if (keep) {
                     atomicOr(&rowbits[al], 1ull << bl);
                     atomicOr(&colbits[bl], 1ull << al);
@@ -291,21 +314,21 @@ __global__ __launch_bounds__(256) void k_corr(CorrArgs a) {
         if (r < a.n) a.adj[r * W + ti] = colbits[tid - kT];
     }
     if (tid == 0) {
-        if (wg_removed) add_ll(&a.st->removed[0], (long long)wg_removed);
-        if (wg_rechecks) add_ll(&a.st->rechecks[0], (long long)wg_rechecks);
-        if (ti == 0 && tj == 0) a.st->tests[0] = (long long)(a.n * (a.n - 1) / 2);
+        Prob &pw = bt.probs[d];
+        if (wg_removed) add_ll(&pw.removed[0], (long long)wg_removed);
+        if (wg_rechecks) add_ll(&pw.rechecks[0], (long long)wg_rechecks);
+        if (ti == 0 && tj == 0) pw.tests[0] = (long long)(a.n * (a.n - 1) / 2);
     }
 }
 
-hipError_t launch_corr(hipStream_t s, const CorrArgs &a, int prec) {
-    const unsigned T = (unsigned)((a.n + kT - 1) / kT);
-    dim3 grid(T, T);
-    if (prec == PC_PREC_FP64)
-        hipLaunchKernelGGL(k_corr<PC_PREC_FP64>, grid, dim3(256), 0, s, a);
-    else if (prec == PC_PREC_FP32)
-        hipLaunchKernelGGL(k_corr<PC_PREC_FP32>, grid, dim3(256), 0, s, a);
+hipError_t launch_corr(hipStream_t s, const Batch &b, long long tiles) {
+    const dim3 grid((unsigned)tiles);
+    if (b.prec == PC_PREC_FP64)
+        hipLaunchKernelGGL(k_corr<PC_PREC_FP64>, grid, dim3(256), 0, s, b);
+    else if (b.prec == PC_PREC_FP32)
+        hipLaunchKernelGGL(k_corr<PC_PREC_FP32>, grid, dim3(256), 0, s, b);
     else
-        hipLaunchKernelGGL(k_corr<PC_PREC_BF16X3>, grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_corr<PC_PREC_BF16X3>, grid, dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

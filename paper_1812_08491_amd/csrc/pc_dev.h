@@ -1,4 +1,8 @@
 // Library-internal declarations shared by the HIP translation units of libpc.so.
+//
+// Every kernel works on a batch of independent problems (datasets) described by a device table of
+// Prob records; a single-problem call is a batch of one. Work of all problems is flattened into
+// one index space per kernel (columns, tiles, rows, work items), so one launch serves the batch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,155 +13,134 @@
 
 namespace pcg {
 
-// Device-resident run state: the work queue of the current level, the stop flag that replaces the
-// host-side max-degree test of Algorithm 2, and per-level counters.
-struct DevState {
-    unsigned long long total_items;  // work items planned for the current level
-    unsigned long long next_item;    // queue head (atomic)
-    unsigned long long total_sets;   // sum over rows of C(d_i, l)
-    int max_deg;                     // max degree of G' found by the last compaction
-    int done;                        // 1 once a compaction found no row with d_i >= l + 1
-    unsigned int blocks_done;        // finished-block counter of the compaction kernel
-    int err;                         // device-detected input error (pc_status), 0 = none
-    int deg_work;                    // atomicMax scratch of the compaction kernel
-    int overflow;                    // a row's subset count exceeded the supported range
-    int rq_overflow;                 // the re-check queue filled up
-    int pad;
-    unsigned long long rq_count;     // entries pushed to the re-check queue this level
-    long long tests[PC_MAX_LEVEL + 2];
-    long long removed[PC_MAX_LEVEL + 2];
-    long long rechecks[PC_MAX_LEVEL + 2];
-    long long items[PC_MAX_LEVEL + 2];
-    long long audit_viol[PC_MAX_LEVEL + 2];  // audit mode: FP32 decisions outside the band that
-                                             // disagree with FP64
-    int maxdeg[PC_MAX_LEVEL + 2];
-};
+constexpr int kLevels = PC_MAX_LEVEL + 2;             // per-level arrays: levels 0 .. PC_MAX_LEVEL+1
+constexpr int kBinomCols = PC_MAX_LEVEL + 2;          // C(a, b) for b = 0 .. PC_MAX_LEVEL + 1
+constexpr unsigned long long kSat = 1ull << 62;       // saturation value of the binomial table
+constexpr int kLevelThreads = 256;                    // threads of a level work-group
+constexpr int kGramLd = PC_MAX_LEVEL + 2;             // leading dimension of an FP64 Gram block
 
 // 64-bit signed counter add (two's complement, so the unsigned atomic is exact).
 __device__ inline void add_ll(long long *p, long long v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
 }
 
-constexpr int kBinomCols = PC_MAX_LEVEL + 2;          // C(a, b) for b = 0 .. PC_MAX_LEVEL + 1
-constexpr unsigned long long kSat = 1ull << 62;       // saturation value of the binomial table
-constexpr int kLevelThreads = 256;                    // threads of a level work-group
-constexpr int kGramLd = PC_MAX_LEVEL + 2;             // leading dimension of a per-wave FP64 Gram
+// One problem of a batch: shapes, buffers (device pointers), thresholds and statistics.
+struct Prob {
+    int64_t n, m, mp, W;
+    const double *X;               // m x n FP64 row-major input
+    double *mu, *inv;              // column mean and 1 / ||X - mu||
+    double *zt64;                  // n x mp FP64 standardized data (variable-major)
+    void *zlo, *zhi;               // low-precision GEMM operands
+    void *C;                       // n x n correlation (FP64 or FP32)
+    unsigned long long *adj;       // live G (bit matrix)
+    int *nbr, *deg;                // compacted G' (row i at nbr + i*n), degrees
+    pc_sep_rec *recs;
+    long long rec_cap;
+    long long *rec_count;
+    int max_level;                 // last level to run (PC_MAX_LEVEL + 1: until the stop rule)
+    int err;                       // device-detected input error (pc_status)
+    double t0, eps_c;              // level 0: tanh(tau_0) and the C error bound (low precision)
+    double tau[kLevels];           // tau_l; NaN when m - l - 3 <= 0
+    float t[kLevels];              // tanh(tau_l) in FP32
+    float band[kLevels];           // FP32 error band scale of level l
+    long long tests[kLevels], removed[kLevels], rechecks[kLevels], items[kLevels];
+    long long audit_viol[kLevels];
+    long long probe_tests[kLevels], probe_removed[kLevels];
+    int maxdeg[kLevels];
+};
+
+// Device-resident queue state of the current level (one per batch).
+struct DevState {
+    unsigned long long total_items;  // work items planned for the current level
+    unsigned long long next_item;    // queue head (atomic)
+    unsigned long long rq_count;     // entries pushed to the re-check queue this level
+    int done;                        // 1 once a planning pass found no work in any problem
+    int overflow;                    // a row's subset count exceeded the supported range
+    int rq_overflow;                 // the re-check queue filled up
+    int pad[3];
+};
+
+// Re-check queue entry: a test whose FP32 decision fell in the error band (or, on the FP64 path,
+// whose M2 is rank deficient).
+struct RqEntry {
+    int prob, i, j, cls;           // cls: FP32 class (0 dependent, 1 independent, 2 in the band)
+    int S[PC_MAX_LEVEL];
+    int pad[3];
+};
+
+// Flattened index tables and shared buffers of a batch (passed by value to every kernel).
+struct Batch {
+    Prob *probs;
+    int count;
+    int prec;
+    int force_recheck;
+    int pad;
+    const long long *row_base;     // count + 1: first flattened row of each problem
+    const long long *cs_base;      // count + 1: first k_colstats block
+    const long long *st_base;      // count + 1: first k_standardize block
+    const long long *tile_base;    // count + 1: first k_corr tile
+    long long *nitems;             // per flattened row: work items of the level
+    long long *item_off;           // total_rows + 1 exclusive offsets
+    const unsigned long long *binom;
+    DevState *st;
+    RqEntry *rq;
+    long long rq_cap;
+    long long total_rows;
+};
+
+// Largest k in [0, count) with base[k] <= x (base ascending, base[0] = 0).
+__device__ inline int find_base(const long long *base, int count, long long x) {
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
 
 inline int64_t pad_m(int64_t m) { return (m + 63) / 64 * 64; }
 inline int64_t words_per_row(int64_t n) { return (n + 63) / 64; }
 inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Workspace layout (byte offsets from the workspace base).
-struct Layout {
-    int64_t n, m, mp;
-    int prec;
-    size_t state, mu, inv, zt64, zlo, zhi, c, adj, nbr, deg, nitems, item_off, binom, rq, total;
-    int64_t rq_cap;
-
-    static Layout make(int64_t n, int64_t m, int prec, int64_t rq_cap) {
-        Layout L{};
-        L.n = n;
-        L.m = m;
-        L.mp = pad_m(m);
-        L.prec = prec;
-        size_t o = 0;
-        auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
-        L.state = take(sizeof(DevState));
-        L.mu = take(sizeof(double) * n);
-        L.inv = take(sizeof(double) * n);
-        L.zt64 = take(sizeof(double) * n * L.mp);
-        // FP32 mode: zlo holds the FP32 copy; BF16x3 mode: zhi and zlo hold the two BF16 halves.
-        size_t low_bytes = prec == PC_PREC_FP32 ? sizeof(float) * n * L.mp
-                         : prec == PC_PREC_BF16X3 ? sizeof(uint16_t) * n * L.mp : 0;
-        L.zlo = take(low_bytes);
-        L.zhi = take(prec == PC_PREC_BF16X3 ? sizeof(uint16_t) * n * L.mp : 0);
-        L.c = take((prec == PC_PREC_FP64 ? sizeof(double) : sizeof(float)) * n * n);
-        L.adj = take(sizeof(unsigned long long) * n * words_per_row(n));
-        L.nbr = take(sizeof(int32_t) * n * n);
-        L.deg = take(sizeof(int32_t) * n);
-        L.nitems = take(sizeof(long long) * n);
-        L.item_off = take(sizeof(long long) * (n + 1));
-        L.binom = take(sizeof(unsigned long long) * (n + 1) * kBinomCols);
-        L.rq_cap = rq_cap;
-        L.rq = take(sizeof(pc_sep_rec) * rq_cap);
-        L.total = o;
-        return L;
-    }
-};
+constexpr int kCsCols = 16;        // columns per k_colstats block
+inline int64_t cs_blocks(int64_t n) { return (n + kCsCols - 1) / kCsCols; }
+inline int64_t st_blocks(int64_t n, int64_t mp) { return ((n + 63) / 64) * (mp / 64); }
+inline int64_t corr_tiles(int64_t n) { const int64_t T = (n + 63) / 64; return T * (T + 1) / 2; }
 
 // ---- launchers (each translation unit launches only its own kernels) ----
 
 // pc_prep.hip
-hipError_t launch_init(hipStream_t s, DevState *st, unsigned long long *binom, int64_t n,
-                       long long *zero_me);
-hipError_t launch_rearm(hipStream_t s, DevState *st);
-hipError_t launch_colstats(hipStream_t s, const double *X, int64_t m, int64_t n, double *mu,
-                           double *inv, DevState *st);
-hipError_t launch_standardize(hipStream_t s, const double *X, int64_t m, int64_t n, int64_t mp,
-                              const double *mu, const double *inv, double *zt64, void *zlo,
-                              void *zhi, int prec);
+hipError_t launch_binom(hipStream_t s, unsigned long long *binom, int64_t rows);
+hipError_t launch_init(hipStream_t s, const Batch &b);
+hipError_t launch_rearm(hipStream_t s, const Batch &b);
+hipError_t launch_colstats(hipStream_t s, const Batch &b, long long blocks);
+hipError_t launch_standardize(hipStream_t s, const Batch &b, long long blocks);
 
 // pc_corr.hip
-struct CorrArgs {
-    const double *zt64;
-    const void *za;        // FP32 copy (FP32 mode) or BF16 high half (BF16x3 mode)
-    const void *zb;        // BF16 low half (BF16x3 mode)
-    void *C;               // n x n, FP64 or FP32
-    unsigned long long *adj;
-    DevState *st;
-    int64_t n, m, mp, W;
-    double tau0;           // level-0 threshold on the Fisher z
-    double t0;             // tanh(tau0): threshold on |r|
-    double eps_c;          // bound on |C_low - C_fp64| for the FP32 / BF16x3 paths
-    int force_recheck;
-};
-hipError_t launch_corr(hipStream_t s, const CorrArgs &a, int prec);
+hipError_t launch_corr(hipStream_t s, const Batch &b, long long tiles);
 
 // pc_level.hip
-struct LevelArgs {
-    const void *C;                 // n x n FP32 or FP64
-    const double *zt64;            // n x mp FP64 standardized data (FP32 paths' re-checks)
-    unsigned long long *adj;       // live G (bit matrix)
-    const int *nbr;                // compacted G': row i at nbr + i*n
-    const int *deg;
-    const long long *item_off;     // n + 1 exclusive offsets of work items per row
-    const unsigned long long *binom;
-    DevState *st;
-    pc_sep_rec *recs;
-    long long *rec_count;
-    long long rec_cap;
-    int64_t n, m, mp, W;
-    int level;
-    int ranks_per_item;            // conditioning sets per work item
-    int lds_bytes;                 // dynamic LDS per work-group
-    int force_recheck;
-    double tau;                    // level threshold on the Fisher z (FP64 decisions)
-    float t;                       // tanh(tau) (FP32 decisions)
-    float band;                    // margin_scale * (eps_c + rounding) for the FP32 band
-    pc_sep_rec *rq;                // re-check queue (level field = FP32 class: 0 dep, 1 indep,
-                                   // 2 in the band)
-    long long rq_cap;
-};
-struct RecheckArgs {
-    const double *zt64;            // FP64 standardized data (NULL: take the block from C64)
-    const double *C64;             // FP64 correlation (FP64 precision path)
-    unsigned long long *adj;
-    DevState *st;
-    const pc_sep_rec *rq;
-    long long rq_cap;
-    pc_sep_rec *recs;
-    long long *rec_count;
-    long long rec_cap;
-    int64_t n, m, mp, W;
-    int level;
-    int audit;                     // compare FP32 classes with FP64 decisions
-    double tau;
-};
-hipError_t launch_recheck(hipStream_t s, const RecheckArgs &a, int grid);
+hipError_t launch_compact(hipStream_t s, const Batch &b, int level, int ranks_per_item);
+hipError_t launch_plan(hipStream_t s, const Batch &b, int level);
+hipError_t launch_level(hipStream_t s, const Batch &b, int level, int ranks_per_item, int lds_bytes,
+                        int grid);
+hipError_t launch_recheck(hipStream_t s, const Batch &b, int level, int grid);
 size_t level_lds_fixed(int prec);
-hipError_t launch_compact(hipStream_t s, const unsigned long long *adj, int64_t n, int64_t W,
-                          int level, int ranks_per_item, int *nbr, int *deg, long long *nitems,
-                          long long *item_off, const unsigned long long *binom, DevState *st);
-hipError_t launch_level(hipStream_t s, const LevelArgs &a, int prec, int grid);
+
+// pc_mlp.hip
+hipError_t launch_mlp_forward(hipStream_t s, const float *params, const float *X, long long rows,
+                              const long long *rows_dev, long long rows_cap, float *scores, float *act,
+                              const int *skip, int grid);
+hipError_t launch_mlp_backward(hipStream_t s, const float *params, const float *X, long long rows,
+                               const float *act, const float *dscore, float *partial, float *grads);
+hipError_t launch_bce(hipStream_t s, const float *scores, const float *labels, long long rows, float pos_weight,
+                      float *dscore, double *loss);
+hipError_t launch_adam(hipStream_t s, float *params, const float *grads, float *m1, float *m2, int step, float lr,
+                       float beta1, float beta2, float eps);
+hipError_t launch_feat_plan(hipStream_t s, const Batch &b, long long *foff, long long cap, int *skip);
+hipError_t launch_features(hipStream_t s, const Batch &b, int level, const long long *foff, float *feats,
+                           int *meta, const int *skip);
+hipError_t launch_probe(hipStream_t s, const Batch &b, int level, const long long *foff, const float *scores,
+                        int topq, const int *skip);
 
 }  // namespace pcg

@@ -1,27 +1,28 @@
-// Levels l >= 1 of PC-stable (Algorithm 1, Sec. 2.4) on gfx950.
+// Levels l >= 1 of PC-stable (Algorithm 1, Sec. 2.4) on gfx950, for a batch of problems.
 //
 // k_compact: the snapshot G' := G as compacted neighbour lists (the A'_G of Sec. 3.3 / Fig. 2):
 //   one wavefront per row turns the row's bit words into ascending neighbour ids with popcount and
-//   a wave prefix sum, then the last work-group to finish scans the per-row work counts into the
-//   work plan of the level. A level with no row of degree >= l + 1 sets the device stop flag: that
-//   is the max-degree test of Algorithm 2 kept on the device.
-//
+//   a wave prefix sum, and counts the row's work items (C(d_i, l) conditioning sets, cut into
+//   items of a fixed number of ranks; none when d_i < l + 1, Sec. 4.1).
+// k_plan: one work-group scans the per-row item counts into the level's work queue. A level with
+//   no work in any problem sets the device stop flag: the max-degree test of Algorithm 2, kept on
+//   the device so that no host round trip is needed between levels.
 // k_level<T, L>: the CI tests of level L. A work item is a row i with a range of ranks of its
 //   l-subsets S of adj(i, G') (the set-sharing view of cuPC-S, Sec. 3.4): for each S the
 //   Cholesky factor of M2 = C[S,S] (Eq. 3) is formed once and serves every j in adj(i,G') \ S, so
-//   the per-j work is one triangular solve. The row's neighbour list, C[i, N_i] and (for l >= 2)
-//   the block C[N_i, N_i] are staged in LDS once per item. Items come from a device-side queue
-//   that a fixed grid of work-groups drains (persistent kernel), absorbing the very uneven
-//   per-row subset counts C(d_i, l).
+//   the per-j work is one triangular solve. The row's neighbour list, C[i, N_i], its live bits and
+//   (when it fits) the block C[N_i, N_i] are staged in LDS once per item. Items come from a
+//   device-side queue that a fixed grid of work-groups drains (persistent kernel), absorbing the
+//   very uneven per-row subset counts.
 //   Every test first checks that edge (i,j) is still in G (early termination, Sec. 4.1). The first
 //   independent test clears the edge with an atomic AND on the bit (min, max); only the thread
 //   whose AND cleared it writes the SepSet record, so each removed edge has exactly one record.
 //   FP32 tests whose |rho| lies within an error band of tanh(tau_l) (and FP64 tests whose M2 is
 //   rank deficient) go to a re-check queue.
-//
 // k_recheck: one wavefront per queued test re-evaluates it in FP64 (the block of C recomputed as
 //   dot products of the FP64 standardized columns, or read from the FP64 C), with a
 //   pseudo-inverse when M2 is rank deficient, and removes the edge if that decides independence.
+#include "pc_citest.h"
 #include "pc_comb.h"
 #include "pc_dev.h"
 
@@ -33,17 +34,9 @@ __device__ inline double wave_sum64(double v) {
     return v;
 }
 
-__device__ inline double fisher_z64(double r) {
-    if (!(fabs(r) < 1.0)) return INFINITY;
-    return fabs(0.5 * log((1.0 + r) / (1.0 - r)));
-}
-
-__device__ inline unsigned long long live_word(unsigned long long *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline long long load_ll(const long long *p) {
-    return __hip_atomic_load(const_cast<long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Whether level l runs for problem P (the level cap, Eq. 6 needing m - l - 3 > 0).
+__device__ inline bool level_enabled(const Prob &P, int l) {
+    return l <= P.max_level && l <= PC_MAX_LEVEL && P.tau[l] == P.tau[l];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -51,108 +44,122 @@ __device__ inline long long load_ll(const long long *p) {
 // ---------------------------------------------------------------------------------------------
 constexpr unsigned long long kMaxSetsPerRow = 1ull << 40;
 
-__global__ __launch_bounds__(256) void k_compact(const unsigned long long *__restrict__ adj,
-                                                 int64_t n, int64_t W, int level, int R,
-                                                 int *__restrict__ nbr, int *__restrict__ deg,
-                                                 long long *nitems, long long *item_off,
-                                                 const unsigned long long *__restrict__ binom,
-                                                 DevState *st) {
-    __shared__ int is_last;
-    __shared__ long long part[256];
-    if (st->done) return;
+__global__ __launch_bounds__(256) void k_compact(Batch b, int level, int R) {
+    if (b.st->done) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t i = (int64_t)blockIdx.x * 4 + wave;
-    if (i < n) {
-        const unsigned long long *row = adj + i * W;
-        int *out = nbr + i * n;
-        int count = 0;
-        for (int64_t w0 = 0; w0 < W; w0 += 64) {
-            const int64_t w = w0 + lane;
-            unsigned long long word = w < W ? row[w] : 0ull;
-            // A caller-supplied G may carry stray bits: drop the diagonal and columns >= n.
-            if (w == (i >> 6)) word &= ~(1ull << (i & 63));
-            if (w == W - 1 && (n & 63)) word &= (1ull << (n & 63)) - 1ull;
-            const int pc = __popcll(word);
-            int incl = pc;
+    const long long grow = (long long)blockIdx.x * 4 + wave;
+    if (grow >= b.total_rows) return;
+    const int d = find_base(b.row_base, b.count, grow);
+    Prob &P = b.probs[d];
+    const int64_t n = P.n, W = P.W, i = grow - b.row_base[d];
+    const unsigned long long *row = P.adj + i * W;
+    int *out = P.nbr + i * n;
+    int count = 0;
+    for (int64_t w0 = 0; w0 < W; w0 += 64) {
+        const int64_t w = w0 + lane;
+        unsigned long long word = w < W ? row[w] : 0ull;
+        // A caller-supplied G may carry stray bits: drop the diagonal and columns >= n.
+        if (w == (i >> 6)) word &= ~(1ull << (i & 63));
+        if (w == W - 1 && (n & 63)) word &= (1ull << (n & 63)) - 1ull;
+        const int pc = __popcll(word);
+        int incl = pc;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                int t = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += t;
-            }
-            const int tot = __shfl(incl, 63, 64);
-            int pos = count + incl - pc;
-            while (word) {
-                const int b = __ffsll((long long)word) - 1;
-                out[pos++] = (int)(w * 64 + b);
-                word &= word - 1;
-            }
-            count += tot;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
         }
-        if (lane == 0) {
-            deg[i] = count;
-            atomicMax(&st->deg_work, count);
-            long long items = 0;
-            if (count >= level + 1) {
-                const unsigned long long nS = binom[(int64_t)count * kBinomCols + level];
-                if (nS > kMaxSetsPerRow) {
-                    atomicOr(&st->overflow, 1);
-                } else {
-                    items = (long long)((nS + (unsigned long long)R - 1) / (unsigned long long)R);
-                }
-            }
-            nitems[i] = items;
+        const int tot = __shfl(incl, 63, 64);
+        int pos = count + incl - pc;
+        while (word) {
+            const int bit = __ffsll((long long)word) - 1;
+            out[pos++] = (int)(w * 64 + bit);
+            word &= word - 1;
         }
+        count += tot;
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) is_last = atomicAdd(&st->blocks_done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    const int64_t chunk = (n + 255) / 256;
-    const int64_t lo = tid * chunk, hi = lo + chunk < n ? lo + chunk : n;
-    long long s = 0;
-    for (int64_t k = lo; k < hi; ++k) s += load_ll(nitems + k);
-    part[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-        long long run = 0;
-        for (int k = 0; k < 256; ++k) {
-            long long v = part[k];
-            part[k] = run;
-            run += v;
+    if (lane == 0) {
+        P.deg[i] = count;
+        long long items = 0;
+        if (count >= level + 1 && level_enabled(P, level)) {
+            const unsigned long long nS = b.binom[(int64_t)count * kBinomCols + level];
+            if (nS > kMaxSetsPerRow) {
+                atomicOr(&b.st->overflow, 1);
+            } else {
+                items = (long long)((nS + (unsigned long long)R - 1) / (unsigned long long)R);
+            }
         }
-        item_off[n] = run;
-        const int md = __hip_atomic_load(&st->deg_work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        st->max_deg = md;
-        st->maxdeg[level] = md;
-        st->total_items = (unsigned long long)run;
-        st->items[level] = run;
-        st->next_item = 0ull;
-        st->rq_count = 0ull;
-        st->deg_work = 0;
-        st->blocks_done = 0u;
-        if (run == 0) st->done = 1;
-    }
-    __syncthreads();
-    long long run = part[tid];
-    for (int64_t k = lo; k < hi; ++k) {
-        item_off[k] = run;
-        run += load_ll(nitems + k);
+        b.nitems[grow] = items;
     }
 }
 
-hipError_t launch_compact(hipStream_t s, const unsigned long long *adj, int64_t n, int64_t W,
-                          int level, int ranks_per_item, int *nbr, int *deg, long long *nitems,
-                          long long *item_off, const unsigned long long *binom, DevState *st) {
-    dim3 grid((unsigned)((n + 3) / 4));
-    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, adj, n, W, level, ranks_per_item, nbr,
-                       deg, nitems, item_off, binom, st);
+hipError_t launch_compact(hipStream_t s, const Batch &b, int level, int ranks_per_item) {
+    const dim3 grid((unsigned)((b.total_rows + 3) / 4));
+    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, b, level, ranks_per_item);
+    return hipGetLastError();
+}
+
+constexpr int kPlanThreads = 1024;
+
+__global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level) {
+    __shared__ long long part[kPlanThreads];
+    DevState *st = b.st;
+    if (st->done) return;
+    const int tid = threadIdx.x;
+    const long long N = b.total_rows;
+    const long long chunk = (N + kPlanThreads - 1) / kPlanThreads;
+    const long long lo = tid * chunk, hi = lo + chunk < N ? lo + chunk : N;
+    long long s = 0;
+    for (long long k = lo; k < hi; ++k) s += b.nitems[k];
+    part[tid] = s;
+    __syncthreads();
+    // Exclusive scan of the per-thread sums (Hillis-Steele in LDS).
+    for (int o = 1; o < kPlanThreads; o <<= 1) {
+        const long long v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    long long run = part[tid] - s;
+    for (long long k = lo; k < hi; ++k) {
+        b.item_off[k] = run;
+        run += b.nitems[k];
+    }
+    const long long total = part[kPlanThreads - 1];
+    if (tid == 0) {
+        b.item_off[N] = total;
+        st->total_items = (unsigned long long)total;
+        st->next_item = 0ull;
+        st->rq_count = 0ull;
+        if (total == 0) st->done = 1;
+    }
+    __syncthreads();
+    for (int d = tid; d < b.count; d += kPlanThreads)
+        b.probs[d].items[level] = b.item_off[b.row_base[d + 1]] - b.item_off[b.row_base[d]];
+    // Max degree of G' per problem (what the stop rule of Algorithm 1 looks at), from the chunk of
+    // rows each thread scanned: one atomic per (thread, problem) segment.
+    if (lo < hi) {
+        int d = find_base(b.row_base, b.count, lo);
+        int best = 0;
+        for (long long k = lo; k < hi; ++k) {
+            while (k >= b.row_base[d + 1]) {
+                atomicMax(&b.probs[d].maxdeg[level], best);
+                best = 0;
+                ++d;
+            }
+            const int dg = b.probs[d].deg[k - b.row_base[d]];
+            best = dg > best ? dg : best;
+        }
+        atomicMax(&b.probs[d].maxdeg[level], best);
+    }
+}
+
+hipError_t launch_plan(hipStream_t s, const Batch &b, int level) {
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, b, level);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------------
-// FP64 decision from a Gram block (used by the re-check and by rank-deficient FP64 tests)
+// FP64 decision from a Gram block (used by the re-check)
 // ---------------------------------------------------------------------------------------------
 
 // Per-wave FP64 scratch of the re-check path, kept in LDS (runtime-sized small matrices).
@@ -270,20 +277,11 @@ __device__ int decide_gram64(const double *G, int ld, int l, double tau, double 
     return fisher_z64(rho) <= tau ? 1 : 0;
 }
 
-// Clears edge (lo, hi) from G. Returns true for the one caller whose atomic AND on the canonical
-// bit (row lo, column hi) found it set: that caller owns the SepSet record.
-__device__ inline bool take_edge(unsigned long long *adj, int64_t W, int lo, int hi) {
-    const unsigned long long bit = 1ull << (hi & 63);
-    const unsigned long long old = atomicAnd(adj + (int64_t)lo * W + (hi >> 6), ~bit);
-    if (!(old & bit)) return false;
-    atomicAnd(adj + (int64_t)hi * W + (lo >> 6), ~(1ull << (lo & 63)));
-    return true;
-}
-
 // ---------------------------------------------------------------------------------------------
 // Level kernel
 // ---------------------------------------------------------------------------------------------
-constexpr int kDcap = 1024;  // neighbour lists up to this degree are staged in LDS
+constexpr int kDcap = 1024;   // neighbour lists up to this degree are staged in LDS
+constexpr int kWcap = 256;    // live-bit words of a row staged in LDS (n <= 16384)
 
 struct TableBinom {
     const unsigned long long *t;
@@ -295,102 +293,128 @@ struct TableBinom {
 
 template <typename T>
 __host__ __device__ constexpr size_t lds_fixed_bytes() {
-    return (sizeof(int) * kDcap + 15) / 16 * 16 + (sizeof(T) * kDcap + 15) / 16 * 16;
-}
-
-// Pushes a test to the re-check queue; cls is the FP32 classification (0 dependent, 1 independent,
-// 2 inside the band).
-template <int L>
-__device__ inline void push_recheck(const LevelArgs &a, int row, int j, const int (&sid)[L], int cls) {
-    const unsigned long long k = atomicAdd(&a.st->rq_count, 1ull);
-    if (k >= (unsigned long long)a.rq_cap) {
-        atomicOr(&a.st->rq_overflow, 1);
-        return;
-    }
-    pc_sep_rec *e = a.rq + k;
-    e->i = row;
-    e->j = j;
-    e->level = cls;
-#pragma unroll
-    for (int c = 0; c < PC_MAX_LEVEL; ++c) e->S[c] = c < L ? sid[c] : -1;
+    return (sizeof(int) * kDcap + 15) / 16 * 16 + (sizeof(T) * kDcap + 15) / 16 * 16 +
+           sizeof(unsigned long long) * kWcap;
 }
 
 template <typename T, int L>
-__global__ __launch_bounds__(kLevelThreads) void k_level(LevelArgs a) {
+__global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds_bytes) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_row;
-    __shared__ long long s_r0;
-    __shared__ int s_mode;  // bit 0: nb/ci in LDS, bit 1: C[N_i,N_i] in LDS
+    __shared__ long long s_grow, s_r0;
+    __shared__ int s_mode;  // bit 0: nb/ci in LDS, bit 1: C[N_i,N_i] in LDS, bit 2: live bits in LDS
     __shared__ long long s_tests, s_removed;
 
-    DevState *st = a.st;
+    DevState *st = b.st;
     if (st->done) return;
     const unsigned long long total = st->total_items;
     const int tid = threadIdx.x;
     int *lds_nb = reinterpret_cast<int *>(smem);
     T *lds_ci = reinterpret_cast<T *>(smem + (sizeof(int) * kDcap + 15) / 16 * 16);
+    unsigned long long *lds_live = reinterpret_cast<unsigned long long *>(
+        smem + (sizeof(int) * kDcap + 15) / 16 * 16 + (sizeof(T) * kDcap + 15) / 16 * 16);
     T *lds_blk = reinterpret_cast<T *>(smem + lds_fixed_bytes<T>());
-    const long long blk_cap = ((long long)a.lds_bytes - (long long)lds_fixed_bytes<T>()) / (long long)sizeof(T);
-    const T *C = static_cast<const T *>(a.C);
-    const TableBinom binom{a.binom};
-    const int64_t n = a.n, W = a.W;
+    const long long blk_cap = ((long long)lds_bytes - (long long)lds_fixed_bytes<T>()) / (long long)sizeof(T);
+    const TableBinom binom{b.binom};
 
     if (tid == 0) { s_tests = 0; s_removed = 0; }
-    int staged = -1, last_row = 0, d = 0;
+    long long staged = -1, last_row = 0;
+    int d = 0;
     long long my_tests = 0, my_removed = 0;
 
     for (;;) {
         __syncthreads();
-        if (tid == 0) {
-            const unsigned long long g = atomicAdd(&st->next_item, 1ull);
+        if (tid < 64) {
+            // Wave 0 pops the next item and finds its row: the largest r with item_off[r] <= g,
+            // by 64-way probing (each round narrows the range 64-fold with one load per lane).
+            unsigned long long g = 0;
+            if (tid == 0) g = atomicAdd(&st->next_item, 1ull);
+            g = __shfl(g, 0, 64);
             if (g >= total) {
-                s_row = -1;
+                if (tid == 0) s_grow = -1;
             } else {
-                int lo = last_row, hi = (int)n;
+                long long lo = last_row, hi = b.total_rows;
                 while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if ((unsigned long long)a.item_off[mid] <= g) lo = mid; else hi = mid;
+                    const long long step = (hi - lo + 63) / 64;
+                    const long long idx = lo + (long long)tid * step;
+                    const bool ok = idx < hi && (unsigned long long)b.item_off[idx] <= g;
+                    const unsigned long long mask = __ballot(ok);
+                    const int top = 63 - __clzll((long long)mask);  // lane 0 always qualifies
+                    lo = lo + (long long)top * step;
+                    hi = lo + step < hi ? lo + step : hi;
                 }
-                s_row = lo;
-                s_r0 = (long long)(g - (unsigned long long)a.item_off[lo]) * a.ranks_per_item;
+                if (tid == 0) {
+                    s_grow = lo;
+                    s_r0 = (long long)(g - (unsigned long long)b.item_off[lo]) * R;
+                }
             }
         }
         __syncthreads();
-        const int row = s_row;
-        if (row < 0) break;
-        last_row = row;
-        if (row != staged) {
-            d = a.deg[row];
+        const long long grow = s_grow;
+        if (grow < 0) break;
+        last_row = grow;
+        const int pd = find_base(b.row_base, b.count, grow);
+        const Prob &P = b.probs[pd];
+        const int64_t n = P.n, W = P.W;
+        const int row = (int)(grow - b.row_base[pd]);
+        const T *C = static_cast<const T *>(P.C);
+        unsigned long long *adj_row = P.adj + (int64_t)row * W;
+        if (grow != staged) {
+            d = P.deg[row];
             const bool nb_lds = d <= kDcap;
-            const bool blk_lds = nb_lds && L >= 2 && (long long)d * d <= blk_cap;
+            const bool blk_lds = nb_lds && (long long)d * d <= blk_cap;
             if (nb_lds)
                 for (int p = tid; p < d; p += kLevelThreads) {
-                    const int k = a.nbr[(int64_t)row * n + p];
+                    const int k = P.nbr[(int64_t)row * n + p];
                     lds_nb[p] = k;
                     lds_ci[p] = C[(int64_t)row * n + k];
                 }
             __syncthreads();
-            if (blk_lds)
-                for (int e = tid; e < d * d; e += kLevelThreads) {
-                    const int p = e / d, q = e - p * d;
-                    lds_blk[e] = C[(int64_t)lds_nb[p] * n + lds_nb[q]];
+            if (blk_lds) {
+                // C[N_i, N_i]: each thread issues 8 independent gathers before storing any.
+                const int dd = d * d;
+                for (int e0 = tid; e0 < dd; e0 += 8 * kLevelThreads) {
+                    T v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + u * kLevelThreads;
+                        v[u] = (T)0;
+                        if (e < dd) {
+                            const int p = e / d, q = e - p * d;
+                            v[u] = C[(int64_t)lds_nb[p] * n + lds_nb[q]];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + u * kLevelThreads;
+                        if (e < dd) lds_blk[e] = v[u];
+                    }
                 }
-            if (tid == 0) s_mode = (nb_lds ? 1 : 0) | (blk_lds ? 2 : 0);
-            staged = row;
-            __syncthreads();
+            }
+            if (tid == 0) s_mode = (nb_lds ? 1 : 0) | (blk_lds ? 2 : 0) | (W <= kWcap ? 4 : 0);
+            staged = grow;
         }
+        // Live bits of row i, refreshed at every item (other rows remove edges meanwhile).
+        if (W <= kWcap)
+            for (int w = tid; w < W; w += kLevelThreads) lds_live[w] = live_word(adj_row + w);
+        __syncthreads();
         const int mode = s_mode;
-        const int *nbg = a.nbr + (int64_t)row * n;
+        const int *nbg = P.nbr + (int64_t)row * n;
         auto NB = [&](int p) -> int { return (mode & 1) ? lds_nb[p] : nbg[p]; };
         auto CI = [&](int p) -> T { return (mode & 1) ? lds_ci[p] : C[(int64_t)row * n + nbg[p]]; };
         auto CS = [&](int p, int q) -> T {
             if (p == q) return (T)1;
             return (mode & 2) ? lds_blk[p * d + q] : C[(int64_t)NB(p) * n + NB(q)];
         };
+        auto LIVE = [&](int j) -> bool {
+            const unsigned long long wv = (mode & 4) ? lds_live[j >> 6] : live_word(adj_row + (j >> 6));
+            return (wv >> (j & 63)) & 1ull;
+        };
+        const double tau = P.tau[L];
+        const float tl = P.t[L], band = P.band[L];
 
         const unsigned long long nS = binom(d, L);
         const long long r0 = s_r0;
-        const long long r1 = (long long)nS < r0 + a.ranks_per_item ? (long long)nS : r0 + a.ranks_per_item;
+        const long long r1 = (long long)nS < r0 + R ? (long long)nS : r0 + R;
         const long long nr = r1 - r0;
         int split, qn, slice;
         long long my_t, my_end;
@@ -410,259 +434,205 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(LevelArgs a) {
             my_end = my_t < r1 ? my_t + 1 : my_t;
         }
         const int psteps = (d + split - 1) / split;
+        int since_refresh = 0;
 
-        int P[L];
+        int P_[L];
 #pragma unroll
-        for (int c = 0; c < L; ++c) P[c] = 0;
+        for (int c = 0; c < L; ++c) P_[c] = 0;
         for (int step = 0; step < qn; ++step) {
             const long long t = my_t + step;
             if (t >= my_end) break;
-            if (step == 0) comb_unrank<L>(d, (unsigned long long)t, P, binom);
-            else comb_next<L>(d, P);
+            if (step == 0) comb_unrank<L>(d, (unsigned long long)t, P_, binom);
+            else comb_next<L>(d, P_);
 
             // Shared per-S work: Cholesky of M2 = C[S,S], y = L^-1 C[S,i]^T, H11 = 1 - y.y.
-            T Lm[L * (L + 1) / 2];
-            T rd[L];
-            T y[L];
-            bool ok = true;
-#pragma unroll
-            for (int r = 0; r < L; ++r) {
-#pragma unroll
-                for (int c = 0; c <= r; ++c) {
-                    T s = CS(P[r], P[c]);
-#pragma unroll
-                    for (int e = 0; e < c; ++e) s -= Lm[r * (r + 1) / 2 + e] * Lm[c * (c + 1) / 2 + e];
-                    if (r == c) {
-                        const T tol = sizeof(T) == 8 ? (T)1e-12 : (T)1e-4;
-                        if (!(s > tol)) ok = false;
-                        const T piv = s > tol ? s : (T)1;
-                        Lm[r * (r + 1) / 2 + r] = sqrt(piv);
-                        rd[r] = (T)1 / sqrt(piv);
-                    } else {
-                        Lm[r * (r + 1) / 2 + c] = s * rd[c];
-                    }
-                }
-            }
-            T yy = 0;
-#pragma unroll
-            for (int r = 0; r < L; ++r) {
-                T s = CI(P[r]);
-#pragma unroll
-                for (int e = 0; e < r; ++e) s -= Lm[r * (r + 1) / 2 + e] * y[e];
-                y[r] = s * rd[r];
-                yy += y[r] * y[r];
-            }
-            const T h11 = (T)1 - yy;
-            float g2 = 4.0f;
-            if (sizeof(T) == 4 && L > 1) {
-                // g = 1 + sqrt(l tr(M2^-1)) bounds 1 + ||M2^-1 c||_1 for any |c| with
-                // c^T M2^-1 c <= 1, where tr(M2^-1) = ||L^-1||_F^2.
-                float tr = 0.0f;
-#pragma unroll
-                for (int k = 0; k < L; ++k) {
-                    float x[L];
-#pragma unroll
-                    for (int r = 0; r < L; ++r) {
-                        if (r < k) { x[r] = 0.0f; continue; }
-                        float s = r == k ? 1.0f : 0.0f;
-#pragma unroll
-                        for (int e = 0; e < r; ++e) s -= (float)Lm[r * (r + 1) / 2 + e] * x[e];
-                        x[r] = s * (float)rd[r];
-                        tr += x[r] * x[r];
-                    }
-                }
-                const float g = 1.0f + sqrtf((float)L * tr);
-                g2 = g * g;
-            }
+            SetFactor<T, L> f;
+            f.build(P_, CS, CI);
             int sid[L];
 #pragma unroll
-            for (int c = 0; c < L; ++c) sid[c] = NB(P[c]);
+            for (int c = 0; c < L; ++c) sid[c] = NB(P_[c]);
 
             for (int pp = 0; pp < psteps; ++pp) {
                 const int p = pp * split + slice;
                 if (p >= d) break;
                 bool inS = false;
 #pragma unroll
-                for (int c = 0; c < L; ++c) inS |= P[c] == p;
+                for (int c = 0; c < L; ++c) inS |= P_[c] == p;
                 if (inS) continue;
                 const int j = NB(p);
-                const unsigned long long wv = live_word(a.adj + (int64_t)row * W + (j >> 6));
-                if (!((wv >> (j & 63)) & 1ull)) continue;
-                ++my_tests;
-                T w[L];
-                T ww = 0, yw = 0;
-#pragma unroll
-                for (int r = 0; r < L; ++r) {
-                    T s = CS(p, P[r]);
-#pragma unroll
-                    for (int e = 0; e < r; ++e) s -= Lm[r * (r + 1) / 2 + e] * w[e];
-                    w[r] = s * rd[r];
-                    ww += w[r] * w[r];
-                    yw += y[r] * w[r];
+                if ((mode & 4) && ++since_refresh >= 16) {
+                    // Fold in removals made by other work-groups since the row was staged.
+                    since_refresh = 0;
+                    atomicAnd(&lds_live[j >> 6], live_word(adj_row + (j >> 6)));
                 }
-                const T h22 = (T)1 - ww;
-                const T h12 = CI(p) - yw;
-                int dec;  // 0 dependent, 1 independent, 2 re-check in FP64
-                if (sizeof(T) == 8) {
-                    if (ok) {
-                        const double rho = (h11 > 0 && h22 > 0) ? (double)h12 / sqrt((double)h11 * (double)h22) : 0.0;
-                        dec = fisher_z64(rho) <= a.tau ? 1 : 0;
-                    } else {
-                        dec = 2;  // rank-deficient M2: pseudo-inverse path of the re-check kernel
-                    }
-                } else {
-                    const float fh11 = (float)h11, fh22 = (float)h22;
-                    const float floor_ = 2.0f * a.band * g2;
-                    if (!ok || fh11 <= floor_ || fh22 <= floor_) {
-                        dec = 2;
-                    } else {
-                        const float inv = rsqrtf(fh11 * fh22);
-                        const float ar = fabsf((float)h12 * inv);
-                        const float err = a.band * g2 * (inv + 0.5f * ar * (1.0f / fh11 + 1.0f / fh22));
-                        dec = ar <= a.t - err ? 1 : (ar > a.t + err ? 0 : 2);
-                    }
-                    if (a.force_recheck) {
-                        push_recheck<L>(a, row, j, sid, dec);
-                        continue;
-                    }
+                if (!LIVE(j)) continue;
+                ++my_tests;
+                const int dec = f.test(P_, p, CS, CI, tau, tl, band);
+                if (sizeof(T) == 4 && b.force_recheck) {
+                    push_recheck<L>(b, pd, row, j, sid, dec);
+                    continue;
                 }
                 if (dec == 2) {
-                    push_recheck<L>(a, row, j, sid, 2);
+                    push_recheck<L>(b, pd, row, j, sid, 2);
                 } else if (dec == 1) {
                     const int lo = row < j ? row : j, hi = row < j ? j : row;
-                    if (take_edge(a.adj, W, lo, hi)) {
+                    if (take_edge(P.adj, W, lo, hi)) {
                         ++my_removed;
-                        const long long k = (long long)atomicAdd((unsigned long long *)a.rec_count, 1ull);
-                        if (k < a.rec_cap) {
-                            pc_sep_rec *rec = a.recs + k;
-                            rec->i = lo;
-                            rec->j = hi;
-                            rec->level = L;
-#pragma unroll
-                            for (int c = 0; c < PC_MAX_LEVEL; ++c) rec->S[c] = c < L ? sid[c] : -1;
-                        }
+                        write_record(P, lo, hi, L, sid);
                     }
+                    if (mode & 4) atomicAnd(&lds_live[j >> 6], ~(1ull << (j & 63)));
                 }
             }
         }
-    }
-    if (my_tests) add_ll(&s_tests, my_tests);
-    if (my_removed) add_ll(&s_removed, my_removed);
-    __syncthreads();
-    if (tid == 0) {
-        if (s_tests) add_ll(&st->tests[L], s_tests);
-        if (s_removed) add_ll(&st->removed[L], s_removed);
+        // Statistics go to the problem of this item (items of one problem are contiguous).
+        if (my_tests) add_ll(&s_tests, my_tests);
+        if (my_removed) add_ll(&s_removed, my_removed);
+        my_tests = 0;
+        my_removed = 0;
+        __syncthreads();
+        if (tid == 0) {
+            Prob &Pw = b.probs[pd];
+            if (s_tests) add_ll(&Pw.tests[L], s_tests);
+            if (s_removed) add_ll(&Pw.removed[L], s_removed);
+            s_tests = 0;
+            s_removed = 0;
+        }
     }
 }
 
 template <typename T, int L>
-static hipError_t launch_level_t(hipStream_t s, const LevelArgs &a, int grid) {
-    hipLaunchKernelGGL((k_level<T, L>), dim3(grid), dim3(kLevelThreads), a.lds_bytes, s, a);
+static hipError_t launch_level_t(hipStream_t s, const Batch &b, int R, int lds_bytes, int grid) {
+    hipLaunchKernelGGL((k_level<T, L>), dim3(grid), dim3(kLevelThreads), lds_bytes, s, b, R, lds_bytes);
     return hipGetLastError();
 }
 
 template <typename T, int L>
 struct LevelDispatch {
-    static hipError_t run(hipStream_t s, const LevelArgs &a, int grid) {
-        if (a.level == L) return launch_level_t<T, L>(s, a, grid);
-        return LevelDispatch<T, L + 1>::run(s, a, grid);
+    static hipError_t run(hipStream_t s, const Batch &b, int level, int R, int lds, int grid) {
+        if (level == L) return launch_level_t<T, L>(s, b, R, lds, grid);
+        return LevelDispatch<T, L + 1>::run(s, b, level, R, lds, grid);
     }
 };
 template <typename T>
 struct LevelDispatch<T, PC_MAX_LEVEL + 1> {
-    static hipError_t run(hipStream_t, const LevelArgs &, int) { return hipErrorInvalidValue; }
+    static hipError_t run(hipStream_t, const Batch &, int, int, int, int) { return hipErrorInvalidValue; }
 };
 
 size_t level_lds_fixed(int prec) {
     return prec == PC_PREC_FP64 ? lds_fixed_bytes<double>() : lds_fixed_bytes<float>();
 }
 
-hipError_t launch_level(hipStream_t s, const LevelArgs &a, int prec, int grid) {
-    if (a.level < 1 || a.level > PC_MAX_LEVEL) return hipErrorInvalidValue;
-    if (prec == PC_PREC_FP64) return LevelDispatch<double, 1>::run(s, a, grid);
-    return LevelDispatch<float, 1>::run(s, a, grid);
+hipError_t launch_level(hipStream_t s, const Batch &b, int level, int R, int lds_bytes, int grid) {
+    if (level < 1 || level > PC_MAX_LEVEL) return hipErrorInvalidValue;
+    if (b.prec == PC_PREC_FP64) return LevelDispatch<double, 1>::run(s, b, level, R, lds_bytes, grid);
+    return LevelDispatch<float, 1>::run(s, b, level, R, lds_bytes, grid);
 }
 
 // ---------------------------------------------------------------------------------------------
 // FP64 re-check
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_recheck(RecheckArgs a) {
-    __shared__ double G[4][kGramLd * kGramLd];
-    __shared__ double work[4][kWork];
-    __shared__ int vl[4][kGramLd];
-    __shared__ long long s_rechecks, s_removed, s_viol;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) { s_rechecks = 0; s_removed = 0; s_viol = 0; }
-    __syncthreads();
-    DevState *st = a.st;
+constexpr int kUnroll = 4;       // 64-sample slices staged per round of the re-check
+
+// One wavefront per work-group; queued tests are taken grid-stride. The FP64 block over
+// (i, j, S) is accumulated lane-parallel over samples: each round a lane loads its samples of the
+// l + 2 standardized rows (kUnroll slices, all loads issued together) into its own LDS column and
+// adds their products into per-pair partial sums, 16 pairs at a time; a wave reduction per pair
+// finishes the dot products.
+__global__ __launch_bounds__(64) void k_recheck(Batch b, int level) {
+    __shared__ double vbuf[kUnroll][kGramLd][64];
+    __shared__ double G[kGramLd * kGramLd];
+    __shared__ double work[kWork];
+    __shared__ int vl[kGramLd];
+    const int lane = threadIdx.x;
+    DevState *st = b.st;
     const unsigned long long pushed = st->rq_count;
-    const long long count = pushed < (unsigned long long)a.rq_cap ? (long long)pushed : a.rq_cap;
-    const int l = a.level, k = l + 2;
-    long long my_rechecks = 0, my_removed = 0, my_viol = 0;
-    for (long long e = (long long)blockIdx.x * 4 + wave; e < count; e += (long long)gridDim.x * 4) {
-        const pc_sep_rec q = a.rq[e];
-        const int i = q.i, j = q.j, cls = q.level;
+    const long long count = pushed < (unsigned long long)b.rq_cap ? (long long)pushed : b.rq_cap;
+    const int l = level, k = l + 2, npairs = k * (k - 1) / 2;
+    for (long long e = blockIdx.x; e < count; e += gridDim.x) {
+        const RqEntry q = b.rq[e];
+        Prob &P = b.probs[q.prob];
+        const int i = q.i, j = q.j, cls = q.cls;
         const int lo = i < j ? i : j, hi = i < j ? j : i;
-        const bool live = (live_word(a.adj + (int64_t)lo * a.W + (hi >> 6)) >> (hi & 63)) & 1ull;
-        if (!live && !a.audit) continue;
-        if (lane < k) vl[wave][lane] = lane == 0 ? i : (lane == 1 ? j : q.S[lane - 2]);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        double *g = G[wave];
-        if (a.zt64) {
-            for (int r = 0; r < k; ++r) {
-                const double *zr = a.zt64 + (int64_t)vl[wave][r] * a.mp;
-                for (int c = r + 1; c < k; ++c) {
-                    const double *zc = a.zt64 + (int64_t)vl[wave][c] * a.mp;
-                    double s = 0.0;
-                    for (int64_t x = lane; x < a.m; x += 64) s += zr[x] * zc[x];
-                    s = wave_sum64(s);
-                    if (lane == 0) { g[r * kGramLd + c] = s; g[c * kGramLd + r] = s; }
+        const int64_t W = P.W, mp = P.mp, m = P.m, n = P.n;
+        const double *zt64 = P.zt64;
+        // One lane reads the live bit and the wave follows it: lanes must agree, since the body
+        // below holds barriers and another work-group may clear the bit at any moment.
+        int live_lane0 = 0;
+        if (lane == 0) live_lane0 = (int)((live_word(P.adj + (int64_t)lo * W + (hi >> 6)) >> (hi & 63)) & 1ull);
+        const bool live = __shfl(live_lane0, 0, 64) != 0;
+        if (!live && !b.force_recheck) continue;
+        if (lane < k) vl[lane] = lane == 0 ? i : (lane == 1 ? j : q.S[lane - 2]);
+        __syncthreads();
+        if (b.prec != PC_PREC_FP64) {
+            for (int pb = 0; pb < npairs; pb += 16) {
+                int pr[16], pc[16];
+                double acc[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    // pair number pb + t -> (r, c), r < c, rows taken in order
+                    int p = pb + t < npairs ? pb + t : 0, r = 0;
+                    while (p >= k - 1 - r) { p -= k - 1 - r; ++r; }
+                    pr[t] = r;
+                    pc[t] = r + 1 + p;
+                    acc[t] = 0.0;
                 }
-                if (lane == 0) g[r * kGramLd + r] = 1.0;
+                for (int64_t x0 = 0; x0 < m; x0 += 64 * kUnroll) {
+                    // All loads of the round into registers first, then into this lane's column.
+                    double vv[kGramLd][kUnroll];
+#pragma unroll
+                    for (int r = 0; r < kGramLd; ++r) {
+                        if (r >= k) continue;
+                        const double *z = zt64 + (int64_t)vl[r] * mp;
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u) {
+                            const int64_t x = x0 + 64 * u + lane;
+                            vv[r][u] = x < mp ? z[x] : 0.0;
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < kGramLd; ++r) {
+                        if (r >= k) continue;
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u) vbuf[u][r][lane] = vv[r][u];
+                    }
+#pragma unroll
+                    for (int t = 0; t < 16; ++t)
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u)
+                            acc[t] += vbuf[u][pr[t]][lane] * vbuf[u][pc[t]][lane];
+                }
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const double sum = wave_sum64(acc[t]);
+                    if (lane == 0 && pb + t < npairs) {
+                        G[pr[t] * kGramLd + pc[t]] = sum;
+                        G[pc[t] * kGramLd + pr[t]] = sum;
+                    }
+                }
             }
+            if (lane < k) G[lane * kGramLd + lane] = 1.0;
         } else if (lane == 0) {
+            const double *C64 = static_cast<const double *>(P.C);
             for (int r = 0; r < k; ++r)
                 for (int c = 0; c < k; ++c)
-                    g[r * kGramLd + c] = r == c ? 1.0 : a.C64[(int64_t)vl[wave][r] * a.n + vl[wave][c]];
+                    G[r * kGramLd + c] = r == c ? 1.0 : C64[(int64_t)vl[r] * n + vl[c]];
         }
-        int res = 0;
-        if (lane == 0) res = decide_gram64(g, kGramLd, l, a.tau, work[wave]);
-        res = __shfl(res, 0, 64);
+        __syncthreads();
         if (lane == 0) {
-            ++my_rechecks;
-            if (a.audit && cls != 2 && cls != res) ++my_viol;
-            if (res && live && take_edge(a.adj, a.W, lo, hi)) {
-                ++my_removed;
-                const long long r = (long long)atomicAdd((unsigned long long *)a.rec_count, 1ull);
-                if (r < a.rec_cap) {
-                    pc_sep_rec *rec = a.recs + r;
-                    rec->i = lo;
-                    rec->j = hi;
-                    rec->level = l;
-                    for (int c = 0; c < PC_MAX_LEVEL; ++c) rec->S[c] = c < l ? q.S[c] : -1;
-                }
+            const int res = decide_gram64(G, kGramLd, l, P.tau[l], work);
+            add_ll(&P.rechecks[l], 1);
+            if (b.force_recheck && cls != 2 && cls != res) add_ll(&P.audit_viol[l], 1);
+            if (res && live && take_edge(P.adj, W, lo, hi)) {
+                add_ll(&P.removed[l], 1);
+                write_record(P, lo, hi, l, q.S);
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-    }
-    if (lane == 0) {
-        if (my_rechecks) add_ll(&s_rechecks, my_rechecks);
-        if (my_removed) add_ll(&s_removed, my_removed);
-        if (my_viol) add_ll(&s_viol, my_viol);
-    }
-    __syncthreads();
-    if (tid == 0) {
-        if (s_rechecks) add_ll(&st->rechecks[l], s_rechecks);
-        if (s_removed) add_ll(&st->removed[l], s_removed);
-        if (s_viol) add_ll(&st->audit_viol[l], s_viol);
+        __syncthreads();
     }
 }
 
-hipError_t launch_recheck(hipStream_t s, const RecheckArgs &a, int grid) {
-    hipLaunchKernelGGL(k_recheck, dim3(grid), dim3(256), 0, s, a);
+hipError_t launch_recheck(hipStream_t s, const Batch &b, int level, int grid) {
+    hipLaunchKernelGGL(k_recheck, dim3(grid), dim3(64), 0, s, b, level);
     return hipGetLastError();
 }
 

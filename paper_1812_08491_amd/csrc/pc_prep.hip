@@ -1,27 +1,19 @@
-// Data preparation: run-state reset, binomial table, column statistics and standardization.
+// Data preparation: binomial table, run-state reset, column statistics and standardization.
 //
 // The paper takes the correlation matrix C as given (Sec. 4.3: the CI tests need only C, m and
 // alpha). Here C is built from the data: every variable is centred with a two-pass FP64 mean and
 // scaled to unit Euclidean norm, Z[:,a] = (X[:,a] - mu_a) / sqrt(sum_r (X[r,a] - mu_a)^2), so that
 // C = Z^T Z is the Pearson correlation. Z is stored variable-major (n rows of mp samples, zero
 // padded to a multiple of 64) in FP64 for re-checks, plus the low-precision copy the GEMM reads.
-#include <hip/hip_bf16.h>
-
 #include "pc_dev.h"
 
 namespace pcg {
 
-__global__ void k_init(DevState *st, unsigned long long *binom, int64_t n, long long *zero_me) {
-    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a == 0) {
-        // Zero the run state with vector stores.
-        int *p = reinterpret_cast<int *>(st);
-        for (size_t k = 0; k < sizeof(DevState) / sizeof(int); ++k) p[k] = 0;
-        if (zero_me) *zero_me = 0;
-    }
-    if (a > n) return;
-    // Row a of Pascal's triangle by the multiplicative recurrence C(a,b+1) = C(a,b)(a-b)/(b+1),
-    // saturating at 2^62.
+// Row a of Pascal's triangle by the multiplicative recurrence C(a,b+1) = C(a,b)(a-b)/(b+1),
+// saturating at 2^62.
+__global__ void k_binom(unsigned long long *binom, int64_t rows) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= rows) return;
     unsigned long long c = 1;
     for (int b = 0; b < kBinomCols; ++b) {
         binom[a * kBinomCols + b] = c;
@@ -30,7 +22,7 @@ __global__ void k_init(DevState *st, unsigned long long *binom, int64_t n, long 
         } else if (c >= kSat) {
             c = kSat;
         } else {
-            unsigned long long f = (unsigned long long)(a - b);
+            const unsigned long long f = (unsigned long long)(a - b);
             if (c > kSat / f) {
                 c = kSat;
             } else {
@@ -41,47 +33,67 @@ __global__ void k_init(DevState *st, unsigned long long *binom, int64_t n, long 
     }
 }
 
-hipError_t launch_init(hipStream_t s, DevState *st, unsigned long long *binom, int64_t n,
-                       long long *zero_me) {
-    int64_t threads = n + 1;
-    dim3 grid((unsigned)((threads + 255) / 256));
-    hipLaunchKernelGGL(k_init, grid, dim3(256), 0, s, st, binom, n, zero_me);
+hipError_t launch_binom(hipStream_t s, unsigned long long *binom, int64_t rows) {
+    hipLaunchKernelGGL(k_binom, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, binom, rows);
     return hipGetLastError();
 }
 
-// Re-arms the level machinery before a caller-driven level: clears the stop flag and the
-// per-level scratch counters (the statistics and the error flag are kept).
-__global__ void k_rearm(DevState *st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->done = 0;
-        st->blocks_done = 0u;
-        st->deg_work = 0;
-        st->rq_count = 0ull;
-        st->rq_overflow = 0;
-        st->overflow = 0;
+// Zeroes the batch queue state and every problem's statistics and SepSet counter (one work-group
+// per problem).
+__global__ __launch_bounds__(256) void k_init(Batch b) {
+    const int d = blockIdx.x, tid = threadIdx.x;
+    if (d == 0 && tid < (int)(sizeof(DevState) / sizeof(int))) reinterpret_cast<int *>(b.st)[tid] = 0;
+    Prob &p = b.probs[d];
+    if (tid < kLevels) {
+        p.tests[tid] = 0;
+        p.removed[tid] = 0;
+        p.rechecks[tid] = 0;
+        p.items[tid] = 0;
+        p.audit_viol[tid] = 0;
+        p.probe_tests[tid] = 0;
+        p.probe_removed[tid] = 0;
+        p.maxdeg[tid] = 0;
+    }
+    if (tid == 0) {
+        p.err = 0;
+        if (p.rec_count) *p.rec_count = 0;
     }
 }
 
-hipError_t launch_rearm(hipStream_t s, DevState *st) {
-    hipLaunchKernelGGL(k_rearm, dim3(1), dim3(64), 0, s, st);
+hipError_t launch_init(hipStream_t s, const Batch &b) {
+    hipLaunchKernelGGL(k_init, dim3((unsigned)b.count), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
-// One work-group per 64 consecutive variables: 4 row groups x 64 columns, rows strided by 4, so
-// each row group reads 512 contiguous bytes of X per step.
-__global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ X, int64_t m, int64_t n,
-                                                  double *__restrict__ mu, double *__restrict__ inv,
-                                                  DevState *st) {
-    __shared__ double part[4][64];
-    __shared__ int bad[64];
-    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int64_t a = (int64_t)blockIdx.x * 64 + c;
+// Re-arms the level machinery before a caller-driven level: clears the stop flag and the queue
+// counters (the problems' statistics are part of the freshly uploaded table).
+__global__ void k_rearm(Batch b) {
+    if (threadIdx.x < (int)(sizeof(DevState) / sizeof(int))) reinterpret_cast<int *>(b.st)[threadIdx.x] = 0;
+}
+
+hipError_t launch_rearm(hipStream_t s, const Batch &b) {
+    hipLaunchKernelGGL(k_rearm, dim3(1), dim3(64), 0, s, b);
+    return hipGetLastError();
+}
+
+// One work-group per 16 consecutive variables of one problem: 16 row groups x 16 columns, rows
+// strided by 16, so each row group reads 128 contiguous bytes of X per step.
+__global__ __launch_bounds__(256) void k_colstats(Batch b) {
+    __shared__ double part[16][kCsCols];
+    __shared__ int bad[kCsCols];
+    const int d = find_base(b.cs_base, b.count, blockIdx.x);
+    Prob &P = b.probs[d];
+    const int64_t n = P.n, m = P.m;
+    const double *__restrict__ X = P.X;
+    const int c = threadIdx.x & (kCsCols - 1), g = threadIdx.x / kCsCols;
+    const int64_t a = (int64_t)(blockIdx.x - b.cs_base[d]) * kCsCols + c;
     const bool valid = a < n;
     double s = 0.0;
     int nonfinite = 0;
     if (valid)
-        for (int64_t r = g; r < m; r += 4) {
-            double x = X[r * n + a];
+#pragma unroll 8
+        for (int64_t r = g; r < m; r += 16) {
+            const double x = X[r * n + a];
             nonfinite |= !isfinite(x);
             s += x;
         }
@@ -89,41 +101,45 @@ __global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ X, 
     if (g == 0) bad[c] = 0;
     __syncthreads();
     if (nonfinite) atomicOr(&bad[c], 1);
-    double mean = (part[0][c] + part[1][c] + part[2][c] + part[3][c]) / (double)m;
+    double tot = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) tot += part[k][c];
+    const double mean = tot / (double)m;
     __syncthreads();
     double ss = 0.0;
     if (valid)
-        for (int64_t r = g; r < m; r += 4) {
-            double d = X[r * n + a] - mean;
-            ss += d * d;
+#pragma unroll 8
+        for (int64_t r = g; r < m; r += 16) {
+            const double dx = X[r * n + a] - mean;
+            ss += dx * dx;
         }
     part[g][c] = ss;
     __syncthreads();
     if (g == 0 && valid) {
-        double tot = part[0][c] + part[1][c] + part[2][c] + part[3][c];
-        mu[a] = mean;
+        double sst = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sst += part[k][c];
+        P.mu[a] = mean;
         if (bad[c]) {
-            inv[a] = 0.0;
-            atomicCAS(&st->err, 0, (int)PC_ERR_NONFINITE);
-        } else if (!(tot > 0.0)) {
-            inv[a] = 0.0;
-            atomicCAS(&st->err, 0, (int)PC_ERR_CONSTANT_COLUMN);
+            P.inv[a] = 0.0;
+            atomicCAS(&P.err, 0, (int)PC_ERR_NONFINITE);
+        } else if (!(sst > 0.0)) {
+            P.inv[a] = 0.0;
+            atomicCAS(&P.err, 0, (int)PC_ERR_CONSTANT_COLUMN);
         } else {
-            inv[a] = 1.0 / sqrt(tot);
+            P.inv[a] = 1.0 / sqrt(sst);
         }
     }
 }
 
-hipError_t launch_colstats(hipStream_t s, const double *X, int64_t m, int64_t n, double *mu,
-                           double *inv, DevState *st) {
-    dim3 grid((unsigned)((n + 63) / 64));
-    hipLaunchKernelGGL(k_colstats, grid, dim3(256), 0, s, X, m, n, mu, inv, st);
+hipError_t launch_colstats(hipStream_t s, const Batch &b, long long blocks) {
+    hipLaunchKernelGGL(k_colstats, dim3((unsigned)blocks), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
 __device__ inline uint16_t bf16_bits_rne(float x) {
     uint32_t u = __float_as_uint(x);
-    uint32_t lsb = (u >> 16) & 1u;
+    const uint32_t lsb = (u >> 16) & 1u;
     u += 0x7fffu + lsb;  // round to nearest even (inputs are finite)
     return (uint16_t)(u >> 16);
 }
@@ -131,53 +147,45 @@ __device__ inline uint16_t bf16_bits_rne(float x) {
 __device__ inline float bf16_bits_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // Transposes a 64 x 64 tile of X (rows r, columns a) through LDS into Z (rows a, columns r).
-// prec selects the low-precision copy: FP32 -> zlo as float; BF16x3 -> zhi/zlo as the two BF16
-// halves hi = bf16(z), lo = bf16(z - hi).
-__global__ __launch_bounds__(256) void k_standardize(const double *__restrict__ X, int64_t m,
-                                                     int64_t n, int64_t mp,
-                                                     const double *__restrict__ mu,
-                                                     const double *__restrict__ inv,
-                                                     double *__restrict__ zt64, void *zlo,
-                                                     void *zhi, int prec) {
+// FP32 precision: zlo holds float; BF16x3: zhi/zlo hold the halves hi = bf16(z), lo = bf16(z - hi).
+__global__ __launch_bounds__(256) void k_standardize(Batch b) {
     __shared__ double tile[64][65];
-    const int64_t a0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
+    const int d = find_base(b.st_base, b.count, blockIdx.x);
+    Prob &P = b.probs[d];
+    const int64_t n = P.n, m = P.m, mp = P.mp;
+    const int64_t k = blockIdx.x - b.st_base[d], rblocks = mp / 64;
+    const int64_t a0 = (k / rblocks) * 64, r0 = (k % rblocks) * 64;
     const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t a = a0 + c;
     double mua = 0.0, inva = 0.0;
-    if (a < n) { mua = mu[a]; inva = inv[a]; }
+    if (a < n) { mua = P.mu[a]; inva = P.inv[a]; }
     for (int rr = g; rr < 64; rr += 4) {
-        int64_t r = r0 + rr;
+        const int64_t r = r0 + rr;
         double z = 0.0;
-        if (a < n && r < m) z = (X[r * n + a] - mua) * inva;
+        if (a < n && r < m) z = (P.X[r * n + a] - mua) * inva;
         tile[rr][c] = z;
     }
     __syncthreads();
     for (int aa = g; aa < 64; aa += 4) {
-        int64_t arow = a0 + aa;
+        const int64_t arow = a0 + aa;
         if (arow >= n) continue;
-        int64_t r = r0 + c;
-        double z = tile[c][aa];
-        size_t off = (size_t)arow * mp + r;
-        zt64[off] = z;
-        if (prec == PC_PREC_FP32) {
-            static_cast<float *>(zlo)[off] = (float)z;
-        } else if (prec == PC_PREC_BF16X3) {
-            float zf = (float)z;
-            uint16_t hi = bf16_bits_rne(zf);
-            float rem = (float)(z - (double)bf16_bits_to_float(hi));
-            uint16_t lo = bf16_bits_rne(rem);
-            static_cast<uint16_t *>(zhi)[off] = hi;
-            static_cast<uint16_t *>(zlo)[off] = lo;
+        const int64_t r = r0 + c;
+        const double z = tile[c][aa];
+        const size_t off = (size_t)arow * mp + r;
+        P.zt64[off] = z;
+        if (b.prec == PC_PREC_FP32) {
+            static_cast<float *>(P.zlo)[off] = (float)z;
+        } else if (b.prec == PC_PREC_BF16X3) {
+            const uint16_t hi = bf16_bits_rne((float)z);
+            const uint16_t lo = bf16_bits_rne((float)(z - (double)bf16_bits_to_float(hi)));
+            static_cast<uint16_t *>(P.zhi)[off] = hi;
+            static_cast<uint16_t *>(P.zlo)[off] = lo;
         }
     }
 }
 
-hipError_t launch_standardize(hipStream_t s, const double *X, int64_t m, int64_t n, int64_t mp,
-                              const double *mu, const double *inv, double *zt64, void *zlo,
-                              void *zhi, int prec) {
-    dim3 grid((unsigned)((n + 63) / 64), (unsigned)(mp / 64));
-    hipLaunchKernelGGL(k_standardize, grid, dim3(256), 0, s, X, m, n, mp, mu, inv, zt64, zlo, zhi,
-                       prec);
+hipError_t launch_standardize(hipStream_t s, const Batch &b, long long blocks) {
+    hipLaunchKernelGGL(k_standardize, dim3((unsigned)blocks), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

@@ -1,0 +1,122 @@
+"""GPU parity of the batched entry points (pc_batch_skeleton, pc_batch_capture + pc_graph_launch)
+against the FP64 oracle, dataset by dataset (marked gpu)."""
+import numpy as np
+import pytest
+
+import oracle
+import semgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1812_08491_amd as pc  # noqa: E402
+
+
+def uneven_batch(count, seed, nmax=200, mmax=2000):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(3, nmax + 1))
+        m = int(rng.integers(40, mmax + 1))
+        d = float(rng.uniform(2, 8))
+        sem = semgen.random_dag(n, semgen.expected_degree_p(n, d), rng)
+        out.append((semgen.sample(sem, m, rng), float(rng.choice([0.01, 0.05])), int(rng.integers(-1, 4))))
+    return out
+
+
+def device_problem(ctx, X, alpha, max_level):
+    m, n = X.shape
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    adj = ctx.adjacency(n)
+    recs, count = ctx.sepsets(n * (n - 1) // 2)
+    return (Xd, alpha, max_level, adj, recs, count)
+
+
+def check_one(X, alpha, max_level, item, status):
+    m, n = X.shape
+    _, _, _, adj, recs, count = item
+    ref = oracle.skeleton(X, alpha, max_level=max_level)
+    G = pc.bits_to_dense(adj.cpu().numpy(), n)
+    assert status == {0: 0, 2: 1}[ref.status]          # oracle warning 2 = pc warning 1
+    assert np.array_equal(G, ref.G), (n, m, alpha, max_level)
+    k = int(count.item())
+    seps = pc.decode_sepsets(recs[:k].cpu().numpy(), k)
+    ref_seps = ref.sepsets.as_dict()
+    assert set(seps) == set(ref_seps)
+    C = oracle.corr(X)
+    for e, (l, S) in seps.items():
+        assert ref_seps[e][0] == l
+        assert oracle.ci_test(C, e[0], e[1], list(S), m, alpha)[0]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+def test_batch_skeleton_matches_oracle(prec):
+    batch = uneven_batch(12, seed=40 + len(prec))
+    ctx = pc.Context(precision=prec)
+    items = [device_problem(ctx, X, a, ml) for X, a, ml in batch]
+    probs = ctx.problems(items)
+    ws = ctx.batch_workspace(probs)
+    stats = (pc.pc_run_stats * len(items))()
+    r, status = ctx.pc_batch_skeleton(probs, ws, stats)
+    assert r >= 0
+    for (X, a, ml), item, st in zip(batch, items, status):
+        check_one(X, a, ml, item, st)
+
+
+def test_graph_replays_match_oracle_with_new_data():
+    batch = uneven_batch(8, seed=77)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = pc.Context(stream=stream, precision="fp32")
+        items = [device_problem(ctx, X, a, ml) for X, a, ml in batch]
+        probs = ctx.problems(items)
+        ws = ctx.batch_workspace(probs)
+        g = ctx.pc_batch_capture(probs, ws)
+        rng = np.random.default_rng(5)
+        for replay in range(3):
+            if replay > 0:
+                # new data of the same shapes, written into the captured buffers
+                for k, (X, a, ml) in enumerate(batch):
+                    sem = semgen.random_dag(X.shape[1], 0.05, rng)
+                    Xn = semgen.sample(sem, X.shape[0], rng)
+                    batch[k] = (Xn, a, ml)
+                    items[k][0].copy_(torch.from_numpy(Xn))
+                # unrelated eager work between replays
+                junk = torch.randn(1024, 1024, device="cuda")
+                (junk @ junk).sum().item()
+            g.pc_graph_launch()
+            r, status = g.pc_graph_results()
+            assert r >= 0
+            for (X, a, ml), item, st in zip(batch, items, status):
+                check_one(X, a, ml, item, st)
+        g.close()
+    torch.cuda.synchronize()
+
+
+def test_graph_rejects_null_stream():
+    ctx = pc.Context(stream=torch.cuda.default_stream(), precision="fp32")
+    X = np.random.default_rng(0).standard_normal((50, 5))
+    items = [device_problem(ctx, X, 0.05, -1)]
+    probs = ctx.problems(items)
+    ws = ctx.batch_workspace(probs)
+    if torch.cuda.default_stream().cuda_stream == 0:
+        with pytest.raises(pc.PCError):
+            ctx.pc_batch_capture(probs, ws)
+
+
+def test_batch_reports_per_dataset_errors():
+    batch = uneven_batch(3, seed=3)
+    X_bad = batch[1][0].copy()
+    X_bad[:, 0] = 1.0
+    batch[1] = (X_bad, batch[1][1], batch[1][2])
+    ctx = pc.Context(precision="fp32")
+    items = [device_problem(ctx, X, a, ml) for X, a, ml in batch]
+    probs = ctx.problems(items)
+    ws = ctx.batch_workspace(probs)
+    r, status = ctx.pc_batch_skeleton(probs, ws)
+    assert status[1] == -3 and r == -3
+    check_one(*batch[0], items[0], status[0])
+    check_one(*batch[2], items[2], status[2])

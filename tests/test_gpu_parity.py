@@ -163,7 +163,7 @@ def compare_with_oracle(X, alpha, prec, max_level=-1, **opt):
     C64 = oracle.corr(X)
     ref = oracle.skeleton_corr(C64, m, alpha, max_level=max_level, keep_levels=True)
     G, seps, st, status = run_skeleton(X, alpha, prec, max_level=max_level, **opt)
-    assert status == ref.status or (status == 0 and ref.status == 0)
+    assert status == {0: 0, 2: 1}[ref.status]          # oracle warning 2 = pc warning 1
     assert np.array_equal(G, ref.G), np.argwhere(G != ref.G)[:8]
     assert st["levels_run"] == ref.levels_run
     # same removal level per edge: every oracle record has a GPU record at the same level

@@ -1,5 +1,6 @@
 """CPU checks of libpc.so: it loads, exports what include/pc.h declares, its ABI structs match the
 binding, and its host-only helpers match the paper's printed examples and scipy. No GPU needed."""
+import ctypes as ct
 import itertools
 import math
 import os
@@ -118,3 +119,17 @@ def test_bit_packing_round_trip():
     for n in (1, 63, 64, 65, 130):
         G = (rng.random((n, n)) < 0.3).astype(np.uint8)
         assert np.array_equal(pc.bits_to_dense(pc.dense_to_bits(G), n), G)
+
+
+def test_abi_mismatch_is_refused_at_load():
+    """A library whose struct sizes differ from the binding's is refused before any call."""
+    from paper_1812_08491_amd import _lib
+
+    class FakeLib:
+        def pc_abi_size(self, k):
+            return ct.sizeof([_lib.pc_options, _lib.pc_sep_rec, _lib.pc_sepset, _lib.pc_run_stats,
+                              _lib.pc_problem, _lib.pc_order][k]) + (224 if k == 3 else 0)
+
+    with pytest.raises(ImportError, match="pc_run_stats"):
+        _lib._check_abi(FakeLib())
+    _lib._check_abi(_lib.lib())
