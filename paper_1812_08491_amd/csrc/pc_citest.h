@@ -25,8 +25,19 @@ __device__ inline bool take_edge(unsigned long long *adj, int64_t W, int lo, int
     return true;
 }
 
+// Appends the SepSet record of the removed edge (lo, hi). The lanes of a wavefront that reach this
+// call together take consecutive slots with a single atomic add by the lowest of them, which keeps
+// the shared counter from serialising one device-scope atomic per removal. All active lanes must
+// be working on the same problem P.
 __device__ inline void write_record(const Prob &P, int lo, int hi, int level, const int *S) {
-    const long long k = (long long)atomicAdd((unsigned long long *)P.rec_count, 1ull);
+    const unsigned long long act = __ballot(1);
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((long long)act) - 1;
+    unsigned long long base = 0ull;
+    if (lane == leader)
+        base = atomicAdd(reinterpret_cast<unsigned long long *>(P.rec_count), (unsigned long long)__popcll(act));
+    base = __shfl(base, leader, 64);
+    const long long k = (long long)(base + (unsigned long long)__popcll(act & ((1ull << lane) - 1ull)));
     if (k < P.rec_cap) {
         pc_sep_rec *rec = P.recs + k;
         rec->i = lo;

@@ -24,6 +24,36 @@ __device__ inline void add_ll(long long *p, long long v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
 }
 
+// Exclusive prefix sum of v over the kThreads threads of a work-group (kThreads a multiple of 64,
+// at most 4096): a shuffle scan inside each wavefront, then one over the wavefront totals. total
+// receives the sum over all threads. lds: kThreads / 64 slots, free again after the next barrier.
+template <int kThreads>
+__device__ inline long long block_exclusive_scan(long long v, long long *lds, long long &total) {
+    static_assert(kThreads % 64 == 0 && kThreads <= 64 * 64, "work-group size");
+    constexpr int kWaves = kThreads / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    long long incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) lds[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        long long w = lane < kWaves ? lds[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < kWaves; o <<= 1) {
+            const long long t = __shfl_up(w, o, 64);
+            if (lane >= o) w += t;
+        }
+        if (lane < kWaves) lds[lane] = w;
+    }
+    __syncthreads();
+    total = lds[kWaves - 1];
+    return (wave > 0 ? lds[wave - 1] : 0) + incl - v;
+}
+
 // One problem of a batch: shapes, buffers (device pointers), thresholds and statistics.
 struct Prob {
     int64_t n, m, mp, W;

@@ -34,6 +34,21 @@ __device__ inline double wave_sum64(double v) {
     return v;
 }
 
+__device__ inline long long wave_sum_ll(long long v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Adds a work-group's test and removal counts of level L to its problem and clears them.
+template <int L>
+__device__ inline void flush_stats(Prob &P, long long &tests, long long &removed) {
+    if (tests) add_ll(&P.tests[L], tests);
+    if (removed) add_ll(&P.removed[L], removed);
+    tests = 0;
+    removed = 0;
+}
+
 // Whether level l runs for problem P (the level cap, Eq. 6 needing m - l - 3 > 0).
 __device__ inline bool level_enabled(const Prob &P, int l) {
     return l <= P.max_level && l <= PC_MAX_LEVEL && P.tau[l] == P.tau[l];
@@ -99,9 +114,10 @@ hipError_t launch_compact(hipStream_t s, const Batch &b, int level, int ranks_pe
 }
 
 constexpr int kPlanThreads = 1024;
+constexpr int kPlanLdsProbs = 4096;     // problems whose max degree is reduced in LDS
 
 __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level) {
-    __shared__ long long part[kPlanThreads];
+    __shared__ long long part[kPlanThreads / 64];
     DevState *st = b.st;
     if (st->done) return;
     const int tid = threadIdx.x;
@@ -110,21 +126,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level) {
     const long long lo = tid * chunk, hi = lo + chunk < N ? lo + chunk : N;
     long long s = 0;
     for (long long k = lo; k < hi; ++k) s += b.nitems[k];
-    part[tid] = s;
-    __syncthreads();
-    // Exclusive scan of the per-thread sums (Hillis-Steele in LDS).
-    for (int o = 1; o < kPlanThreads; o <<= 1) {
-        const long long v = tid >= o ? part[tid - o] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    long long run = part[tid] - s;
+    long long total = 0;
+    long long run = block_exclusive_scan<kPlanThreads>(s, part, total);
     for (long long k = lo; k < hi; ++k) {
         b.item_off[k] = run;
         run += b.nitems[k];
     }
-    const long long total = part[kPlanThreads - 1];
     if (tid == 0) {
         b.item_off[N] = total;
         st->total_items = (unsigned long long)total;
@@ -135,21 +142,37 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level) {
     __syncthreads();
     for (int d = tid; d < b.count; d += kPlanThreads)
         b.probs[d].items[level] = b.item_off[b.row_base[d + 1]] - b.item_off[b.row_base[d]];
-    // Max degree of G' per problem (what the stop rule of Algorithm 1 looks at), from the chunk of
-    // rows each thread scanned: one atomic per (thread, problem) segment.
+    // Max degree of G' per problem (what the stop rule of Algorithm 1 looks at). Each thread scans
+    // its chunk of rows segment by segment; segment maxima meet in LDS (one slot per problem) when
+    // the batch is small enough, so no global address sees more than one write per problem.
+    const bool in_lds = b.count <= kPlanLdsProbs;
+    __shared__ int s_maxdeg[kPlanLdsProbs];
+    if (in_lds)
+        for (int d = tid; d < b.count; d += kPlanThreads) s_maxdeg[d] = 0;
+    __syncthreads();
     if (lo < hi) {
         int d = find_base(b.row_base, b.count, lo);
         int best = 0;
         for (long long k = lo; k < hi; ++k) {
             while (k >= b.row_base[d + 1]) {
-                atomicMax(&b.probs[d].maxdeg[level], best);
+                if (best > 0) {
+                    if (in_lds) atomicMax(&s_maxdeg[d], best);
+                    else atomicMax(&b.probs[d].maxdeg[level], best);
+                }
                 best = 0;
                 ++d;
             }
             const int dg = b.probs[d].deg[k - b.row_base[d]];
             best = dg > best ? dg : best;
         }
-        atomicMax(&b.probs[d].maxdeg[level], best);
+        if (best > 0) {
+            if (in_lds) atomicMax(&s_maxdeg[d], best);
+            else atomicMax(&b.probs[d].maxdeg[level], best);
+        }
+    }
+    if (in_lds) {
+        __syncthreads();
+        for (int d = tid; d < b.count; d += kPlanThreads) b.probs[d].maxdeg[level] = s_maxdeg[d];
     }
 }
 
@@ -318,16 +341,18 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
 
     if (tid == 0) { s_tests = 0; s_removed = 0; }
     long long staged = -1, last_row = 0;
-    int d = 0;
+    int d = 0, stats_pd = -1;
     long long my_tests = 0, my_removed = 0;
+    bool first = true;
 
     for (;;) {
         __syncthreads();
         if (tid < 64) {
-            // Wave 0 pops the next item and finds its row: the largest r with item_off[r] <= g,
+            // Wave 0 takes the next item and finds its row: the largest r with item_off[r] <= g,
             // by 64-way probing (each round narrows the range 64-fold with one load per lane).
-            unsigned long long g = 0;
-            if (tid == 0) g = atomicAdd(&st->next_item, 1ull);
+            // The first item of a work-group is its own index; later ones come from the queue.
+            unsigned long long g = blockIdx.x;
+            if (!first && tid == 0) g = gridDim.x + atomicAdd(&st->next_item, 1ull);
             g = __shfl(g, 0, 64);
             if (g >= total) {
                 if (tid == 0) s_grow = -1;
@@ -349,10 +374,16 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
             }
         }
         __syncthreads();
+        first = false;
         const long long grow = s_grow;
         if (grow < 0) break;
         last_row = grow;
         const int pd = find_base(b.row_base, b.count, grow);
+        if (pd != stats_pd) {
+            // Counts are kept per work-group and written once per problem it worked on.
+            if (tid == 0 && stats_pd >= 0) flush_stats<L>(b.probs[stats_pd], s_tests, s_removed);
+            stats_pd = pd;
+        }
         const Prob &P = b.probs[pd];
         const int64_t n = P.n, W = P.W;
         const int row = (int)(grow - b.row_base[pd]);
@@ -484,20 +515,16 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                 }
             }
         }
-        // Statistics go to the problem of this item (items of one problem are contiguous).
-        if (my_tests) add_ll(&s_tests, my_tests);
-        if (my_removed) add_ll(&s_removed, my_removed);
+        // Per-wavefront sums into the work-group counters of this problem.
+        const long long wt = wave_sum_ll(my_tests), wr = wave_sum_ll(my_removed);
+        if ((tid & 63) == 0) {
+            if (wt) add_ll(&s_tests, wt);
+            if (wr) add_ll(&s_removed, wr);
+        }
         my_tests = 0;
         my_removed = 0;
-        __syncthreads();
-        if (tid == 0) {
-            Prob &Pw = b.probs[pd];
-            if (s_tests) add_ll(&Pw.tests[L], s_tests);
-            if (s_removed) add_ll(&Pw.removed[L], s_removed);
-            s_tests = 0;
-            s_removed = 0;
-        }
     }
+    if (tid == 0 && stats_pd >= 0) flush_stats<L>(b.probs[stats_pd], s_tests, s_removed);
 }
 
 template <typename T, int L>
@@ -531,108 +558,114 @@ hipError_t launch_level(hipStream_t s, const Batch &b, int level, int R, int lds
 // ---------------------------------------------------------------------------------------------
 // FP64 re-check
 // ---------------------------------------------------------------------------------------------
-constexpr int kUnroll = 4;       // 64-sample slices staged per round of the re-check
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-// One wavefront per work-group; queued tests are taken grid-stride. The FP64 block over
-// (i, j, S) is accumulated lane-parallel over samples: each round a lane loads its samples of the
-// l + 2 standardized rows (kUnroll slices, all loads issued together) into its own LDS column and
-// adds their products into per-pair partial sums, 16 pairs at a time; a wave reduction per pair
-// finishes the dot products.
-__global__ __launch_bounds__(64) void k_recheck(Batch b, int level) {
-    __shared__ double vbuf[kUnroll][kGramLd][64];
+constexpr int kRcThreads = 256;            // re-check work-group: 4 wavefronts per queued test
+constexpr int kRcChunk = 16;               // consecutive samples per lane per round
+constexpr int kRcRound = kRcThreads / 16 * kRcChunk;   // samples per round of a work-group (256)
+
+// One work-group per queued test (grid-stride). The FP64 Gram block of the standardized rows
+// (i, j, S) is one 16 x 16 tile Z Z^T accumulated on v_mfma_f64_16x16x4f64: lane l carries row
+// l % 16 of the tile, so the same register is both the A operand (Z) and the B operand (Z^T), and
+// each k-step sums four samples. Each lane holds 16 consecutive samples of its row per round; the
+// four wavefront tiles are added in LDS. Rows l + 2 .. 15 of the tile stay zero.
+__global__ __launch_bounds__(kRcThreads) void k_recheck(Batch b, int level) {
+    __shared__ double part[kRcThreads / 64][16 * 16];
     __shared__ double G[kGramLd * kGramLd];
     __shared__ double work[kWork];
-    __shared__ int vl[kGramLd];
-    const int lane = threadIdx.x;
-    DevState *st = b.st;
-    const unsigned long long pushed = st->rq_count;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned long long pushed = b.st->rq_count;
     const long long count = pushed < (unsigned long long)b.rq_cap ? (long long)pushed : b.rq_cap;
-    const int l = level, k = l + 2, npairs = k * (k - 1) / 2;
+    const int l = level, k = l + 2;
+    // Work-group totals, written once per problem (thread 0 only).
+    int cur = -1;
+    long long n_rc = 0, n_rm = 0, n_viol = 0;
+    __shared__ int s_v[16];        // variables of the tile rows: i, j, S..., then -1
+    __shared__ int s_prob, s_cls;
     for (long long e = blockIdx.x; e < count; e += gridDim.x) {
-        const RqEntry q = b.rq[e];
-        Prob &P = b.probs[q.prob];
-        const int i = q.i, j = q.j, cls = q.cls;
-        const int lo = i < j ? i : j, hi = i < j ? j : i;
-        const int64_t W = P.W, mp = P.mp, m = P.m, n = P.n;
-        const double *zt64 = P.zt64;
-        // One lane reads the live bit and the wave follows it: lanes must agree, since the body
-        // below holds barriers and another work-group may clear the bit at any moment.
-        int live_lane0 = 0;
-        if (lane == 0) live_lane0 = (int)((live_word(P.adj + (int64_t)lo * W + (hi >> 6)) >> (hi & 63)) & 1ull);
-        const bool live = __shfl(live_lane0, 0, 64) != 0;
-        if (!live && !b.force_recheck) continue;
-        if (lane < k) vl[lane] = lane == 0 ? i : (lane == 1 ? j : q.S[lane - 2]);
-        __syncthreads();
-        if (b.prec != PC_PREC_FP64) {
-            for (int pb = 0; pb < npairs; pb += 16) {
-                int pr[16], pc[16];
-                double acc[16];
-#pragma unroll
-                for (int t = 0; t < 16; ++t) {
-                    // pair number pb + t -> (r, c), r < c, rows taken in order
-                    int p = pb + t < npairs ? pb + t : 0, r = 0;
-                    while (p >= k - 1 - r) { p -= k - 1 - r; ++r; }
-                    pr[t] = r;
-                    pc[t] = r + 1 + p;
-                    acc[t] = 0.0;
-                }
-                for (int64_t x0 = 0; x0 < m; x0 += 64 * kUnroll) {
-                    // All loads of the round into registers first, then into this lane's column.
-                    double vv[kGramLd][kUnroll];
-#pragma unroll
-                    for (int r = 0; r < kGramLd; ++r) {
-                        if (r >= k) continue;
-                        const double *z = zt64 + (int64_t)vl[r] * mp;
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u) {
-                            const int64_t x = x0 + 64 * u + lane;
-                            vv[r][u] = x < mp ? z[x] : 0.0;
-                        }
-                    }
-#pragma unroll
-                    for (int r = 0; r < kGramLd; ++r) {
-                        if (r >= k) continue;
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u) vbuf[u][r][lane] = vv[r][u];
-                    }
-#pragma unroll
-                    for (int t = 0; t < 16; ++t)
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u)
-                            acc[t] += vbuf[u][pr[t]][lane] * vbuf[u][pc[t]][lane];
-                }
-#pragma unroll
-                for (int t = 0; t < 16; ++t) {
-                    const double sum = wave_sum64(acc[t]);
-                    if (lane == 0 && pb + t < npairs) {
-                        G[pr[t] * kGramLd + pc[t]] = sum;
-                        G[pc[t] * kGramLd + pr[t]] = sum;
-                    }
-                }
-            }
-            if (lane < k) G[lane * kGramLd + lane] = 1.0;
-        } else if (lane == 0) {
-            const double *C64 = static_cast<const double *>(P.C);
-            for (int r = 0; r < k; ++r)
-                for (int c = 0; c < k; ++c)
-                    G[r * kGramLd + c] = r == c ? 1.0 : C64[(int64_t)vl[r] * n + vl[c]];
+        const RqEntry *qe = b.rq + e;
+        if (tid < 16) s_v[tid] = tid == 0 ? qe->i : (tid == 1 ? qe->j : (tid < k ? qe->S[tid - 2] : -1));
+        if (tid == 0) {
+            s_prob = qe->prob;
+            s_cls = qe->cls;
         }
         __syncthreads();
-        if (lane == 0) {
+        const int prob = s_prob;
+        Prob &P = b.probs[prob];
+        const int i = s_v[0], j = s_v[1];
+        const int lo = i < j ? i : j, hi = i < j ? j : i;
+        if (b.prec != PC_PREC_FP64) {
+            const int64_t mp = P.mp;
+            const int vr = s_v[lane & 15];
+            const double *z = P.zt64 + (int64_t)(vr < 0 ? 0 : vr) * mp;
+            const int64_t off = (int64_t)(wave * 4 + (lane >> 4)) * kRcChunk;
+            doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int64_t x0 = 0; x0 < mp; x0 += kRcRound) {
+                // mp is a multiple of 64, so a chunk of 16 is either wholly inside or outside.
+                const int64_t x = x0 + off;
+                double v[kRcChunk];
+                if (vr >= 0 && x < mp) {
+                    const double2 *src = reinterpret_cast<const double2 *>(z + x);
+#pragma unroll
+                    for (int u = 0; u < kRcChunk / 2; ++u) {
+                        const double2 t = src[u];
+                        v[2 * u] = t.x;
+                        v[2 * u + 1] = t.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kRcChunk; ++u) v[u] = 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kRcChunk; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u], v[u], acc, 0, 0, 0);
+            }
+            // D layout of the FP64 16x16x4 product: lane l holds rows l / 16 + 4 t, column l % 16.
+#pragma unroll
+            for (int t = 0; t < 4; ++t) part[wave][((lane >> 4) + 4 * t) * 16 + (lane & 15)] = acc[t];
+            __syncthreads();
+            {
+                const int rr = tid >> 4, cc = tid & 15;
+                if (rr < k && cc < k)
+                    G[rr * kGramLd + cc] = rr == cc ? 1.0 : part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+            }
+        } else if (tid < k * k) {
+            const int rr = tid / k, cc = tid % k;
+            G[rr * kGramLd + cc] = rr == cc ? 1.0 : static_cast<const double *>(P.C)[(int64_t)s_v[rr] * P.n + s_v[cc]];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            if (prob != cur) {
+                if (cur >= 0) {
+                    Prob &Pc = b.probs[cur];
+                    add_ll(&Pc.rechecks[l], n_rc);
+                    if (n_rm) add_ll(&Pc.removed[l], n_rm);
+                    if (n_viol) add_ll(&Pc.audit_viol[l], n_viol);
+                }
+                cur = prob;
+                n_rc = n_rm = n_viol = 0;
+            }
             const int res = decide_gram64(G, kGramLd, l, P.tau[l], work);
-            add_ll(&P.rechecks[l], 1);
-            if (b.force_recheck && cls != 2 && cls != res) add_ll(&P.audit_viol[l], 1);
-            if (res && live && take_edge(P.adj, W, lo, hi)) {
-                add_ll(&P.removed[l], 1);
-                write_record(P, lo, hi, l, q.S);
+            ++n_rc;
+            if (b.force_recheck && s_cls != 2 && s_cls != res) ++n_viol;
+            // The atomic on the canonical bit decides: an edge another test already removed stays
+            // removed and keeps that test's SepSet.
+            if (res && take_edge(P.adj, P.W, lo, hi)) {
+                ++n_rm;
+                write_record(P, lo, hi, l, s_v + 2);
             }
         }
         __syncthreads();
     }
+    if (tid == 0 && cur >= 0) {
+        Prob &Pc = b.probs[cur];
+        add_ll(&Pc.rechecks[l], n_rc);
+        if (n_rm) add_ll(&Pc.removed[l], n_rm);
+        if (n_viol) add_ll(&Pc.audit_viol[l], n_viol);
+    }
 }
 
 hipError_t launch_recheck(hipStream_t s, const Batch &b, int level, int grid) {
-    hipLaunchKernelGGL(k_recheck, dim3(grid), dim3(64), 0, s, b, level);
+    hipLaunchKernelGGL(k_recheck, dim3(grid), dim3(kRcThreads), 0, s, b, level);
     return hipGetLastError();
 }
 

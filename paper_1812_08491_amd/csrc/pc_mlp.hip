@@ -296,7 +296,7 @@ hipError_t launch_adam(hipStream_t s, float *params, const float *grads, float *
 // the level's G'); foff[total_rows] is the total. Sets *skip when the total exceeds the capacity
 // (the level then runs without a probe) or when the level has no work.
 __global__ __launch_bounds__(1024) void k_feat_plan(Batch b, long long *foff, long long cap, int *skip) {
-    __shared__ long long part[1024];
+    __shared__ long long part[1024 / 64];
     const int tid = threadIdx.x;
     if (b.st->done) {
         if (tid == 0) *skip = 1;
@@ -312,22 +312,15 @@ __global__ __launch_bounds__(1024) void k_feat_plan(Batch b, long long *foff, lo
     };
     long long s = 0;
     for (long long k = lo; k < hi; ++k) s += cnt(k);
-    part[tid] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const long long v = tid >= o ? part[tid - o] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    long long run = part[tid] - s;
+    long long total = 0;
+    long long run = block_exclusive_scan<1024>(s, part, total);
     for (long long k = lo; k < hi; ++k) {
         foff[k] = run;
         run += cnt(k);
     }
-    if (tid == 1023) {
-        foff[N] = part[1023];
-        *skip = part[1023] > cap || part[1023] == 0 ? 1 : 0;
+    if (tid == 0) {
+        foff[N] = total;
+        *skip = total > cap || total == 0 ? 1 : 0;
     }
 }
 
