@@ -159,3 +159,37 @@ def test_ordered_skeleton_n1000():
     assert np.array_equal(G, ref.G)
     assert set(seps) == set(ref.sepsets.as_dict())
     assert st["probe_removed"][1] > 0
+
+
+def test_training_pipeline_beats_random_order_and_keeps_skeleton():
+    """Rows from the plain method on generated SEMs, training on the library's kernels, then the
+    trained scorer against a random order on held-out directions, and the learned-order skeleton
+    against the plain one."""
+    from paper_1812_08491_amd import learn
+    data = [(X, a) for X, _, a in semgen.training_sems(40, instance=7, n=100, m=600)]
+    X, y = learn.collect(data[:32], 100, 600, cap_per_level=4096, seed=1)
+    assert X.shape[0] > 10000 and 0.02 < float(y.mean()) < 0.6
+    pos = float(y.sum())
+    pw = min(50.0, (y.numel() - pos) / pos)
+    coll = learn.RowCollector(100, 600)
+    vrows = [r for Xv, a in data[32:] for r in coll.run(Xv, a, None, whole_directions=True)]
+    coll.close()
+    vX = torch.cat([r[1] for r in vrows])
+    vy = torch.cat([r[2] for r in vrows])
+    vdir = torch.cat([r[3] + (k << 32) for k, r in enumerate(vrows)])
+    tr = learn.Trainer(seed=2, batch=16384)
+    v0 = learn.bce_loss(tr, vX, vy, pw)
+    for _ in range(8):
+        tr.epoch(X, y, pw)
+    v1 = learn.bce_loss(tr, vX, vy, pw)
+    rec = learn.topq_recall(tr.scores_of(vX), vy, vdir, 4)
+    rnd = learn.topq_recall(torch.rand(vX.shape[0], device="cuda"), vy, vdir, 4)
+    print(f"val loss {v0:.4f} -> {v1:.4f}; recall@4 trained {rec:.3f} random {rnd:.3f}")
+    assert v1 < 0.9 * v0
+    assert rec > rnd + 0.1
+    X2, _, a2 = next(semgen.training_sems(1, instance=8, n=200, m=1000))
+    cmp = learn.compare_orders(X2, a2, tr.params, min_level=1, top=4, repeats=1)
+    print({k: cmp[k] for k in ("plain", "learned")})
+    assert cmp["same_skeleton"]
+    assert sum(cmp["learned"]["probe_removed"]) > 0
+    tr.close()
