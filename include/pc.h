@@ -31,8 +31,9 @@ extern "C" {
 #endif
 
 /* Largest conditioning-set size a level can use. A run that would need a larger level stops
- * after level PC_MAX_LEVEL and returns PC_WARN_LEVEL_CAP. */
-#define PC_MAX_LEVEL 13
+ * after level PC_MAX_LEVEL and returns PC_WARN_LEVEL_CAP. Levels up to 13 keep each conditioning
+ * set's factor in registers; deeper levels factor each set cooperatively across a wavefront. */
+#define PC_MAX_LEVEL 30
 
 typedef enum {
     PC_OK = 0,
@@ -70,7 +71,13 @@ typedef struct {
                                   1 = correlation kernel (incl. level 0), 2 = level kernels,
                                   4 = compaction, 8 = FP64 re-check, 16 = standardization */
     int64_t recheck_cap;       /* capacity of the FP64 re-check queue in tests per level
-                                  (0 = 1<<20); a level that needs more returns PC_ERR_WORKSPACE */
+                                  (0 = automatic: the sum of n^2/4 over the batch, at least
+                                  2^16, at most 2^25); a level that needs more returns
+                                  PC_ERR_WORKSPACE */
+    int32_t graph_levels;      /* levels recorded in a captured graph (pc_batch_capture; 0 = 10).
+                                  A replay whose datasets need more levels continues them on the
+                                  stream in pc_graph_results. */
+    int32_t pad;
 } pc_options;
 
 /* One SepSet record, written for every edge removed at a level >= 1 (Algorithm 1: "store S").
@@ -155,7 +162,9 @@ pc_status pc_level(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, u
                    const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes);
 
 /* The whole skeleton step (Algorithm 1 / Algorithm 2): pc_corr, then levels 1, 2, ... while the
- * maximum degree of G minus 1 is >= l (and l <= max_level if max_level >= 0).
+ * maximum degree of G minus 1 is >= l (and l <= max_level if max_level >= 0). The stop rule is
+ * evaluated on the device; the host reads the maximum degree once, after planning level 2, to
+ * bound how many levels it enqueues (degrees only shrink, so later levels cannot need more).
  *   X        device m x n FP64 data.
  *   adj_out  device bit matrix: the skeleton.
  *   sep      SepSet table (count is zeroed first).
@@ -197,17 +206,20 @@ size_t pc_batch_workspace_bytes(const pc_problem *probs, int count, const pc_opt
 pc_status pc_batch_skeleton(pc_ctx *ctx, const pc_problem *probs, int count, pc_run_stats *st,
                             pc_status *status, void *ws, size_t ws_bytes);
 
-/* A captured batch: the whole batched skeleton (standardize, correlation, and every level up to the
- * largest cap of the batch, each kernel exiting at once when no work is left) recorded once as a
- * hipGraph and replayed with pc_graph_launch. The graph keeps the pointers it was captured with:
- * new data is run by writing it into the same X buffers. The context's stream must not be the
- * null stream. */
+/* A captured batch: the batched skeleton (standardize, correlation, and levels 1 .. G, where G is
+ * the smaller of opt.graph_levels and the largest cap of the batch; each kernel exits at once when
+ * no work is left) recorded once as a hipGraph and replayed with pc_graph_launch. The graph keeps
+ * the pointers it was captured with: new data is run by writing it into the same X buffers. The
+ * context's stream must not be the null stream. */
 typedef struct pc_graph pc_graph;
 pc_status pc_batch_capture(pc_ctx *ctx, const pc_problem *probs, int count, void *ws,
                            size_t ws_bytes, pc_graph **out);
 /* Enqueues one replay on the context's stream (asynchronous). */
 pc_status pc_graph_launch(pc_graph *g);
-/* Waits for the last replay and reports per-dataset statistics and results (as pc_batch_skeleton). */
+/* Waits for the last replay and reports per-dataset statistics and results (as pc_batch_skeleton).
+ * If a dataset still has work after the recorded levels, the remaining levels are run on the
+ * context's stream first (ordinary launches), so the results are always those of the whole
+ * skeleton. */
 pc_status pc_graph_results(pc_graph *g, pc_run_stats *st, pc_status *status);
 void pc_graph_destroy(pc_graph *g);
 

@@ -35,6 +35,7 @@ struct pc_ctx {
     // Event pairs of the timed phases: prep, corr, and per level compact / level / re-check.
     hipEvent_t ev_prep[2], ev_corr[2];
     hipEvent_t ev_compact[kLevels][2], ev_level[kLevels][2], ev_recheck[kLevels][2];
+    int top_run;                    // highest level enqueued by the current call
 };
 
 struct pc_graph {
@@ -45,6 +46,9 @@ struct pc_graph {
     int count;
     size_t table_off, st_off;
     std::vector<Prob> host_probs;
+    std::vector<pc_problem> probs;  // descriptors it was captured with (for continuation)
+    int captured;                   // levels recorded in the graph
+    int top;                        // last level any dataset may need (PC_MAX_LEVEL + 1 = planning)
 };
 
 namespace {
@@ -69,6 +73,7 @@ pc_options defaults() {
     o.grid = 0;
     o.timing = 0;
     o.recheck_cap = 0;
+    o.graph_levels = 0;
     return o;
 }
 
@@ -76,10 +81,19 @@ bool valid_options(const pc_options &o) {
     if (o.precision < PC_PREC_FP64 || o.precision > PC_PREC_BF16X3) return false;
     if (!(o.margin_scale >= 1.0f)) return false;
     if (o.lds_budget < 0 || o.ranks_per_lane < 0 || o.grid < 0 || o.recheck_cap < 0) return false;
+    if (o.graph_levels < 0 || o.graph_levels > PC_MAX_LEVEL) return false;
     return true;
 }
 
-int64_t rq_cap_of(const pc_options &o) { return o.recheck_cap > 0 ? o.recheck_cap : (int64_t)1 << 20; }
+// Re-check queue capacity: the option, else sum of n^2 / 4 over the batch within [2^16, 2^25]
+// (a level's tests grow with the pairs; borderline ones are a small fraction of them, largest
+// with BF16x3, whose split error dominates its band).
+int64_t rq_cap_of(const pc_options &o, double sum_n2) {
+    if (o.recheck_cap > 0) return o.recheck_cap;
+    return std::min<int64_t>((int64_t)1 << 25, std::max<int64_t>((int64_t)1 << 16, (int64_t)(sum_n2 / 4.0)));
+}
+
+int graph_levels_of(const pc_options &o) { return o.graph_levels > 0 ? o.graph_levels : 10; }
 
 // Standard normal CDF from erfc, and its inverse by Halley's method started from the rational
 // approximation of Abramowitz & Stegun 26.2.23 (|error| < 4.5e-4); a few Halley steps reach full
@@ -110,9 +124,18 @@ double tau_of(double z, double m, int level) {
 // by 1): FP32 rounding of Z (2u) plus sequential FP32 accumulation of mp terms (mp u); for the
 // three BF16 products also the dropped lo*lo term and the split residuals (3 * 2^-18) over 3 mp
 // accumulated terms.
+// Bound on |C_low - C_64| for unit-norm standardized columns (every sum of |products| is <= 1 by
+// Cauchy-Schwarz). The correlation kernel accumulates blocks of 16 (FP32) or 32 (BF16) samples
+// from zero and adds the blocks with compensated summation, so:
+//   FP32:   rounding Z to FP32 (2u per product), at most 2 roundings per product inside a block of
+//           16 (32u), compensated summation of the blocks (2u), the stored FP32 value (u): 37u.
+//   BF16x3: the dropped terms of z = hi + lo + r (|lo| <= 2^-8 |z|, |r| <= 2^-16 |z|):
+//           lo*lo + hi*r + r*hi <= (3 + 2^-7) 2^-16; one block of 32 samples x 3 products with 2
+//           roundings each (192u), compensated summation (2u), the stored value (u).
 double eps_c_of(int prec, int64_t mp) {
-    if (prec == PC_PREC_FP32) return ((double)mp + 4.0) * kU32;
-    if (prec == PC_PREC_BF16X3) return 3.0 * std::ldexp(1.0, -18) + (3.0 * (double)mp + 8.0) * kU32;
+    (void)mp;
+    if (prec == PC_PREC_FP32) return 37.0 * kU32;
+    if (prec == PC_PREC_BF16X3) return (3.0 + std::ldexp(1.0, -7)) * std::ldexp(1.0, -16) + 195.0 * kU32;
     return 0.0;
 }
 
@@ -148,7 +171,6 @@ Plan make_plan(const int64_t *ns, const int64_t *ms, int count, const pc_options
     Plan L;
     L.count = count;
     L.prec = o.precision;
-    L.rq_cap = rq_cap_of(o);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
     L.st = take(sizeof(DevState));
@@ -170,6 +192,9 @@ Plan make_plan(const int64_t *ns, const int64_t *ms, int count, const pc_options
     L.cs_blocks = L.cs_base[count];
     L.st_blocks = L.st_base[count];
     L.tiles = L.tile_base[count];
+    double sum_n2 = 0.0;
+    for (int d = 0; d < count; ++d) sum_n2 += (double)ns[d] * (double)ns[d];
+    L.rq_cap = rq_cap_of(o, sum_n2);
     L.nitems = take(sizeof(long long) * (size_t)L.total_rows);
     L.item_off = take(sizeof(long long) * (size_t)(L.total_rows + 1));
     L.rq = take(sizeof(RqEntry) * (size_t)L.rq_cap);
@@ -302,7 +327,10 @@ pc_status upload_table(pc_ctx *ctx, const Plan &L, unsigned char *ws, const std:
 
 int auto_grid(const pc_ctx *ctx) { return ctx->opt.grid > 0 ? ctx->opt.grid : 2 * ctx->num_cu; }
 
+// Conditioning-set ranks per work item. Levels up to kFastLevels give every thread its own sets;
+// deeper levels give every wavefront one set at a time, so their items are much smaller.
 int ranks_per_item(const pc_ctx *ctx, int level) {
+    if (level > kFastLevels) return 4 * (ctx->opt.ranks_per_lane > 0 ? ctx->opt.ranks_per_lane : 4);
     const int q = ctx->opt.ranks_per_lane > 0 ? ctx->opt.ranks_per_lane : (level == 1 ? 1 : 4);
     return q * kLevelThreads;
 }
@@ -310,7 +338,7 @@ int ranks_per_item(const pc_ctx *ctx, int level) {
 int level_lds_bytes(const pc_ctx *ctx) {
     const size_t fixed = level_lds_fixed(ctx->opt.precision);
     size_t budget = (size_t)ctx->opt.lds_budget;
-    const size_t limit = 64 * 1024 - 1024 - fixed;  // stay within 64 KiB of dynamic LDS
+    const size_t limit = 60 * 1024 - fixed;  // with the kernel's static staging, within 64 KiB
     if (budget > limit) budget = limit;
     return (int)(fixed + budget);
 }
@@ -339,15 +367,23 @@ struct OrderRun {
 
 constexpr int kProbeMaxLevel = 8;
 
-// Compaction, planning, (probe pass,) CI tests and FP64 re-check of one level.
-pc_status enqueue_level(pc_ctx *ctx, const Batch &b, int level, bool capturing, const OrderRun *ord = nullptr) {
+// Compaction and planning of one level: the snapshot G' and the work plan (and the stop rule's
+// maximum degree) of every problem. Level PC_MAX_LEVEL + 1 is planned only, to tell whether the
+// level cap stopped a run.
+pc_status enqueue_plan(pc_ctx *ctx, const Batch &b, int level, bool capturing) {
     hipStream_t s = ctx->stream;
     const int R = ranks_per_item(ctx, level <= PC_MAX_LEVEL ? level : PC_MAX_LEVEL);
     if (timed(ctx, 4, capturing)) PC_HIP(hipEventRecord(ctx->ev_compact[level][0], s));
     PC_HIP(launch_compact(s, b, level, R));
     PC_HIP(launch_plan(s, b, level));
     if (timed(ctx, 4, capturing)) PC_HIP(hipEventRecord(ctx->ev_compact[level][1], s));
-    if (level > PC_MAX_LEVEL) return PC_OK;  // planning only: tells whether the cap stopped a run
+    return PC_OK;
+}
+
+// (Probe pass,) CI tests and FP64 re-check of a planned level.
+pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, const OrderRun *ord) {
+    hipStream_t s = ctx->stream;
+    const int R = ranks_per_item(ctx, level);
     if (ord && level >= ord->order->min_level && level <= kProbeMaxLevel) {
         const Plan &L = *ord->L;
         long long *foff = reinterpret_cast<long long *>(ord->ws + L.foff);
@@ -366,6 +402,51 @@ pc_status enqueue_level(pc_ctx *ctx, const Batch &b, int level, bool capturing, 
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][0], s));
     PC_HIP(launch_recheck(s, b, level, 4 * ctx->num_cu));
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][1], s));
+    ctx->top_run = std::max(ctx->top_run, level);
+    return PC_OK;
+}
+
+// Compaction, planning, (probe pass,) CI tests and FP64 re-check of one level.
+pc_status enqueue_level(pc_ctx *ctx, const Batch &b, int level, bool capturing, const OrderRun *ord = nullptr) {
+    pc_status st = enqueue_plan(ctx, b, level, capturing);
+    if (st != PC_OK || level > PC_MAX_LEVEL) return st;
+    return enqueue_run(ctx, b, level, capturing, ord);
+}
+
+// Copies the problem table and queue state back (synchronising the stream).
+pc_status read_table(pc_ctx *ctx, const Plan &L, unsigned char *ws, std::vector<Prob> &host, DevState &ds) {
+    host.resize(L.count);
+    PC_HIP(hipMemcpyAsync(host.data(), ws + L.table, sizeof(Prob) * L.count, hipMemcpyDeviceToHost, ctx->stream));
+    PC_HIP(hipMemcpyAsync(&ds, ws + L.st, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
+    PC_HIP(hipStreamSynchronize(ctx->stream));
+    return PC_OK;
+}
+
+// Levels from..top on the stream, level `from` already planned. The stop rule runs on the device;
+// the host only bounds how far to enqueue: degrees never grow, so a problem whose G' at level l has
+// maximum degree D needs no level past D - 1. The bound is read after planning `from` and, on long
+// runs, again every few levels.
+pc_status run_levels_eager(pc_ctx *ctx, const Batch &b, const Plan &L, unsigned char *ws, int from, int top,
+                           const OrderRun *ord) {
+    std::vector<Prob> host;
+    DevState ds;
+    int l = from;
+    while (l <= top) {
+        pc_status s = read_table(ctx, L, ws, host, ds);
+        if (s != PC_OK) return s;
+        if (ds.done) break;
+        int last = 0;
+        for (const Prob &P : host) {
+            const int md = P.maxdeg[l];
+            if (md - 1 >= l) last = std::max(last, std::min(std::min(P.max_level, PC_MAX_LEVEL + 1), md - 1));
+        }
+        if (last < l) break;
+        const int upto = std::min(top, last - l >= 6 ? l + 3 : last);
+        for (; l <= upto; ++l) {
+            if (l <= PC_MAX_LEVEL && (s = enqueue_run(ctx, b, l, false, ord)) != PC_OK) return s;
+            if (l + 1 <= top && (s = enqueue_plan(ctx, b, l + 1, false)) != PC_OK) return s;
+        }
+    }
     return PC_OK;
 }
 
@@ -485,10 +566,22 @@ pc_status enqueue_skeletons(pc_ctx *ctx, const pc_problem *pp, int count, const 
     pc_status s = enqueue_corr(ctx, b, L, capturing);
     if (s != PC_OK) return s;
     const OrderRun ord{order, &L, ws};
+    const OrderRun *po = order ? &ord : nullptr;
     const int top = levels_to_enqueue(pp, count);
-    for (int l = 1; l <= top; ++l)
-        if ((s = enqueue_level(ctx, b, l, capturing, order ? &ord : nullptr)) != PC_OK) return s;
-    return PC_OK;
+    ctx->top_run = 0;
+    if (capturing) {
+        // A graph holds levels 1..G and the planning of G + 1; pc_graph_results continues the rest.
+        const int G = std::min(top, graph_levels_of(ctx->opt));
+        for (int l = 1; l <= G; ++l)
+            if ((s = enqueue_level(ctx, b, l, true, po)) != PC_OK) return s;
+        if (G < top && (s = enqueue_plan(ctx, b, G + 1, true)) != PC_OK) return s;
+        return PC_OK;
+    }
+    if (top < 1) return PC_OK;
+    if ((s = enqueue_level(ctx, b, 1, false, po)) != PC_OK) return s;
+    if (top < 2) return PC_OK;
+    if ((s = enqueue_plan(ctx, b, 2, false)) != PC_OK) return s;
+    return run_levels_eager(ctx, b, L, ws, 2, top, po);
 }
 
 bool valid_order(const pc_order *o) {
@@ -701,7 +794,7 @@ pc_status pc_skeleton(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double
     const pc_status r = collect(ctx, L.table, L.st, 1, w, st, &status, host);
     if (r == PC_ERR_HIP) return r;
     if (st) {
-        fill_times(ctx, st, levels_to_enqueue(&p, 1));
+        fill_times(ctx, st, ctx->top_run);
         st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;
@@ -741,6 +834,9 @@ pc_status pc_batch_capture(pc_ctx *ctx, const pc_problem *probs, int count, void
     g->count = count;
     g->table_off = L.table;
     g->st_off = L.st;
+    g->probs.assign(probs, probs + count);
+    g->top = levels_to_enqueue(probs, count);
+    g->captured = std::min(g->top, graph_levels_of(ctx->opt));
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) { delete g; return PC_ERR_HIP; }
     if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         delete g;
@@ -772,8 +868,16 @@ pc_status pc_graph_launch(pc_graph *g) {
 
 pc_status pc_graph_results(pc_graph *g, pc_run_stats *st, pc_status *status) {
     if (!g) return PC_ERR_INVALID_ARG;
+    pc_ctx *ctx = g->ctx;
+    if (g->captured < g->top) {
+        // Datasets that still have work after the recorded levels continue on the stream.
+        const Plan L = plan_of(g->probs.data(), g->count, ctx->opt);
+        const Batch b = make_batch(ctx, L, g->ws);
+        pc_status s = run_levels_eager(ctx, b, L, g->ws, g->captured + 1, g->top, nullptr);
+        if (s != PC_OK) return s;
+    }
     std::vector<Prob> host;
-    return collect(g->ctx, g->table_off, g->st_off, g->count, g->ws, st, status, host);
+    return collect(ctx, g->table_off, g->st_off, g->count, g->ws, st, status, host);
 }
 
 void pc_graph_destroy(pc_graph *g) {
@@ -817,7 +921,7 @@ pc_status pc_skeleton_ordered(pc_ctx *ctx, const double *X, int64_t m, int64_t n
     const pc_status r = collect(ctx, L.table, L.st, 1, w, st, &status, host);
     if (r == PC_ERR_HIP) return r;
     if (st) {
-        fill_times(ctx, st, levels_to_enqueue(&p, 1));
+        fill_times(ctx, st, ctx->top_run);
         st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;

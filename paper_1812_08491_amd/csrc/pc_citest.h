@@ -25,6 +25,14 @@ __device__ inline bool take_edge(unsigned long long *adj, int64_t W, int lo, int
     return true;
 }
 
+// Writes one SepSet record: (lo, hi, level) and S[0..level), the rest -1.
+__device__ inline void store_record(pc_sep_rec *rec, int lo, int hi, int level, const int *S) {
+    rec->i = lo;
+    rec->j = hi;
+    rec->level = level;
+    for (int c = 0; c < PC_MAX_LEVEL; ++c) rec->S[c] = c < level ? S[c] : -1;
+}
+
 // Appends the SepSet record of the removed edge (lo, hi). The lanes of a wavefront that reach this
 // call together take consecutive slots with a single atomic add by the lowest of them, which keeps
 // the shared counter from serialising one device-scope atomic per removal. All active lanes must
@@ -38,13 +46,7 @@ __device__ inline void write_record(const Prob &P, int lo, int hi, int level, co
         base = atomicAdd(reinterpret_cast<unsigned long long *>(P.rec_count), (unsigned long long)__popcll(act));
     base = __shfl(base, leader, 64);
     const long long k = (long long)(base + (unsigned long long)__popcll(act & ((1ull << lane) - 1ull)));
-    if (k < P.rec_cap) {
-        pc_sep_rec *rec = P.recs + k;
-        rec->i = lo;
-        rec->j = hi;
-        rec->level = level;
-        for (int c = 0; c < PC_MAX_LEVEL; ++c) rec->S[c] = c < level ? S[c] : -1;
-    }
+    if (k < P.rec_cap) store_record(P.recs + k, lo, hi, level, S);
 }
 
 // Pushes a test to the re-check queue; cls is the FP32 classification (0 dependent, 1 independent,
@@ -62,7 +64,7 @@ __device__ inline void push_recheck(const Batch &b, int d, int row, int j, const
     e->j = j;
     e->cls = cls;
 #pragma unroll
-    for (int c = 0; c < PC_MAX_LEVEL; ++c) e->S[c] = c < L ? sid[c] : -1;
+    for (int c = 0; c < PC_MAX_LEVEL; ++c) e->S[c] = c < L ? (uint16_t)sid[c] : (uint16_t)0xffff;
 }
 
 // Factor of M2 = C[S,S] for one S (positions P into the row's neighbour list), shared by all j.
@@ -153,12 +155,21 @@ struct SetFactor {
             const double rho = (h11 > 0 && h22 > 0) ? (double)h12 / sqrt((double)h11 * (double)h22) : 0.0;
             return fisher_z64(rho) <= tau ? 1 : 0;
         }
+        // Errors dC in the entries of C move H12 by up to dC (1 + |M2^-1 c_iS|_1)(1 + |M2^-1 c_jS|_1)
+        // and H11, H22 by the squares. At l = 1 (M2 = [1]) these factors are 1 + |C_ik| and
+        // 1 + |C_jk| exactly; above, g bounds both.
+        float gi2 = g2, gj2 = g2, gij = g2;
+        if (L == 1) {
+            const float gi = 1.0f + fabsf((float)y[0]), gj = 1.0f + fabsf((float)w[0]);
+            gi2 = gi * gi;
+            gj2 = gj * gj;
+            gij = gi * gj;
+        }
         const float fh11 = (float)h11, fh22 = (float)h22;
-        const float floor_ = 2.0f * band * g2;
-        if (!ok || fh11 <= floor_ || fh22 <= floor_) return 2;
+        if (!ok || fh11 <= 2.0f * band * gi2 || fh22 <= 2.0f * band * gj2) return 2;
         const float inv = rsqrtf(fh11 * fh22);
         const float ar = fabsf((float)h12 * inv);
-        const float err = band * g2 * (inv + 0.5f * ar * (1.0f / fh11 + 1.0f / fh22));
+        const float err = band * (gij * inv + 0.5f * ar * (gi2 / fh11 + gj2 / fh22));
         return ar <= tl - err ? 1 : (ar > tl + err ? 0 : 2);
     }
 };

@@ -215,19 +215,44 @@ __global__ __launch_bounds__(256) void k_corr(Batch bt) {
     if (tid < kT) { rowbits[tid] = 0ull; colbits[tid] = 0ull; }
     if (tid == 0) { bcount = 0; wg_removed = 0; wg_rechecks = 0; }
 
-    acc_t acc[2][2];
+    // FP32 / BF16x3: the MFMA accumulator holds one block of BK samples at a time (from zero),
+    // and the blocks are added with compensated (two-sum) summation, so the rounding error of C
+    // grows with the block length instead of with m.
+    acc_t acc[2][2], sum[2][2], cmp[2][2];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int nj = 0; nj < 2; ++nj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[mi][nj][v] = 0;
+            for (int v = 0; v < 4; ++v) acc[mi][nj][v] = sum[mi][nj][v] = cmp[mi][nj][v] = 0;
 
     for (int64_t k0 = 0; k0 < a.mp; k0 += BK) {
         load_tiles<PREC>(sm, ops, a0, b0, k0, tid);
         __syncthreads();
         mma_step<PREC>(sm, acc, lane, wr, wc);
+        if constexpr (PREC != PC_PREC_FP64) {
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float x = acc[mi][nj][v], s0 = sum[mi][nj][v];
+                        const float t = s0 + x, bp = t - s0;
+                        cmp[mi][nj][v] += (s0 - (t - bp)) + (x - bp);
+                        sum[mi][nj][v] = t;
+                        acc[mi][nj][v] = 0.0f;
+                    }
+        }
         __syncthreads();
+    }
+    if constexpr (PREC != PC_PREC_FP64) {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[mi][nj][v] = sum[mi][nj][v] + cmp[mi][nj][v];
     }
 
     // Epilogue: store C (tile and mirror), level-0 decisions, adjacency bits.

@@ -18,6 +18,8 @@ constexpr int kBinomCols = PC_MAX_LEVEL + 2;          // C(a, b) for b = 0 .. PC
 constexpr unsigned long long kSat = 1ull << 62;       // saturation value of the binomial table
 constexpr int kLevelThreads = 256;                    // threads of a level work-group
 constexpr int kGramLd = PC_MAX_LEVEL + 2;             // leading dimension of an FP64 Gram block
+constexpr int kFastLevels = 13;    // levels whose per-set factor lives in registers (k_level);
+                                   // deeper levels factor each set across a wavefront
 
 // 64-bit signed counter add (two's complement, so the unsigned atomic is exact).
 __device__ inline void add_ll(long long *p, long long v) {
@@ -94,9 +96,10 @@ struct DevState {
 // whose M2 is rank deficient).
 struct RqEntry {
     int prob, i, j, cls;           // cls: FP32 class (0 dependent, 1 independent, 2 in the band)
-    int S[PC_MAX_LEVEL];
-    int pad[3];
+    uint16_t S[PC_MAX_LEVEL];      // variable ids (n <= 65536)
+    uint16_t pad[(8 - PC_MAX_LEVEL % 8) % 8];
 };
+static_assert(sizeof(RqEntry) % 16 == 0, "queue entries stay 16-byte aligned");
 
 // Flattened index tables and shared buffers of a batch (passed by value to every kernel).
 struct Batch {

@@ -187,7 +187,9 @@ hipError_t launch_plan(hipStream_t s, const Batch &b, int level) {
 
 // Per-wave FP64 scratch of the re-check path, kept in LDS (runtime-sized small matrices).
 constexpr int kMM = PC_MAX_LEVEL * PC_MAX_LEVEL;
-constexpr int kWork = 4 * kMM + 2 * PC_MAX_LEVEL;   // Lm, a, v, P, y, w
+constexpr int kWork = 4 * kMM + 2 * PC_MAX_LEVEL;   // Lm, a, v, P, y, w (levels up to PC_MAX_LEVEL)
+constexpr int kMMs = 14 * 14;                       // the same for levels up to 14 (16 variables)
+constexpr int kWorks = 4 * kMMs + 2 * 14;
 
 // Moore-Penrose inverse of the symmetric k x k block A (row stride lda) by cyclic Jacobi
 // rotations (Sec. 4.4 asks for a pseudo-inverse of M2; the eigen route gives the same unique
@@ -247,12 +249,12 @@ __device__ void pinv_jacobi(const double *A, int lda, int k, double *a, double *
 // G: (l+2) x (l+2) correlation block over (i, j, S...), row stride ld. Returns 1 iff the Fisher z
 // of rho(i,j|S) (Eq. 3-5) is <= tau. Rules: M2 through its Cholesky factor unless a pivot is
 // <= 1e-12 * max diag(M2), then through its pseudo-inverse; H11 <= 0 or H22 <= 0 gives rho = 0.
-// work: kWork doubles of scratch.
-__device__ int decide_gram64(const double *G, int ld, int l, double tau, double *work) {
+// work: 4 mm + 2 l doubles of scratch, mm >= l * l.
+__device__ int decide_gram64(const double *G, int ld, int l, double tau, double *work, int mm) {
     double h11 = 1.0, h22 = 1.0, h12 = G[1];
     if (l > 0) {
-        double *Lm = work, *a = work + kMM, *v = work + 2 * kMM, *P = work + 3 * kMM;
-        double *y = work + 4 * kMM, *w = y + PC_MAX_LEVEL;
+        double *Lm = work, *a = work + mm, *v = work + 2 * mm, *P = work + 3 * mm;
+        double *y = work + 4 * mm, *w = y + l;
         const double *M2 = G + 2 * ld + 2;
         double maxdiag = 0.0;
         for (int r = 0; r < l; ++r) maxdiag = fmax(maxdiag, M2[r * ld + r]);
@@ -303,6 +305,7 @@ __device__ int decide_gram64(const double *G, int ld, int l, double tau, double 
 // ---------------------------------------------------------------------------------------------
 // Level kernel
 // ---------------------------------------------------------------------------------------------
+constexpr int kStageCap = kLevelThreads;   // removals staged per item (one settling thread each)
 constexpr int kDcap = 1024;   // neighbour lists up to this degree are staged in LDS
 constexpr int kWcap = 256;    // live-bit words of a row staged in LDS (n <= 16384)
 
@@ -326,6 +329,12 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
     __shared__ long long s_grow, s_r0;
     __shared__ int s_mode;  // bit 0: nb/ci in LDS, bit 1: C[N_i,N_i] in LDS, bit 2: live bits in LDS
     __shared__ long long s_tests, s_removed;
+    // Removals found while testing are staged here and settled at the end of the item, so a
+    // wavefront never waits on a device-scope atomic inside the test loop.
+    __shared__ int s_nstage, s_nwin;
+    __shared__ int s_stage_j[kStageCap];
+    __shared__ unsigned long long s_stage_t[kStageCap];
+    __shared__ unsigned long long s_rec_base;
 
     DevState *st = b.st;
     if (st->done) return;
@@ -339,7 +348,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
     const long long blk_cap = ((long long)lds_bytes - (long long)lds_fixed_bytes<T>()) / (long long)sizeof(T);
     const TableBinom binom{b.binom};
 
-    if (tid == 0) { s_tests = 0; s_removed = 0; }
+    if (tid == 0) { s_tests = 0; s_removed = 0; s_nstage = 0; s_nwin = 0; }
     long long staged = -1, last_row = 0;
     int d = 0, stats_pd = -1;
     long long my_tests = 0, my_removed = 0;
@@ -506,12 +515,58 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                 if (dec == 2) {
                     push_recheck<L>(b, pd, row, j, sid, 2);
                 } else if (dec == 1) {
-                    const int lo = row < j ? row : j, hi = row < j ? j : row;
-                    if (take_edge(P.adj, W, lo, hi)) {
-                        ++my_removed;
-                        write_record(P, lo, hi, L, sid);
+                    const int slot = atomicAdd(&s_nstage, 1);
+                    if (slot < kStageCap) {
+                        s_stage_j[slot] = j;
+                        s_stage_t[slot] = (unsigned long long)t;
+                    } else {
+                        const int lo = row < j ? row : j, hi = row < j ? j : row;
+                        if (take_edge(P.adj, W, lo, hi)) {
+                            ++my_removed;
+                            write_record(P, lo, hi, L, sid);
+                        }
                     }
                     if (mode & 4) atomicAnd(&lds_live[j >> 6], ~(1ull << (j & 63)));
+                }
+            }
+        }
+        // Settle the staged removals: every ticket is taken at once (one thread each), the
+        // winners get consecutive SepSet slots from one atomic add, and re-derive S from its rank.
+        __syncthreads();
+        const int nst = s_nstage < kStageCap ? s_nstage : kStageCap;
+        if (nst > 0) {
+            int myslot = -1, sj = 0;
+            unsigned long long srank = 0;
+            if (tid < nst) {
+                sj = s_stage_j[tid];
+                srank = s_stage_t[tid];
+                const int lo = row < sj ? row : sj, hi = row < sj ? sj : row;
+                if (take_edge(P.adj, W, lo, hi)) {
+                    ++my_removed;
+                    myslot = atomicAdd(&s_nwin, 1);
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const int nw = s_nwin;
+                s_rec_base = nw ? atomicAdd(reinterpret_cast<unsigned long long *>(P.rec_count),
+                                            (unsigned long long)nw)
+                                : 0ull;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                s_nstage = 0;
+                s_nwin = 0;
+            }
+            if (myslot >= 0) {
+                const long long k = (long long)(s_rec_base + (unsigned long long)myslot);
+                if (k < P.rec_cap) {
+                    int Q[L];
+                    comb_unrank<L>(d, srank, Q, binom);
+                    int qs[L];
+#pragma unroll
+                    for (int c = 0; c < L; ++c) qs[c] = NB(Q[c]);
+                    store_record(P.recs + k, row < sj ? row : sj, row < sj ? sj : row, L, qs);
                 }
             }
         }
@@ -527,9 +582,261 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
     if (tid == 0 && stats_pd >= 0) flush_stats<L>(b.probs[stats_pd], s_tests, s_removed);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Deep levels (l > kFastLevels): one conditioning set per wavefront
+// ---------------------------------------------------------------------------------------------
+constexpr int kDeepWaves = kLevelThreads / 64;
+
+// Orders the LDS accesses of the lanes of one wavefront around a cooperative step.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Same work items as k_level (rows and ranges of conditioning-set ranks), but a register-resident
+// factor per thread does not fit beyond kFastLevels, so each wavefront takes one set S at a time:
+// M2 = C[S,S] is staged in LDS and factored (FP64 Cholesky, lanes splitting each column and the
+// trailing update), y = L^-1 C[S,i] and H11 follow, and the lanes then test the candidates j of
+// the row against that factor (Eq. 3-6). Tests whose decision the FP32 C leaves open, or whose M2
+// has a pivot below the tolerance, go to the FP64 re-check queue.
+template <typename T, int L>
+__global__ __launch_bounds__(kLevelThreads) void k_level_deep(Batch b, int R) {
+    __shared__ long long s_grow, s_r0;
+    __shared__ long long s_tests, s_removed;
+    __shared__ int s_mode;
+    __shared__ int s_nb[kDcap];
+    __shared__ T s_ci[kDcap];
+    __shared__ unsigned long long s_live[kWcap];
+    __shared__ int s_P[kDeepWaves][L];
+    __shared__ double s_y[kDeepWaves][L];
+    __shared__ double s_M[kDeepWaves][L][L + 1];
+
+    DevState *st = b.st;
+    if (st->done) return;
+    const unsigned long long total = st->total_items;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const TableBinom binom{b.binom};
+    if (tid == 0) { s_tests = 0; s_removed = 0; }
+    long long staged = -1, last_row = 0;
+    int d = 0, stats_pd = -1;
+    long long my_tests = 0, my_removed = 0;
+    bool first = true;
+    double (*M)[L + 1] = s_M[wave];
+    int *PS = s_P[wave];
+    double *yv = s_y[wave];
+
+    for (;;) {
+        __syncthreads();
+        if (tid < 64) {
+            unsigned long long g = blockIdx.x;
+            if (!first && tid == 0) g = gridDim.x + atomicAdd(&st->next_item, 1ull);
+            g = __shfl(g, 0, 64);
+            if (g >= total) {
+                if (tid == 0) s_grow = -1;
+            } else {
+                long long lo = last_row, hi = b.total_rows;
+                while (hi - lo > 1) {
+                    const long long step = (hi - lo + 63) / 64;
+                    const long long idx = lo + (long long)tid * step;
+                    const bool okb = idx < hi && (unsigned long long)b.item_off[idx] <= g;
+                    const unsigned long long mask = __ballot(okb);
+                    const int top = 63 - __clzll((long long)mask);
+                    lo = lo + (long long)top * step;
+                    hi = lo + step < hi ? lo + step : hi;
+                }
+                if (tid == 0) {
+                    s_grow = lo;
+                    s_r0 = (long long)(g - (unsigned long long)b.item_off[lo]) * R;
+                }
+            }
+        }
+        __syncthreads();
+        first = false;
+        const long long grow = s_grow;
+        if (grow < 0) break;
+        last_row = grow;
+        const int pd = find_base(b.row_base, b.count, grow);
+        if (pd != stats_pd) {
+            if (tid == 0 && stats_pd >= 0) flush_stats<L>(b.probs[stats_pd], s_tests, s_removed);
+            stats_pd = pd;
+        }
+        const Prob &P = b.probs[pd];
+        const int64_t n = P.n, W = P.W;
+        const int row = (int)(grow - b.row_base[pd]);
+        const T *C = static_cast<const T *>(P.C);
+        unsigned long long *adj_row = P.adj + (int64_t)row * W;
+        if (grow != staged) {
+            d = P.deg[row];
+            const bool nb_lds = d <= kDcap;
+            if (nb_lds)
+                for (int p = tid; p < d; p += kLevelThreads) {
+                    const int k = P.nbr[(int64_t)row * n + p];
+                    s_nb[p] = k;
+                    s_ci[p] = C[(int64_t)row * n + k];
+                }
+            if (tid == 0) s_mode = (nb_lds ? 1 : 0) | (W <= kWcap ? 4 : 0);
+            staged = grow;
+        }
+        if (W <= kWcap)
+            for (int w = tid; w < W; w += kLevelThreads) s_live[w] = live_word(adj_row + w);
+        __syncthreads();
+        const int mode = s_mode;
+        const int *nbg = P.nbr + (int64_t)row * n;
+        auto NB = [&](int p) -> int { return (mode & 1) ? s_nb[p] : nbg[p]; };
+        auto CI = [&](int p) -> double { return (double)((mode & 1) ? s_ci[p] : C[(int64_t)row * n + nbg[p]]); };
+        auto CS = [&](int p, int q) -> double { return p == q ? 1.0 : (double)C[(int64_t)NB(p) * n + NB(q)]; };
+        auto LIVE = [&](int j) -> bool {
+            const unsigned long long wv = (mode & 4) ? s_live[j >> 6] : live_word(adj_row + (j >> 6));
+            return (wv >> (j & 63)) & 1ull;
+        };
+        const double tau = P.tau[L];
+        const double tl = tanh(tau);
+        const double band = (double)P.band[L];
+        const double tol = sizeof(T) == 8 ? 1e-12 : 1e-4;
+
+        const unsigned long long nS = binom(d, L);
+        const long long r0 = s_r0;
+        const long long r1 = (long long)nS < r0 + R ? (long long)nS : r0 + R;
+        for (long long t = r0 + wave; t < r1; t += kDeepWaves) {
+            int Q[L];
+            comb_unrank<L>(d, (unsigned long long)t, Q, binom);
+            if (lane == 0) {
+#pragma unroll
+                for (int c = 0; c < L; ++c) PS[c] = Q[c];
+            }
+            wave_sync();
+            for (int e = lane; e < L * L; e += 64) {
+                const int r = e / L, c = e - r * L;
+                if (c <= r) M[r][c] = CS(PS[r], PS[c]);
+            }
+            wave_sync();
+            // Right-looking Cholesky in place (lower triangle).
+            bool ok = true;
+            for (int c = 0; c < L; ++c) {
+                const double piv = M[c][c];
+                ok = ok && piv > tol;
+                const double pv = piv > tol ? piv : 1.0;
+                const double rd = 1.0 / sqrt(pv);
+                wave_sync();
+                if (lane == 0) M[c][c] = sqrt(pv);
+                for (int r = c + 1 + lane; r < L; r += 64) M[r][c] *= rd;
+                wave_sync();
+                const int q = L - c - 1;
+                for (int e = lane; e < q * q; e += 64) {
+                    const int r = c + 1 + e / q, k = c + 1 + e % q;
+                    if (k <= r) M[r][k] -= M[r][c] * M[k][c];
+                }
+                wave_sync();
+            }
+            // X = L^-1 by columns (lane k solves L x = e_k), written over the factor; its squared
+            // Frobenius norm is tr(M2^-1) for the FP32 error factor g = 1 + sqrt(l tr(M2^-1)).
+            double tr = 0.0;
+            {
+                double x[L];
+#pragma unroll
+                for (int r = 0; r < L; ++r) {
+                    double a = r == lane ? 1.0 : 0.0;
+#pragma unroll
+                    for (int e = 0; e < r; ++e) a -= M[r][e] * x[e];
+                    x[r] = lane < L ? a / M[r][r] : 0.0;
+                    tr += x[r] * x[r];
+                }
+                wave_sync();
+                if (lane < L) {
+#pragma unroll
+                    for (int r = 0; r < L; ++r)
+                        if (r >= lane) M[r][lane] = x[r];
+                }
+                wave_sync();
+            }
+            tr = wave_sum64(tr);
+            const double gf = 1.0 + sqrt((double)L * tr);
+            const double g2 = sizeof(T) == 4 ? gf * gf : 4.0;
+            // y = X C[S,i] (lane r takes row r), H11 = 1 - |y|^2.
+            if (lane < L) {
+                double a = 0.0;
+                for (int e = 0; e <= lane; ++e) a += M[lane][e] * CI(PS[e]);
+                yv[lane] = a;
+            }
+            wave_sync();
+            double yy = 0.0;
+            for (int r = 0; r < L; ++r) yy += yv[r] * yv[r];
+            const double h11 = 1.0 - yy;
+            for (int p = lane; p < d; p += 64) {
+                bool inS = false;
+#pragma unroll
+                for (int c = 0; c < L; ++c) inS |= Q[c] == p;
+                if (inS) continue;
+                const int j = NB(p);
+                if (!LIVE(j)) continue;
+                ++my_tests;
+                // w = X C[S,j] row by row: H22 = 1 - |w|^2, H12 = C_ij - y.w.
+                T cj[L];
+#pragma unroll
+                for (int e = 0; e < L; ++e) cj[e] = (T)CS(p, Q[e]);
+                double ww = 0.0, yw = 0.0;
+#pragma unroll
+                for (int r = 0; r < L; ++r) {
+                    double a = 0.0;
+#pragma unroll
+                    for (int e = 0; e <= r; ++e) a += M[r][e] * (double)cj[e];
+                    ww += a * a;
+                    yw += yv[r] * a;
+                }
+                const double h22 = 1.0 - ww, h12 = CI(p) - yw;
+                int dec;
+                if (!ok) {
+                    dec = 2;
+                } else if (sizeof(T) == 8) {
+                    const double rho = (h11 > 0.0 && h22 > 0.0) ? h12 / sqrt(h11 * h22) : 0.0;
+                    dec = fisher_z64(rho) <= tau ? 1 : 0;
+                } else {
+                    // FP64 arithmetic on FP32 entries of C: the band only covers C's own error.
+                    const double fl = 2.0 * band * g2;
+                    if (h11 <= fl || h22 <= fl) {
+                        dec = 2;
+                    } else {
+                        const double inv = 1.0 / sqrt(h11 * h22), ar = fabs(h12) * inv;
+                        const double err = band * g2 * (inv + 0.5 * ar * (1.0 / h11 + 1.0 / h22));
+                        dec = ar <= tl - err ? 1 : (ar > tl + err ? 0 : 2);
+                    }
+                }
+                if (dec == 1 && !(sizeof(T) == 4 && b.force_recheck)) {
+                    const int lo = row < j ? row : j, hi = row < j ? j : row;
+                    if (take_edge(P.adj, W, lo, hi)) {
+                        int sid[L];
+#pragma unroll
+                        for (int c = 0; c < L; ++c) sid[c] = NB(Q[c]);
+                        ++my_removed;
+                        write_record(P, lo, hi, L, sid);
+                    }
+                    if (mode & 4) atomicAnd(&s_live[j >> 6], ~(1ull << (j & 63)));
+                } else if (dec == 2 || (sizeof(T) == 4 && b.force_recheck)) {
+                    int sid[L];
+#pragma unroll
+                    for (int c = 0; c < L; ++c) sid[c] = NB(Q[c]);
+                    push_recheck<L>(b, pd, row, j, sid, dec);
+                }
+            }
+            wave_sync();
+        }
+        const long long wt = wave_sum_ll(my_tests), wr = wave_sum_ll(my_removed);
+        if (lane == 0) {
+            if (wt) add_ll(&s_tests, wt);
+            if (wr) add_ll(&s_removed, wr);
+        }
+        my_tests = 0;
+        my_removed = 0;
+    }
+    if (tid == 0 && stats_pd >= 0) flush_stats<L>(b.probs[stats_pd], s_tests, s_removed);
+}
+
 template <typename T, int L>
 static hipError_t launch_level_t(hipStream_t s, const Batch &b, int R, int lds_bytes, int grid) {
-    hipLaunchKernelGGL((k_level<T, L>), dim3(grid), dim3(kLevelThreads), lds_bytes, s, b, R, lds_bytes);
+    if constexpr (L <= kFastLevels)
+        hipLaunchKernelGGL((k_level<T, L>), dim3(grid), dim3(kLevelThreads), lds_bytes, s, b, R, lds_bytes);
+    else
+        hipLaunchKernelGGL((k_level_deep<T, L>), dim3(grid), dim3(kLevelThreads), 0, s, b, R);
     return hipGetLastError();
 }
 
@@ -564,27 +871,134 @@ constexpr int kRcThreads = 256;            // re-check work-group: 4 wavefronts 
 constexpr int kRcChunk = 16;               // consecutive samples per lane per round
 constexpr int kRcRound = kRcThreads / 16 * kRcChunk;   // samples per round of a work-group (256)
 
-// One work-group per queued test (grid-stride). The FP64 Gram block of the standardized rows
-// (i, j, S) is one 16 x 16 tile Z Z^T accumulated on v_mfma_f64_16x16x4f64: lane l carries row
-// l % 16 of the tile, so the same register is both the A operand (Z) and the B operand (Z^T), and
-// each k-step sums four samples. Each lane holds 16 consecutive samples of its row per round; the
-// four wavefront tiles are added in LDS. Rows l + 2 .. 15 of the tile stay zero.
+// Statistics of the re-checks a worker settled, written once per problem.
+struct RcStats {
+    int cur = -1;
+    long long rc = 0, rm = 0, viol = 0;
+    __device__ void flush(const Batch &b, int l) {
+        if (cur < 0) return;
+        Prob &Pc = b.probs[cur];
+        add_ll(&Pc.rechecks[l], rc);
+        if (rm) add_ll(&Pc.removed[l], rm);
+        if (viol) add_ll(&Pc.audit_viol[l], viol);
+        rc = rm = viol = 0;
+    }
+    __device__ void at(const Batch &b, int l, int prob) {
+        if (prob != cur) {
+            flush(b, l);
+            cur = prob;
+        }
+    }
+};
+
+// Decision and removal of one re-checked test from its FP64 Gram block G (row stride ld).
+__device__ inline void settle_recheck(const Batch &b, Prob &P, int l, const double *G, int ld, double *work,
+                                      int mm, int i, int j, int cls, const int *S, RcStats &rs) {
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    const int res = decide_gram64(G, ld, l, P.tau[l], work, mm);
+    ++rs.rc;
+    if (b.force_recheck && cls != 2 && cls != res) ++rs.viol;
+    // The atomic on the canonical bit decides: an edge another test already removed stays
+    // removed and keeps that test's SepSet.
+    if (res && take_edge(P.adj, P.W, lo, hi)) {
+        ++rs.rm;
+        write_record(P, lo, hi, l, S);
+    }
+}
+
+// Queued tests of levels up to 14 (at most 16 variables): one wavefront per test, grid-stride.
+// The FP64 Gram block of the standardized rows (i, j, S) is one 16 x 16 tile Z Z^T accumulated
+// on v_mfma_f64_16x16x4f64 over all samples: lane l carries row l % 16 (so the same register is
+// both the A operand, Z, and the B operand, Z^T) and 16 consecutive samples per round; each k-step
+// sums four samples. Rows past l + 2 stay zero. On the FP64 path the block is read from C.
 __global__ __launch_bounds__(kRcThreads) void k_recheck(Batch b, int level) {
-    __shared__ double part[kRcThreads / 64][16 * 16];
-    __shared__ double G[kGramLd * kGramLd];
-    __shared__ double work[kWork];
+    constexpr int kW = kRcThreads / 64;
+    __shared__ double G[kW][16 * 16];
+    __shared__ double work[kW][kWorks];
+    __shared__ int s_v[kW][16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const unsigned long long pushed = b.st->rq_count;
     const long long count = pushed < (unsigned long long)b.rq_cap ? (long long)pushed : b.rq_cap;
     const int l = level, k = l + 2;
-    // Work-group totals, written once per problem (thread 0 only).
-    int cur = -1;
-    long long n_rc = 0, n_rm = 0, n_viol = 0;
-    __shared__ int s_v[16];        // variables of the tile rows: i, j, S..., then -1
+    double *Gw = G[wave];
+    int *vw = s_v[wave];
+    RcStats rs;
+    for (long long e = (long long)blockIdx.x * kW + wave; e < count; e += (long long)gridDim.x * kW) {
+        const RqEntry *qe = b.rq + e;
+        if (lane < 16) vw[lane] = lane == 0 ? qe->i : (lane == 1 ? qe->j : (lane < k ? (int)qe->S[lane - 2] : -1));
+        const int prob = qe->prob, cls = qe->cls;
+        wave_sync();
+        Prob &P = b.probs[prob];
+        if (b.prec != PC_PREC_FP64) {
+            const int64_t mp = P.mp;
+            const int vr = vw[lane & 15];
+            const double *z = P.zt64 + (int64_t)(vr < 0 ? 0 : vr) * mp;
+            const int64_t off = (int64_t)(lane >> 4) * kRcChunk;
+            doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+            // Four rounds of 64 samples per step, all loads issued before their products. mp is
+            // a multiple of 64, so a lane's chunk of 16 is either wholly inside or outside.
+            for (int64_t x0 = 0; x0 < mp; x0 += 4 * 64) {
+                double v[4][kRcChunk];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t x = x0 + 64 * q + off;
+                    if (vr >= 0 && x < mp) {
+                        const double2 *src = reinterpret_cast<const double2 *>(z + x);
+#pragma unroll
+                        for (int u = 0; u < kRcChunk / 2; ++u) {
+                            const double2 t = src[u];
+                            v[q][2 * u] = t.x;
+                            v[q][2 * u + 1] = t.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < kRcChunk; ++u) v[q][u] = 0.0;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int u = 0; u < kRcChunk; ++u)
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[q][u], v[q][u], acc, 0, 0, 0);
+            }
+            // D layout of the FP64 16x16x4 product: lane l holds rows l / 16 + 4 t, column l % 16.
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int rr = (lane >> 4) + 4 * t, cc = lane & 15;
+                Gw[rr * 16 + cc] = rr == cc ? 1.0 : acc[t];
+            }
+        } else {
+            for (int q = lane; q < k * k; q += 64) {
+                const int rr = q / k, cc = q % k;
+                Gw[rr * 16 + cc] = rr == cc ? 1.0 : static_cast<const double *>(P.C)[(int64_t)vw[rr] * P.n + vw[cc]];
+            }
+        }
+        wave_sync();
+        if (lane == 0) {
+            rs.at(b, l, prob);
+            settle_recheck(b, P, l, Gw, 16, work[wave], kMMs, vw[0], vw[1], cls, vw + 2, rs);
+        }
+        wave_sync();
+    }
+    if (lane == 0) rs.flush(b, l);
+}
+
+// Queued tests of deeper levels (17 to 32 variables): one work-group per test. The Gram block
+// spans 2 x 2 tiles of 16 x 16; wavefront w accumulates tile (w / 2, w % 2) over all samples.
+__global__ __launch_bounds__(kRcThreads) void k_recheck_deep(Batch b, int level) {
+    __shared__ double part[kRcThreads / 64][16 * 16];
+    __shared__ double G[kGramLd * kGramLd];
+    __shared__ double work[kWork];
+    __shared__ int s_v[32];        // variables of the tile rows: i, j, S..., then -1
     __shared__ int s_prob, s_cls;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned long long pushed = b.st->rq_count;
+    const long long count = pushed < (unsigned long long)b.rq_cap ? (long long)pushed : b.rq_cap;
+    const int l = level, k = l + 2;
+    RcStats rs;
     for (long long e = blockIdx.x; e < count; e += gridDim.x) {
         const RqEntry *qe = b.rq + e;
-        if (tid < 16) s_v[tid] = tid == 0 ? qe->i : (tid == 1 ? qe->j : (tid < k ? qe->S[tid - 2] : -1));
+        if (tid < 32) s_v[tid] = tid == 0 ? qe->i : (tid == 1 ? qe->j : (tid < k ? (int)qe->S[tid - 2] : -1));
         if (tid == 0) {
             s_prob = qe->prob;
             s_cls = qe->cls;
@@ -592,80 +1006,52 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck(Batch b, int level) {
         __syncthreads();
         const int prob = s_prob;
         Prob &P = b.probs[prob];
-        const int i = s_v[0], j = s_v[1];
-        const int lo = i < j ? i : j, hi = i < j ? j : i;
         if (b.prec != PC_PREC_FP64) {
             const int64_t mp = P.mp;
-            const int vr = s_v[lane & 15];
-            const double *z = P.zt64 + (int64_t)(vr < 0 ? 0 : vr) * mp;
-            const int64_t off = (int64_t)(wave * 4 + (lane >> 4)) * kRcChunk;
+            const int ra = s_v[16 * (wave >> 1) + (lane & 15)], rb = s_v[16 * (wave & 1) + (lane & 15)];
+            const double *za = P.zt64 + (int64_t)(ra < 0 ? 0 : ra) * mp;
+            const double *zb = P.zt64 + (int64_t)(rb < 0 ? 0 : rb) * mp;
+            const int64_t off = (int64_t)(lane >> 4) * kRcChunk;
             doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-            for (int64_t x0 = 0; x0 < mp; x0 += kRcRound) {
-                // mp is a multiple of 64, so a chunk of 16 is either wholly inside or outside.
+            for (int64_t x0 = 0; x0 < mp; x0 += 4 * kRcChunk) {
                 const int64_t x = x0 + off;
-                double v[kRcChunk];
-                if (vr >= 0 && x < mp) {
-                    const double2 *src = reinterpret_cast<const double2 *>(z + x);
+                double va[kRcChunk], vb[kRcChunk];
 #pragma unroll
-                    for (int u = 0; u < kRcChunk / 2; ++u) {
-                        const double2 t = src[u];
-                        v[2 * u] = t.x;
-                        v[2 * u + 1] = t.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < kRcChunk; ++u) v[u] = 0.0;
+                for (int u = 0; u < kRcChunk; ++u) {
+                    va[u] = ra >= 0 && x < mp ? za[x + u] : 0.0;
+                    vb[u] = rb >= 0 && x < mp ? zb[x + u] : 0.0;
                 }
 #pragma unroll
-                for (int u = 0; u < kRcChunk; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u], v[u], acc, 0, 0, 0);
+                for (int u = 0; u < kRcChunk; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], vb[u], acc, 0, 0, 0);
             }
-            // D layout of the FP64 16x16x4 product: lane l holds rows l / 16 + 4 t, column l % 16.
 #pragma unroll
             for (int t = 0; t < 4; ++t) part[wave][((lane >> 4) + 4 * t) * 16 + (lane & 15)] = acc[t];
             __syncthreads();
-            {
-                const int rr = tid >> 4, cc = tid & 15;
-                if (rr < k && cc < k)
-                    G[rr * kGramLd + cc] = rr == cc ? 1.0 : part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+            for (int q = tid; q < 4 * 256; q += kRcThreads) {
+                const int w = q >> 8, rr = 16 * (w >> 1) + ((q & 255) >> 4), cc = 16 * (w & 1) + (q & 15);
+                if (rr < k && cc < k) G[rr * kGramLd + cc] = rr == cc ? 1.0 : part[w][q & 255];
             }
-        } else if (tid < k * k) {
-            const int rr = tid / k, cc = tid % k;
-            G[rr * kGramLd + cc] = rr == cc ? 1.0 : static_cast<const double *>(P.C)[(int64_t)s_v[rr] * P.n + s_v[cc]];
+        } else {
+            for (int q = tid; q < k * k; q += kRcThreads) {
+                const int rr = q / k, cc = q % k;
+                G[rr * kGramLd + cc] = rr == cc ? 1.0 : static_cast<const double *>(P.C)[(int64_t)s_v[rr] * P.n + s_v[cc]];
+            }
         }
         __syncthreads();
         if (tid == 0) {
-            if (prob != cur) {
-                if (cur >= 0) {
-                    Prob &Pc = b.probs[cur];
-                    add_ll(&Pc.rechecks[l], n_rc);
-                    if (n_rm) add_ll(&Pc.removed[l], n_rm);
-                    if (n_viol) add_ll(&Pc.audit_viol[l], n_viol);
-                }
-                cur = prob;
-                n_rc = n_rm = n_viol = 0;
-            }
-            const int res = decide_gram64(G, kGramLd, l, P.tau[l], work);
-            ++n_rc;
-            if (b.force_recheck && s_cls != 2 && s_cls != res) ++n_viol;
-            // The atomic on the canonical bit decides: an edge another test already removed stays
-            // removed and keeps that test's SepSet.
-            if (res && take_edge(P.adj, P.W, lo, hi)) {
-                ++n_rm;
-                write_record(P, lo, hi, l, s_v + 2);
-            }
+            rs.at(b, l, prob);
+            settle_recheck(b, P, l, G, kGramLd, work, kMM, s_v[0], s_v[1], s_cls, s_v + 2, rs);
         }
         __syncthreads();
     }
-    if (tid == 0 && cur >= 0) {
-        Prob &Pc = b.probs[cur];
-        add_ll(&Pc.rechecks[l], n_rc);
-        if (n_rm) add_ll(&Pc.removed[l], n_rm);
-        if (n_viol) add_ll(&Pc.audit_viol[l], n_viol);
-    }
+    if (tid == 0) rs.flush(b, l);
 }
 
 hipError_t launch_recheck(hipStream_t s, const Batch &b, int level, int grid) {
-    hipLaunchKernelGGL(k_recheck, dim3(grid), dim3(kRcThreads), 0, s, b, level);
+    if (level + 2 <= 16)
+        hipLaunchKernelGGL(k_recheck, dim3(grid), dim3(kRcThreads), 0, s, b, level);
+    else
+        hipLaunchKernelGGL(k_recheck_deep, dim3(grid), dim3(kRcThreads), 0, s, b, level);
     return hipGetLastError();
 }
 

@@ -120,3 +120,26 @@ def test_batch_reports_per_dataset_errors():
     assert status[1] == -3 and r == -3
     check_one(*batch[0], items[0], status[0])
     check_one(*batch[2], items[2], status[2])
+
+
+def test_graph_continues_past_recorded_levels():
+    """A graph that records only 2 levels still yields whole skeletons: pc_graph_results runs the
+    levels the datasets still need on the stream, on every replay."""
+    batch = uneven_batch(6, seed=91, nmax=160)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = pc.Context(stream=stream, precision="fp32", graph_levels=2)
+        items = [device_problem(ctx, X, a, -1) for X, a, _ in batch]
+        probs = ctx.problems(items)
+        ws = ctx.batch_workspace(probs)
+        g = ctx.pc_batch_capture(probs, ws)
+        for replay in range(2):
+            g.pc_graph_launch()
+            stats = (pc.pc_run_stats * len(items))()
+            r, status = g.pc_graph_results(stats)
+            assert r >= 0
+            assert max(st.levels_run for st in stats) > 3
+            for (X, a, _), item, st in zip(batch, items, status):
+                check_one(X, a, -1, item, st)
+        g.close()
+    torch.cuda.synchronize()

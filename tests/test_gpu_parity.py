@@ -26,11 +26,11 @@ U32 = 2.0 ** -24
 
 
 def eps_c(prec, m):
-    mp = (m + 63) // 64 * 64
+    # the stated bound on |C - C_64| (blocked accumulation with compensated block sums)
     if prec == "fp32":
-        return (mp + 4) * U32
+        return 37 * U32
     if prec == "bf16x3":
-        return 3 * 2.0 ** -18 + (3 * mp + 8) * U32
+        return (3 + 2.0 ** -7) * 2.0 ** -16 + 195 * U32
     return 1e-12
 
 
@@ -239,3 +239,24 @@ def test_sepset_capacity_error():
             ctx.pc_skeleton(Xt, 0.05, adj, recs, count, ws)
         assert e.value.status == -8
         assert np.array_equal(pc.bits_to_dense(adj.cpu().numpy(), n), ref.G)
+
+
+def hub_data(parents, m, seed, extra=8):
+    """A collider hub with `parents` independent parents (plus unrelated variables): every
+    hub-parent edge is a true edge, so the hub keeps its degree and the levels run up to
+    parents - 1, through the wavefront-per-set kernel of the deep levels."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((m, parents + 1 + extra))
+    w = rng.choice([-1.0, 1.0], parents) * rng.uniform(0.3, 1.0, parents)
+    X[:, parents] = X[:, :parents] @ w + rng.standard_normal(m)
+    return np.ascontiguousarray(X)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_skeleton_deep_levels_hub(prec):
+    X = hub_data(17, 5000, 31)
+    print(f"deep levels prec={prec} n={X.shape[1]} m={X.shape[0]}", flush=True)
+    st, ref = compare_with_oracle(X, 0.01, prec)
+    assert ref.levels_run >= 17 and st["levels_run"] == ref.levels_run
+    assert sum(st["tests"][14:ref.levels_run]) > 0
+
