@@ -1,20 +1,26 @@
-"""Benchmark: PC-stable skeleton on one MI355X through the C ABI (pc_skeleton).
+"""Benchmark: PC-stable skeleton on one MI355X through the C ABI.
 
 One step = one whole skeleton (standardize, correlation GEMM with the level-0 test, then every
-level until the stop rule) on a synthetic linear-Gaussian SEM dataset that is already resident in
-HBM: n = 1000 variables, expected degree 4, m = 500 samples, alpha = 0.01, FP32 CI tests with FP64
-re-checks of borderline tests.
+level until the stop rule, FP64 re-checks included) of a synthetic linear-Gaussian SEM dataset that
+is already resident in HBM: n = 1000 variables, expected degree 4, m = 500 samples, alpha = 0.01,
+FP32 CI tests with FP64 re-checks of borderline tests. The skeleton is captured once as a hipGraph
+(pc_batch_capture) and each step is one replay; `ms_per_step` is the replay time.
 
-Prints one JSON line. `value` is CI tests per second: the number of CI tests the sequential
-PC-stable enumeration performs on this input (canonical order, early stop per edge; counted by the
-CPU oracle in the cpu_baseline leg, which runs on the same input) divided by the GPU wall time per
-skeleton. The tests the GPU actually evaluated (it runs some speculatively) are reported beside it.
+`value` is CI tests per second: the tests the sequential PC-stable enumeration performs on this
+input (canonical order, early stop per edge; counted by the CPU oracle in the cpu_baseline leg, on
+the same input) divided by the time per step. The tests the GPU evaluated are reported beside it.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+Also reported: the same skeleton through pc_skeleton on the stream (with HIP events around the
+kernels, which give the roofline of the dominant kernel), plain vs learned conditioning-set order
+on n = 2000 (expected degree 10, m = 1000, identical skeleton required), and a captured batch of
+256 uneven datasets.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--copy-calibration MiB]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,13 +32,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "n1000_d4_m500_fp32"
+APPLY_WORKLOAD = "n2000_d10_m1000_apply"
 PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_level1_n1000_d4_m500.json")
+LEVEL_SOURCES = ["paper_1812_08491_amd/csrc/pc_level.hip", "paper_1812_08491_amd/csrc/pc_citest.h",
+                 "paper_1812_08491_amd/csrc/pc_dev.h", "paper_1812_08491_amd/csrc/pc_comb.h"]
+
+
+def level_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in LEVEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of k_level<float,1> from the committed PMC summary, or None when the
+    level kernel's sources changed after the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != level_source_hash():
+        return None
+    return float(t["bytes_per_launch"])
 
 
 def cpu_baseline(X: np.ndarray, alpha: float, min_seconds: float = 10.0, max_reps: int = 30):
     """The FP64 oracle (single-threaded C, as it stands) on the same input, repeated until about
-    min_seconds of CPU time; returns (canonical tests per skeleton, seconds per skeleton, reps)."""
+    min_seconds of CPU time; returns (oracle result, seconds per skeleton, runs)."""
     import oracle
     t0 = time.perf_counter()
     ref = oracle.skeleton(X, alpha)
@@ -44,17 +75,65 @@ def cpu_baseline(X: np.ndarray, alpha: float, min_seconds: float = 10.0, max_rep
     return ref, float(np.mean(times)), len(times)
 
 
+def copy_calibration(mib: int, reps: int = 5) -> None:
+    """Device-to-device copies of a known size, for scaling the PMC byte counters."""
+    import torch
+    src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": mib << 20, "reps": reps}))
+
+
+def write_traffic(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str,
+                  copy_bytes: int) -> None:
+    """Per-launch HBM bytes of k_level<float,1> from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for a device copy of
+    copy_bytes; written to the traffic summary with the hash of the level kernel's sources."""
+    import csv
+
+    def per_dispatch(path, kernel):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if r["Kernel_Name"].startswith(kernel)]
+        return float(np.mean(vals)), len(vals)
+
+    fetch, nf = per_dispatch(fetch_csv, "void pcg::k_level<float, 1>")
+    write, nw = per_dispatch(write_csv, "void pcg::k_level<float, 1>")
+    cf, _ = per_dispatch(copy_fetch_csv, "__amd_rocclr_copyBuffer")
+    cw, _ = per_dispatch(copy_write_csv, "__amd_rocclr_copyBuffer")
+    f_fetch, f_write = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    out = {"kernel": "k_level<float,1>", "workload": "n=1000, degree 4, m=500, alpha 0.01, fp32",
+           "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
+           "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": f_fetch, "write_scale": f_write,
+           "bytes_per_launch": (fetch * f_fetch + write * f_write) * 1024.0,
+           "source_hash": level_source_hash()}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the learned-order and batch legs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                         "COPY_WRITE_CSV"))
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic, copy_bytes=256 << 20)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               f"multi-GPU path.", file=sys.stderr)
         return 2
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return 0
 
     import torch
 
@@ -64,41 +143,9 @@ def main() -> int:
     X, sem, alpha = semgen.workload(WORKLOAD)
     m, n = X.shape
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    # time the correlation GEMM (1) and the level kernels (2) with HIP events on the library stream
-    ctx = pc.Context(stream=stream, precision="fp32", timing=1 | 2)
-    ws = ctx.workspace(n, m)
-    adj = ctx.adjacency(n)
-    recs, count = ctx.sepsets(n * (n - 1) // 2)
     Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
-    st = pc.pc_run_stats()
 
-    for _ in range(args.warmup):
-        ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st)
-    torch.cuda.synchronize()
-
-    corr_ms, level_ms, per_step = [], [], []
-    executed = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        status = ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st)
-        per_step.append(time.perf_counter() - s0)
-        d = st.as_dict()
-        corr_ms.append(d["corr_ms"])
-        level_ms.append(d["level_ms"])
-        executed = d
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    assert status == 0, pc.status_str(status)
-    sec_per_step = (t1 - t0) / args.steps
-
-    G = pc.bits_to_dense(adj.cpu().numpy(), n)
-    gpu_tests = int(sum(executed["tests"]))
-
-    # The same skeleton captured once as a hipGraph (pc_batch_capture with one problem) and replayed.
-    graph_ms = None
+    # -- timed region: graph replays of the whole skeleton ----------------------------------------
     gstream = torch.cuda.Stream()
     with torch.cuda.stream(gstream):
         gctx = pc.Context(stream=gstream, precision="fp32")
@@ -109,15 +156,49 @@ def main() -> int:
         graph = gctx.pc_batch_capture(probs, gws)
         for _ in range(args.warmup):
             graph.pc_graph_launch()
-        gstream.synchronize()
+        torch.cuda.synchronize()
         g0 = time.perf_counter()
         for _ in range(args.steps):
             graph.pc_graph_launch()
-        gstream.synchronize()
-        graph_ms = (time.perf_counter() - g0) / args.steps * 1e3
-        r, gstatus = graph.pc_graph_results()
-        graph_same = bool(np.array_equal(pc.bits_to_dense(gadj.cpu().numpy(), n), G)) and r == 0
+        torch.cuda.synchronize()
+        sec_per_step = (time.perf_counter() - g0) / args.steps
+        gst = (pc.pc_run_stats * 1)()
+        r, gstatus = graph.pc_graph_results(gst)
         graph.close()
+    assert r == 0 and gstatus[0] == 0, (r, gstatus)
+    G = pc.bits_to_dense(gadj.cpu().numpy(), n)
+    gstats = gst[0].as_dict()
+    gpu_tests = int(sum(gstats["tests"]))
+
+    # -- the same skeleton through pc_skeleton on the stream, HIP events around every kernel phase ----
+    stream = torch.cuda.current_stream()
+    ctx = pc.Context(stream=stream, precision="fp32", timing=1 | 2 | 4 | 8 | 16)
+    ws = ctx.workspace(n, m)
+    adj = ctx.adjacency(n)
+    recs, count = ctx.sepsets(n * (n - 1) // 2)
+    st = pc.pc_run_stats()
+    for _ in range(args.warmup):
+        ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st)
+    torch.cuda.synchronize()
+    runs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        status = ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st)
+        runs.append(st.as_dict())
+    torch.cuda.synchronize()
+    stream_sec = (time.perf_counter() - t0) / args.steps
+    assert status == 0, pc.status_str(status)
+    same_as_graph = bool(np.array_equal(pc.bits_to_dense(adj.cpu().numpy(), n), G))
+    L = runs[-1]["levels_run"]
+
+    def mean_of(key, lvl=None):
+        v = [d[key] if lvl is None else d[key][lvl] for d in runs]
+        return float(np.mean(v))
+
+    level_ms = [mean_of("level_ms", l) for l in range(L)]
+    kernel_ms = {"prep": mean_of("prep_ms"), "corr_gemm_level0": mean_of("corr_ms"),
+                 "compact_plan": [mean_of("compact_ms", l) for l in range(L)],
+                 "level": level_ms, "recheck": [mean_of("recheck_ms", l) for l in range(L)]}
 
     out = {
         "metric": "CI tests/sec and skeleton wall time (PC-stable skeleton, identical to the FP64 oracle)",
@@ -134,33 +215,82 @@ def main() -> int:
         "data": "synthetic linear-Gaussian SEM (seeded), resident in HBM",
         "config": {"workload": "pc_stable_skeleton_n1000_deg4_m500_alpha0.01_fp32_recheck",
                    "n": n, "m": m, "expected_degree": 4, "alpha": alpha, "precision": "fp32+fp64 recheck",
-                   "levels_run": executed["levels_run"], "edges": int(G.sum()) // 2},
+                   "step": "one hipGraph replay of the whole skeleton",
+                   "levels_run": gstats["levels_run"], "edges": int(G.sum()) // 2},
         "gpu_tests_per_step": gpu_tests,
         "gpu_executed_tests_per_s": gpu_tests / sec_per_step,
-        "skeleton_wall_ms_median": float(np.median(per_step)) * 1e3,
-        "graph_replay_ms_per_step": graph_ms,
-        "graph_replay_same_skeleton": graph_same,
-        "per_level_tests": executed["tests"],
-        "rechecks": executed["rechecks"],
+        "per_level_tests": gstats["tests"][:gstats["levels_run"]],
+        "rechecks": gstats["rechecks"][:gstats["levels_run"]],
+        "stream_ms_per_step": stream_sec * 1e3,
+        "stream_same_skeleton": same_as_graph,
+        "kernel_ms": kernel_ms,
     }
 
-    # Roofline of the correlation GEMM (SYRK, m n (n-1) flops per launch on FP32 MFMA).
-    corr = float(np.mean(corr_ms))
-    flops = float(m) * n * (n - 1)
-    ach = flops / (corr * 1e-3) / 1e12
-    lvl = np.array([x + [0.0] * (pc.PC_MAX_LEVEL + 1 - len(x)) for x in level_ms]).mean(axis=0)
-    out["kernel_ms"] = {"corr_gemm_level0": corr, "levels": [float(v) for v in lvl[:executed["levels_run"]]]}
-    out["roofline"] = {"kernel": "k_corr<fp32> (SYRK + level-0 test)", "bound": "mfma",
-                       "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                       "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None}
+    # -- roofline of the dominant kernel: the level-1 CI tests (gather bound: per test C_ij and the
+    #    entry C[j,S], 4 (l + 1) = 8 bytes at l = 1) --------------------------------------------------
+    t1 = runs[-1]["tests"][1]
+    l1_s = level_ms[1] * 1e-3
+    ach = t1 * 8.0 / l1_s / 1e9
+    traffic = measured_traffic()
+    out["roofline"] = {"kernel": "k_level<float,1> (level-1 CI tests)", "bound": "hbm",
+                       "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                       "traffic": traffic, "algorithmic_bytes": t1 * 8.0, "launch_ms": level_ms[1]}
+    corr_s = kernel_ms["corr_gemm_level0"] * 1e-3
+    fl = float(m) * n * (n - 1) / corr_s / 1e12
+    out["roofline_corr"] = {"kernel": "k_corr<fp32> (SYRK + level-0 test)", "bound": "mfma", "achieved": fl,
+                            "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": fl / PEAK_FP32_MFMA_TFLOPS,
+                            "launch_ms": kernel_ms["corr_gemm_level0"]}
+
+    if not args.no_extras:
+        # -- plain vs learned conditioning-set order (same data, identical skeleton required) ------
+        from paper_1812_08491_amd import learn
+        Xa, _, alpha_a = semgen.workload(APPLY_WORKLOAD)
+        cmp = learn.compare_orders(Xa, alpha_a, learn.load_weights(), min_level=2, top=4, repeats=5)
+        tp, tl = sum(cmp["plain"]["tests"]), sum(cmp["learned"]["tests"])
+        out["learned_vs_plain"] = {
+            "workload": "n2000_deg10_m1000_alpha0.01_fp32", "same_skeleton": cmp["same_skeleton"],
+            "plain_ms": cmp["plain"]["wall_ms"], "learned_ms": cmp["learned"]["wall_ms"],
+            "plain_tests": tp, "learned_tests": tl,
+            "plain_tests_per_s": tp / (cmp["plain"]["wall_ms"] * 1e-3),
+            "learned_tests_per_s": tl / (cmp["learned"]["wall_ms"] * 1e-3),
+            "probe_tests": sum(cmp["learned"]["probe_tests"]),
+            "probe_removed": sum(cmp["learned"]["probe_removed"]),
+            "order": {"min_level": 2, "top": 4, "weights": "weights/order_mlp_n200.npy"}}
+        # -- 256 uneven datasets in one captured graph --------------------------------------------
+        batch = semgen.batch_problems(256)
+        bstream = torch.cuda.Stream()
+        with torch.cuda.stream(bstream):
+            bctx = pc.Context(stream=bstream, precision="fp32")
+            items = []
+            for Xb, _, ab in batch:
+                mb, nb = Xb.shape
+                rb, cb = bctx.sepsets(nb * (nb - 1) // 2)
+                items.append((torch.from_numpy(np.ascontiguousarray(Xb)).cuda(), ab, -1, bctx.adjacency(nb), rb, cb))
+            bprobs = bctx.problems(items)
+            bws = bctx.batch_workspace(bprobs)
+            bgraph = bctx.pc_batch_capture(bprobs, bws)
+            for _ in range(2):
+                bgraph.pc_graph_launch()
+            torch.cuda.synchronize()
+            reps = max(3, args.steps // 5)
+            b0 = time.perf_counter()
+            for _ in range(reps):
+                bgraph.pc_graph_launch()
+            torch.cuda.synchronize()
+            bms = (time.perf_counter() - b0) / reps * 1e3
+            bst = (pc.pc_run_stats * len(items))()
+            br, bstatus = bgraph.pc_graph_results(bst)
+            bgraph.close()
+        out["batch256_graph"] = {"workload": "256 datasets, n~U[20,400], degree~U[2,8], m~U[200,5000], alpha 0.01",
+                                 "ms_per_batch": bms, "status": br,
+                                 "tests": int(sum(sum(s.as_dict()["tests"]) for s in bst))}
 
     if not args.no_cpu_baseline:
         ref, cpu_sec, reps = cpu_baseline(X, alpha)
         canonical = int(sum(ref.tests))
-        same = bool(np.array_equal(G, ref.G))
         out["value"] = canonical / sec_per_step
         out["canonical_tests_per_step"] = canonical
-        out["skeleton_equal_to_oracle"] = same
+        out["skeleton_equal_to_oracle"] = bool(np.array_equal(G, ref.G))
         out["cpu_baseline"] = {"value": canonical / cpu_sec, "unit": "CI tests/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"whole workload (same input), {reps} runs, {cpu_sec:.3f} s each",
