@@ -384,7 +384,8 @@ pc_status enqueue_plan(pc_ctx *ctx, const Batch &b, int level, bool capturing) {
 pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, const OrderRun *ord) {
     hipStream_t s = ctx->stream;
     const int R = ranks_per_item(ctx, level);
-    if (ord && level >= ord->order->min_level && level <= kProbeMaxLevel) {
+    // The probe tests subsets of the top candidates: none exist once the level exceeds top.
+    if (ord && level >= ord->order->min_level && level <= kProbeMaxLevel && level <= ord->order->top) {
         const Plan &L = *ord->L;
         long long *foff = reinterpret_cast<long long *>(ord->ws + L.foff);
         int *skip = reinterpret_cast<int *>(ord->ws + L.skip);
