@@ -75,55 +75,76 @@ struct Operands {
     const void *zlo, *zhi;
 };
 
+// One thread's share of the next K block of both operand tiles, held in registers between the
+// global loads and the LDS stores so the loads can overlap the previous block's products.
+template <int PREC> struct Frag;
+template <> struct Frag<PC_PREC_FP32> { float4 a, b; };
+template <> struct Frag<PC_PREC_FP64> { double2 a0, a1, b0, b1; };
+template <> struct Frag<PC_PREC_BF16X3> { uint4 ah, al, bh, bl; };
+
 template <int PREC>
-__device__ inline void load_tiles(Smem<PREC> &sm, const Operands &a, int64_t a0, int64_t b0,
-                                  int64_t k0, int tid) {
+__device__ inline void fetch_tiles(Frag<PREC> &f, const Operands &a, int64_t a0, int64_t b0, int64_t k0, int tid) {
     const int row = tid >> 2;
     if constexpr (PREC == PC_PREC_FP32) {
         const int kq = (tid & 3) * 4;
         const float *z = static_cast<const float *>(a.zlo);
-        float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
-        if (a0 + row < a.n) va = *reinterpret_cast<const float4 *>(z + (a0 + row) * a.mp + k0 + kq);
-        if (b0 + row < a.n) vb = *reinterpret_cast<const float4 *>(z + (b0 + row) * a.mp + k0 + kq);
-        sm.A[kq + 0][row] = va.x; sm.A[kq + 1][row] = va.y;
-        sm.A[kq + 2][row] = va.z; sm.A[kq + 3][row] = va.w;
-        sm.B[kq + 0][row] = vb.x; sm.B[kq + 1][row] = vb.y;
-        sm.B[kq + 2][row] = vb.z; sm.B[kq + 3][row] = vb.w;
+        f.a = make_float4(0.f, 0.f, 0.f, 0.f);
+        f.b = f.a;
+        if (a0 + row < a.n) f.a = *reinterpret_cast<const float4 *>(z + (a0 + row) * a.mp + k0 + kq);
+        if (b0 + row < a.n) f.b = *reinterpret_cast<const float4 *>(z + (b0 + row) * a.mp + k0 + kq);
     } else if constexpr (PREC == PC_PREC_FP64) {
         const int kq = (tid & 3) * 4;
         const double *z = a.zt64;
-        double2 va0 = make_double2(0.0, 0.0), va1 = va0, vb0 = va0, vb1 = va0;
+        f.a0 = make_double2(0.0, 0.0);
+        f.a1 = f.b0 = f.b1 = f.a0;
         if (a0 + row < a.n) {
             const double2 *p = reinterpret_cast<const double2 *>(z + (a0 + row) * a.mp + k0 + kq);
-            va0 = p[0];
-            va1 = p[1];
+            f.a0 = p[0];
+            f.a1 = p[1];
         }
         if (b0 + row < a.n) {
             const double2 *p = reinterpret_cast<const double2 *>(z + (b0 + row) * a.mp + k0 + kq);
-            vb0 = p[0];
-            vb1 = p[1];
+            f.b0 = p[0];
+            f.b1 = p[1];
         }
-        sm.A[kq + 0][row] = va0.x; sm.A[kq + 1][row] = va0.y;
-        sm.A[kq + 2][row] = va1.x; sm.A[kq + 3][row] = va1.y;
-        sm.B[kq + 0][row] = vb0.x; sm.B[kq + 1][row] = vb0.y;
-        sm.B[kq + 2][row] = vb1.x; sm.B[kq + 3][row] = vb1.y;
     } else {
         const int k8 = (tid & 3) * 8;
         const uint16_t *zh = static_cast<const uint16_t *>(a.zhi);
         const uint16_t *zl = static_cast<const uint16_t *>(a.zlo);
-        uint4 ah = make_uint4(0, 0, 0, 0), al = ah, bh = ah, bl = ah;
+        f.ah = make_uint4(0, 0, 0, 0);
+        f.al = f.bh = f.bl = f.ah;
         if (a0 + row < a.n) {
-            ah = *reinterpret_cast<const uint4 *>(zh + (a0 + row) * a.mp + k0 + k8);
-            al = *reinterpret_cast<const uint4 *>(zl + (a0 + row) * a.mp + k0 + k8);
+            f.ah = *reinterpret_cast<const uint4 *>(zh + (a0 + row) * a.mp + k0 + k8);
+            f.al = *reinterpret_cast<const uint4 *>(zl + (a0 + row) * a.mp + k0 + k8);
         }
         if (b0 + row < a.n) {
-            bh = *reinterpret_cast<const uint4 *>(zh + (b0 + row) * a.mp + k0 + k8);
-            bl = *reinterpret_cast<const uint4 *>(zl + (b0 + row) * a.mp + k0 + k8);
+            f.bh = *reinterpret_cast<const uint4 *>(zh + (b0 + row) * a.mp + k0 + k8);
+            f.bl = *reinterpret_cast<const uint4 *>(zl + (b0 + row) * a.mp + k0 + k8);
         }
-        *reinterpret_cast<uint4 *>(&sm.Ahi[row][k8]) = ah;
-        *reinterpret_cast<uint4 *>(&sm.Alo[row][k8]) = al;
-        *reinterpret_cast<uint4 *>(&sm.Bhi[row][k8]) = bh;
-        *reinterpret_cast<uint4 *>(&sm.Blo[row][k8]) = bl;
+    }
+}
+
+template <int PREC>
+__device__ inline void stage_tiles(Smem<PREC> &sm, const Frag<PREC> &f, int tid) {
+    const int row = tid >> 2;
+    if constexpr (PREC == PC_PREC_FP32) {
+        const int kq = (tid & 3) * 4;
+        sm.A[kq + 0][row] = f.a.x; sm.A[kq + 1][row] = f.a.y;
+        sm.A[kq + 2][row] = f.a.z; sm.A[kq + 3][row] = f.a.w;
+        sm.B[kq + 0][row] = f.b.x; sm.B[kq + 1][row] = f.b.y;
+        sm.B[kq + 2][row] = f.b.z; sm.B[kq + 3][row] = f.b.w;
+    } else if constexpr (PREC == PC_PREC_FP64) {
+        const int kq = (tid & 3) * 4;
+        sm.A[kq + 0][row] = f.a0.x; sm.A[kq + 1][row] = f.a0.y;
+        sm.A[kq + 2][row] = f.a1.x; sm.A[kq + 3][row] = f.a1.y;
+        sm.B[kq + 0][row] = f.b0.x; sm.B[kq + 1][row] = f.b0.y;
+        sm.B[kq + 2][row] = f.b1.x; sm.B[kq + 3][row] = f.b1.y;
+    } else {
+        const int k8 = (tid & 3) * 8;
+        *reinterpret_cast<uint4 *>(&sm.Ahi[row][k8]) = f.ah;
+        *reinterpret_cast<uint4 *>(&sm.Alo[row][k8]) = f.al;
+        *reinterpret_cast<uint4 *>(&sm.Bhi[row][k8]) = f.bh;
+        *reinterpret_cast<uint4 *>(&sm.Blo[row][k8]) = f.bl;
     }
 }
 
@@ -207,7 +228,7 @@ __global__ __launch_bounds__(256) void k_corr(Batch bt) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
 
-    __shared__ Smem<PREC> sm;
+    __shared__ Smem<PREC> sm[2];   // double buffer: block k + 1 is staged while block k is multiplied
     __shared__ unsigned long long rowbits[kT], colbits[kT];
     __shared__ unsigned int blist[kT * kT];
     __shared__ int bcount;
@@ -226,10 +247,15 @@ __global__ __launch_bounds__(256) void k_corr(Batch bt) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[mi][nj][v] = sum[mi][nj][v] = cmp[mi][nj][v] = 0;
 
+    Frag<PREC> frag;
+    fetch_tiles<PREC>(frag, ops, a0, b0, 0, tid);
+    stage_tiles<PREC>(sm[0], frag, tid);
+    __syncthreads();
+    int cur = 0;
     for (int64_t k0 = 0; k0 < a.mp; k0 += BK) {
-        load_tiles<PREC>(sm, ops, a0, b0, k0, tid);
-        __syncthreads();
-        mma_step<PREC>(sm, acc, lane, wr, wc);
+        const bool more = k0 + BK < a.mp;
+        if (more) fetch_tiles<PREC>(frag, ops, a0, b0, k0 + BK, tid);
+        mma_step<PREC>(sm[cur], acc, lane, wr, wc);
         if constexpr (PREC != PC_PREC_FP64) {
 #pragma unroll
             for (int mi = 0; mi < 2; ++mi)
@@ -244,7 +270,9 @@ __global__ __launch_bounds__(256) void k_corr(Batch bt) {
                         acc[mi][nj][v] = 0.0f;
                     }
         }
+        if (more) stage_tiles<PREC>(sm[cur ^ 1], frag, tid);
         __syncthreads();
+        cur ^= 1;
     }
     if constexpr (PREC != PC_PREC_FP64) {
 #pragma unroll
