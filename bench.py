@@ -36,8 +36,9 @@ APPLY_WORKLOAD = "n2000_d10_m1000_apply"
 PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_level1_n1000_d4_m500.json")
-LEVEL_SOURCES = ["paper_1812_08491_amd/csrc/pc_level.hip", "paper_1812_08491_amd/csrc/pc_citest.h",
-                 "paper_1812_08491_amd/csrc/pc_dev.h", "paper_1812_08491_amd/csrc/pc_comb.h"]
+LEVEL_SOURCES = ["paper_1812_08491_amd/csrc/pc_level.h", "paper_1812_08491_amd/csrc/pc_level_f32.hip",
+                 "paper_1812_08491_amd/csrc/pc_citest.h", "paper_1812_08491_amd/csrc/pc_dev.h",
+                 "paper_1812_08491_amd/csrc/pc_comb.h"]
 
 
 def level_source_hash() -> str:

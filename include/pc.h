@@ -64,9 +64,12 @@ typedef struct {
     float margin_scale;        /* safety factor on the FP32 error band (default 2; must be >= 1) */
     int32_t force_recheck_all; /* 1: every FP32 test is re-evaluated in FP64 (precision audit) */
     int32_t lds_budget;        /* bytes of LDS a level work-group may use to stage C[N_i,N_i]
-                                  (default 65536; 0 forces the global-memory gather path) */
-    int32_t ranks_per_lane;    /* conditioning sets per lane in one work item (0 = automatic) */
-    int32_t grid;              /* work-groups of the persistent level kernel (0 = automatic) */
+                                  (default 16384, so that several work-groups share a CU; capped
+                                  near 50 KiB; 0 forces the global-memory gather path) */
+    int32_t ranks_per_lane;    /* conditioning sets per lane in one work item (0 = automatic:
+                                  1 at level 1, 4 at levels 2-3, 2 at 4-7, 1 above) */
+    int32_t grid;              /* work-groups of the persistent level kernel (0 = automatic: as
+                                  many as fit on the device at once) */
     int32_t timing;            /* bit mask of phases timed with HIP events into pc_run_stats:
                                   1 = correlation kernel (incl. level 0), 2 = level kernels,
                                   4 = compaction, 8 = FP64 re-check, 16 = standardization */
@@ -77,7 +80,9 @@ typedef struct {
     int32_t graph_levels;      /* levels recorded in a captured graph (pc_batch_capture; 0 = 10).
                                   A replay whose datasets need more levels continues them on the
                                   stream in pc_graph_results. */
-    int32_t pad;
+    int32_t tests_per_lane;    /* levels up to 13: rows with long neighbour lists get work items of
+                                  fewer conditioning sets, so one lane runs about this many CI
+                                  tests per item (0 = automatic, 128) */
 } pc_options;
 
 /* One SepSet record, written for every edge removed at a level >= 1 (Algorithm 1: "store S").

@@ -13,7 +13,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpc.so")
-SOURCES = ["pc_prep.hip", "pc_corr.hip", "pc_level.hip", "pc_mlp.hip", "pc_api.cpp"]
+# Longest compilations first: the level-kernel instances dominate the build.
+SOURCES = ["pc_level_deep.hip", "pc_level_f32.hip", "pc_level_f64.hip", "pc_recheck.hip", "pc_mlp.hip",
+           "pc_corr.hip", "pc_level.hip", "pc_prep.hip", "pc_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I" + os.path.join(ROOT, "include"),
@@ -37,7 +39,7 @@ def _compile(src: str, build_dir: str) -> str:
 def build(verbose: bool = True) -> str:
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=4) as ex:
+    with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
         objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
     tmp = OUT + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)

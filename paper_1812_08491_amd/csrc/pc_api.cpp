@@ -36,6 +36,7 @@ struct pc_ctx {
     hipEvent_t ev_prep[2], ev_corr[2];
     hipEvent_t ev_compact[kLevels][2], ev_level[kLevels][2], ev_recheck[kLevels][2];
     int top_run;                    // highest level enqueued by the current call
+    int level_grid[kLevels];        // work-groups of the level kernels: all that fit at once
 };
 
 struct pc_graph {
@@ -54,6 +55,7 @@ struct pc_graph {
 namespace {
 
 constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24, unit roundoff of FP32
+constexpr int kAutoLaneTests = 128;               // default bound on CI tests per lane and item
 
 #define PC_HIP(call)                                                       \
     do {                                                                   \
@@ -68,7 +70,7 @@ pc_options defaults() {
     o.max_level = -1;
     o.margin_scale = 2.0f;
     o.force_recheck_all = 0;
-    o.lds_budget = 65536;
+    o.lds_budget = 16384;
     o.ranks_per_lane = 0;
     o.grid = 0;
     o.timing = 0;
@@ -81,6 +83,7 @@ bool valid_options(const pc_options &o) {
     if (o.precision < PC_PREC_FP64 || o.precision > PC_PREC_BF16X3) return false;
     if (!(o.margin_scale >= 1.0f)) return false;
     if (o.lds_budget < 0 || o.ranks_per_lane < 0 || o.grid < 0 || o.recheck_cap < 0) return false;
+    if (o.tests_per_lane < 0) return false;
     if (o.graph_levels < 0 || o.graph_levels > PC_MAX_LEVEL) return false;
     return true;
 }
@@ -269,6 +272,7 @@ Batch make_batch(const pc_ctx *ctx, const Plan &L, unsigned char *ws) {
     b.count = L.count;
     b.prec = L.prec;
     b.force_recheck = L.prec != PC_PREC_FP64 && ctx->opt.force_recheck_all;
+    b.lane_tests = ctx->opt.tests_per_lane > 0 ? ctx->opt.tests_per_lane : kAutoLaneTests;
     const long long *bases = reinterpret_cast<const long long *>(ws + L.table + sizeof(Prob) * L.count);
     b.row_base = bases;
     b.cs_base = bases + (L.count + 1);
@@ -325,13 +329,20 @@ pc_status upload_table(pc_ctx *ctx, const Plan &L, unsigned char *ws, const std:
     return PC_OK;
 }
 
-int auto_grid(const pc_ctx *ctx) { return ctx->opt.grid > 0 ? ctx->opt.grid : 2 * ctx->num_cu; }
+int auto_grid(const pc_ctx *ctx, int level) {
+    if (ctx->opt.grid > 0) return ctx->opt.grid;
+    const int g = ctx->level_grid[level];
+    return g > 0 ? g : 2 * ctx->num_cu;
+}
 
 // Conditioning-set ranks per work item. Levels up to kFastLevels give every thread its own sets;
 // deeper levels give every wavefront one set at a time, so their items are much smaller.
 int ranks_per_item(const pc_ctx *ctx, int level) {
     if (level > kFastLevels) return 4 * (ctx->opt.ranks_per_lane > 0 ? ctx->opt.ranks_per_lane : 4);
-    const int q = ctx->opt.ranks_per_lane > 0 ? ctx->opt.ranks_per_lane : (level == 1 ? 1 : 4);
+    // Sets per lane: one at level 1 (a set there is a single division), several while a set's
+    // factor is cheap, one again once it is long (l^3 work per set at deep levels).
+    const int q = ctx->opt.ranks_per_lane > 0 ? ctx->opt.ranks_per_lane
+                                               : (level == 1 ? 1 : (level <= 3 ? 4 : (level <= 7 ? 2 : 1)));
     return q * kLevelThreads;
 }
 
@@ -398,7 +409,7 @@ pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, co
         PC_HIP(launch_probe(s, b, level, foff, scores, ord->order->top, skip));
     }
     if (timed(ctx, 2, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][0], s));
-    PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx), auto_grid(ctx)));
+    PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx), auto_grid(ctx, level)));
     if (timed(ctx, 2, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][1], s));
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][0], s));
     PC_HIP(launch_recheck(s, b, level, 4 * ctx->num_cu));
@@ -657,6 +668,11 @@ pc_status pc_create(pc_ctx **out, void *stream, const pc_options *opt) {
     if (hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming) != hipSuccess) {
         c->staging_done = nullptr;
         ok = false;
+    }
+    // Level kernels launch as many work-groups as fit on the device at once (persistent workers).
+    for (int l = 0; l < kLevels; ++l) {
+        const int nb = l >= 1 && l <= PC_MAX_LEVEL ? level_blocks_per_cu(o.precision, l, level_lds_bytes(c)) : 0;
+        c->level_grid[l] = nb > 0 ? nb * c->num_cu : 0;
     }
     if (ok && ensure_binom(c, 8191) != PC_OK) ok = false;
     if (ok && hipStreamSynchronize(c->stream) != hipSuccess) ok = false;
@@ -1009,7 +1025,9 @@ pc_status pc_comb_unrank(int32_t d, int32_t l, uint64_t t, int32_t skip, int32_t
     if (t >= binom(pool, l)) return PC_ERR_INVALID_ARG;
     int P[PC_MAX_LEVEL];
     // Dispatch on the compile-time subset size the device code uses.
+    static_assert(PC_MAX_LEVEL == 30, "one case per subset size up to PC_MAX_LEVEL");
     switch (l) {
+        case 0: break;
 #define PC_CASE(K)                                                        \
     case K: {                                                             \
         int Q[K];                                                         \
@@ -1018,9 +1036,12 @@ pc_status pc_comb_unrank(int32_t d, int32_t l, uint64_t t, int32_t skip, int32_t
         break;                                                            \
     }
         PC_CASE(1) PC_CASE(2) PC_CASE(3) PC_CASE(4) PC_CASE(5) PC_CASE(6) PC_CASE(7)
-        PC_CASE(8) PC_CASE(9) PC_CASE(10) PC_CASE(11) PC_CASE(12) PC_CASE(13)
+        PC_CASE(8) PC_CASE(9) PC_CASE(10) PC_CASE(11) PC_CASE(12) PC_CASE(13) PC_CASE(14)
+        PC_CASE(15) PC_CASE(16) PC_CASE(17) PC_CASE(18) PC_CASE(19) PC_CASE(20) PC_CASE(21)
+        PC_CASE(22) PC_CASE(23) PC_CASE(24) PC_CASE(25) PC_CASE(26) PC_CASE(27) PC_CASE(28)
+        PC_CASE(29) PC_CASE(30)
 #undef PC_CASE
-        default: break;
+        default: return PC_ERR_INVALID_ARG;
     }
     for (int c = 0; c < l; ++c) out[c] = (skip >= 0 && P[c] >= skip) ? P[c] + 1 : P[c];
     return PC_OK;

@@ -137,11 +137,19 @@ struct SetFactor {
     template <class CS, class CI>
     __device__ inline int test(const int (&P)[L], int p, const CS &cs, const CI &ci, double tau,
                                float tl, float band) const {
+        T col[L];
+#pragma unroll
+        for (int r = 0; r < L; ++r) col[r] = cs(p, P[r]);
+        return test_vals(col, ci(p), tau, tl, band);
+    }
+
+    // The same test from values already loaded: col[r] = C[N_p, S_r], cij = C[i, N_p].
+    __device__ inline int test_vals(const T (&col)[L], T cij, double tau, float tl, float band) const {
         T w[L];
         T ww = 0, yw = 0;
 #pragma unroll
         for (int r = 0; r < L; ++r) {
-            T s = cs(p, P[r]);
+            T s = col[r];
 #pragma unroll
             for (int e = 0; e < r; ++e) s -= Lm[r * (r + 1) / 2 + e] * w[e];
             w[r] = s * rd[r];
@@ -149,7 +157,7 @@ struct SetFactor {
             yw += y[r] * w[r];
         }
         const T h22 = (T)1 - ww;
-        const T h12 = ci(p) - yw;
+        const T h12 = cij - yw;
         if (sizeof(T) == 8) {
             if (!ok) return 2;  // rank-deficient M2: pseudo-inverse path of the re-check kernel
             const double rho = (h11 > 0 && h22 > 0) ? (double)h12 / sqrt((double)h11 * (double)h22) : 0.0;
@@ -167,9 +175,14 @@ struct SetFactor {
         }
         const float fh11 = (float)h11, fh22 = (float)h22;
         if (!ok || fh11 <= 2.0f * band * gi2 || fh22 <= 2.0f * band * gj2) return 2;
-        const float inv = rsqrtf(fh11 * fh22);
+        // v_rsq_f32 and v_rcp_f32 (1 ulp each): both pivots exceed 2 band > 0 here, far from the
+        // denormal range, so no input scaling is needed. err bounds the FP32 error of ar; it is
+        // inflated by 2^-16 so that the rounding of its own few operations cannot leave it short.
+        const float inv = __builtin_amdgcn_rsqf(fh11 * fh22);
         const float ar = fabsf((float)h12 * inv);
-        const float err = band * (gij * inv + 0.5f * ar * (gi2 / fh11 + gj2 / fh22));
+        const float err = band * (gij * inv + 0.5f * ar * (gi2 * __builtin_amdgcn_rcpf(fh11) +
+                                                            gj2 * __builtin_amdgcn_rcpf(fh22))) *
+                          (1.0f + 0x1p-16f);
         return ar <= tl - err ? 1 : (ar > tl + err ? 0 : 2);
     }
 };

@@ -16,19 +16,41 @@
 namespace pcg {
 
 // binom(a, b) must return C(a, b), and 0 when a < b. L is the subset size; t < C(d, L).
+//
+// Same function as the walk described above, with fewer table reads: the subsets whose element at
+// position c is below y, given elements before it and smallest candidate x, number
+// C(d - x, k) - C(d - y, k) with k = L - c (the hockey-stick identity summed over the skipped
+// values), so the element is the largest y with that count <= t, found by bisection when the
+// candidate range is long and by the step-by-step walk when it is short. At L = 1 the element is t.
 template <int L, typename Binom>
 __host__ __device__ inline void comb_unrank(int d, unsigned long long t, int (&P)[L > 0 ? L : 1],
                                             const Binom &binom) {
+    if constexpr (L == 1) {
+        P[0] = (int)t;
+        return;
+    }
     int x = 0;
 #pragma unroll
     for (int c = 0; c < L; ++c) {
-        for (; x < d; ++x) {  // x < d always holds for t < C(d, L); the bound is a guard
-            unsigned long long cnt = binom(d - 1 - x, L - 1 - c);
-            if (t < cnt) break;
-            t -= cnt;
+        const int k = L - c;
+        int lo = x, hi = d - k;   // the element lies in [lo, hi] for t < C(d - x, k)
+        if (hi - lo >= 8) {
+            const unsigned long long top = binom(d - x, k);
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (top - binom(d - mid, k) <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            t -= top - binom(d - lo, k);
+        } else {
+            for (; lo < hi; ++lo) {
+                const unsigned long long cnt = binom(d - 1 - lo, k - 1);
+                if (t < cnt) break;
+                t -= cnt;
+            }
         }
-        P[c] = x;
-        ++x;
+        P[c] = lo;
+        x = lo + 1;
     }
 }
 

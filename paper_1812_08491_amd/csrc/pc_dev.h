@@ -107,7 +107,7 @@ struct Batch {
     int count;
     int prec;
     int force_recheck;
-    int pad;
+    int lane_tests;                // bound on the CI tests one lane runs per work item (0: none)
     const long long *row_base;     // count + 1: first flattened row of each problem
     const long long *cs_base;      // count + 1: first k_colstats block
     const long long *st_base;      // count + 1: first k_standardize block
@@ -120,6 +120,19 @@ struct Batch {
     long long rq_cap;
     long long total_rows;
 };
+
+// Conditioning sets per work item of a row of degree d at level l, from the base count R. A set
+// costs about d - l tests (one per j), so rows with long neighbour lists get fewer sets per item,
+// down to one set whose j loop the whole work-group splits, until a lane runs at most `lane_tests`
+// tests per item. Deep levels (one set per wavefront) keep R. The planner and the level kernel
+// call this with the same arguments, so they agree on the item layout of every row.
+__host__ __device__ inline long long item_sets(int d, int l, long long R, int lane_tests) {
+    if (lane_tests <= 0 || l > kFastLevels) return R;
+    const long long jn = d - l > 1 ? d - l : 1;
+    long long r = R;
+    while (r > 1 && r * jn > (long long)lane_tests * kLevelThreads) r >>= 1;
+    return r;
+}
 
 // Largest k in [0, count) with base[k] <= x (base ascending, base[0] = 0).
 __device__ inline int find_base(const long long *base, int count, long long x) {
@@ -158,6 +171,7 @@ hipError_t launch_plan(hipStream_t s, const Batch &b, int level);
 hipError_t launch_level(hipStream_t s, const Batch &b, int level, int ranks_per_item, int lds_bytes,
                         int grid);
 hipError_t launch_recheck(hipStream_t s, const Batch &b, int level, int grid);
+int level_blocks_per_cu(int prec, int level, int lds_bytes);   // resident work-groups per CU
 size_t level_lds_fixed(int prec);
 
 // pc_mlp.hip

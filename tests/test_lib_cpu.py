@@ -6,6 +6,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 from scipy import stats
 
@@ -81,12 +82,35 @@ def test_comb_unrank_matches_paper_examples():
     assert seen == 8
 
 
-@pytest.mark.parametrize("d,l", [(1, 1), (5, 1), (6, 2), (9, 3), (11, 4), (13, 6), (14, 13)])
+@pytest.mark.parametrize("d,l", [(1, 1), (5, 1), (6, 2), (9, 3), (11, 4), (13, 6), (14, 13), (40, 2), (26, 3),
+                                 (64, 1), (20, 7)])
 def test_comb_unrank_is_lexicographic(d, l):
     for t, ref in enumerate(itertools.combinations(range(d), l)):
         assert pc.pc_comb_unrank(d, l, t) == list(ref)
     with pytest.raises(pc.PCError):
         pc.pc_comb_unrank(d, l, math.comb(d, l))
+
+
+def _unrank_by_counting(d, l, t):
+    """The t-th l-subset of range(d) in lexicographic order, by counting the subsets each candidate
+    element skips (the definition, with exact integers)."""
+    out, x = [], 0
+    for c in range(l):
+        while math.comb(d - 1 - x, l - 1 - c) <= t:
+            t -= math.comb(d - 1 - x, l - 1 - c)
+            x += 1
+        out.append(x)
+        x += 1
+    return out
+
+
+@pytest.mark.parametrize("d,l", [(585, 2), (1000, 3), (300, 5), (64, 13), (31, 30)])
+def test_comb_unrank_sampled_ranks_of_long_rows(d, l):
+    rng = np.random.default_rng(d * 100 + l)
+    total = math.comb(d, l)
+    ranks = {0, 1, total - 1, total - 2, total // 2} | {int(rng.integers(0, total)) for _ in range(300)}
+    for t in sorted(r for r in ranks if 0 <= r < total):
+        assert pc.pc_comb_unrank(d, l, t) == _unrank_by_counting(d, l, t), t
 
 
 @pytest.mark.parametrize("d,l,skip", [(6, 2, 4), (8, 3, 0), (8, 3, 7), (10, 1, 5)])
