@@ -4,7 +4,9 @@ One step = one whole skeleton (standardize, correlation GEMM with the level-0 te
 level until the stop rule, FP64 re-checks included) of a synthetic linear-Gaussian SEM dataset that
 is already resident in HBM: n = 1000 variables, expected degree 4, m = 500 samples, alpha = 0.01,
 FP32 CI tests with FP64 re-checks of borderline tests. The skeleton is captured once as a hipGraph
-(pc_batch_capture) and each step is one replay; `ms_per_step` is the replay time.
+(pc_batch_capture) and each step is one replay; `ms_per_step` is the replay time. The graph records
+as many levels as an untimed pc_skeleton run on the same data needed (graph_levels), and the run
+asserts that no replay needed the stream continuation of pc_graph_results.
 
 `value` is CI tests per second: the tests the sequential PC-stable enumeration performs on this
 input (canonical order, early stop per edge; counted by the CPU oracle in the cpu_baseline leg, on
@@ -146,10 +148,34 @@ def main() -> int:
     torch.cuda.set_device(0)
     Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
 
+    # -- the skeleton through pc_skeleton on the stream, HIP events around every kernel phase -------
+    stream = torch.cuda.current_stream()
+    ctx = pc.Context(stream=stream, precision="fp32", timing=1 | 2 | 4 | 8 | 16)
+    ws = ctx.workspace(n, m)
+    adj = ctx.adjacency(n)
+    recs, count = ctx.sepsets(n * (n - 1) // 2)
+    st = pc.pc_run_stats()
+    for _ in range(args.warmup):
+        ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st)
+    torch.cuda.synchronize()
+    runs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        status = ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st)
+        runs.append(st.as_dict())
+    torch.cuda.synchronize()
+    stream_sec = (time.perf_counter() - t0) / args.steps
+    assert status == 0, pc.status_str(status)
+    L = runs[-1]["levels_run"]
+    graph_levels = max(1, L - 1)
+
     # -- timed region: graph replays of the whole skeleton ----------------------------------------
     gstream = torch.cuda.Stream()
     with torch.cuda.stream(gstream):
-        gctx = pc.Context(stream=gstream, precision="fp32")
+        # The graph records as many levels as the eager run needed (levels 1 .. L-1, then the
+        # planning pass of level L that finds no work); a deeper replay would be continued by
+        # pc_graph_results, which the check below rules out for the timed replays.
+        gctx = pc.Context(stream=gstream, precision="fp32", graph_levels=graph_levels)
         gadj = gctx.adjacency(n)
         grecs, gcount = gctx.sepsets(n * (n - 1) // 2)
         probs = gctx.problems([(Xd, alpha, -1, gadj, grecs, gcount)])
@@ -169,28 +195,11 @@ def main() -> int:
     assert r == 0 and gstatus[0] == 0, (r, gstatus)
     G = pc.bits_to_dense(gadj.cpu().numpy(), n)
     gstats = gst[0].as_dict()
+    assert gstats["levels_run"] - 1 <= graph_levels, "the recorded graph did not cover every level"
+
     gpu_tests = int(sum(gstats["tests"]))
 
-    # -- the same skeleton through pc_skeleton on the stream, HIP events around every kernel phase ----
-    stream = torch.cuda.current_stream()
-    ctx = pc.Context(stream=stream, precision="fp32", timing=1 | 2 | 4 | 8 | 16)
-    ws = ctx.workspace(n, m)
-    adj = ctx.adjacency(n)
-    recs, count = ctx.sepsets(n * (n - 1) // 2)
-    st = pc.pc_run_stats()
-    for _ in range(args.warmup):
-        ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st)
-    torch.cuda.synchronize()
-    runs = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        status = ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st)
-        runs.append(st.as_dict())
-    torch.cuda.synchronize()
-    stream_sec = (time.perf_counter() - t0) / args.steps
-    assert status == 0, pc.status_str(status)
     same_as_graph = bool(np.array_equal(pc.bits_to_dense(adj.cpu().numpy(), n), G))
-    L = runs[-1]["levels_run"]
 
     def mean_of(key, lvl=None):
         v = [d[key] if lvl is None else d[key][lvl] for d in runs]
@@ -217,6 +226,7 @@ def main() -> int:
         "config": {"workload": "pc_stable_skeleton_n1000_deg4_m500_alpha0.01_fp32_recheck",
                    "n": n, "m": m, "expected_degree": 4, "alpha": alpha, "precision": "fp32+fp64 recheck",
                    "step": "one hipGraph replay of the whole skeleton",
+                   "graph_levels": graph_levels,
                    "levels_run": gstats["levels_run"], "edges": int(G.sum()) // 2},
         "gpu_tests_per_step": gpu_tests,
         "gpu_executed_tests_per_s": gpu_tests / sec_per_step,

@@ -292,6 +292,7 @@ __device__ inline void lds_and(lds_ptr<unsigned long long> p, unsigned long long
 // Level kernel
 // ---------------------------------------------------------------------------------------------
 constexpr int kStageCap = kLevelThreads;   // removals staged per item (one settling thread each)
+constexpr int kWaveSetLevels = 1;   // levels whose conditioning sets are shared by a whole wavefront
 constexpr int kDcap = 1024;   // neighbour lists up to this degree are staged in LDS
 constexpr int kWcap = 256;    // live-bit words of a row staged in LDS (n <= 16384)
 
@@ -434,23 +435,21 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         const long long r0 = s_item * Rr;
         const long long r1 = (long long)nS < r0 + Rr ? (long long)nS : r0 + Rr;
         const long long nr = r1 - r0;
-        int split, qn, slice;
-        long long my_t, my_end;
-        if (nr >= kLevelThreads) {
-            split = 1;
-            slice = 0;
-            qn = (int)((nr + kLevelThreads - 1) / kLevelThreads);
-            my_t = r0 + (long long)tid * qn;
-            my_end = my_t + qn < r1 ? my_t + qn : r1;
-        } else {
-            // Fewer sets than threads: several threads share one S and split its j loop.
-            split = 1;
+        // `split` threads share each conditioning set and divide its j loop; each group of them
+        // takes qn consecutive sets. At level 1 a set needs no factor, so a whole wavefront shares
+        // it: its lanes then read one row of C (or of the staged block) at consecutive neighbour
+        // positions, instead of 64 rows at once, and a wavefront's later sets skip the edges its
+        // earlier ones removed. Above (where sets are many and their j loops short), one thread per
+        // set, unless the item has fewer sets than threads.
+        int split = 1;
+        if (L <= kWaveSetLevels) split = 64;
+        else if (nr < kLevelThreads)
             while (split * 2 * nr <= kLevelThreads) split *= 2;
-            slice = tid % split;
-            qn = 1;
-            my_t = r0 + tid / split;
-            my_end = my_t < r1 ? my_t + 1 : my_t;
-        }
+        const int groups = kLevelThreads / split;
+        const int slice = tid % split;
+        const int qn = (int)((nr + groups - 1) / groups);
+        const long long my_t = r0 + (long long)(tid / split) * qn;
+        const long long my_end = my_t + qn < r1 ? my_t + qn : r1;
         const int psteps = (d + split - 1) / split;
         int since_refresh = 0;
 

@@ -55,6 +55,45 @@ __device__ inline int decide_wave(const double *G, int ld, int l, double tau, do
     return res;
 }
 
+// Pairwise dot products of up to four FP64 standardized rows v[0..K) (levels 1 and 2, where the
+// 16 x 16 MFMA tile would be mostly zero rows): each lane takes two consecutive samples of every
+// block of 128 starting at x_first (blocks x_step apart) and returns its partial sums of the pairs
+// (0,1), (0,2), (1,2), (0,3), (1,3), (2,3) in s.
+__device__ inline void gram_small_part(const Prob &P, const int *v, int K, int lane, int64_t x_first, int64_t x_step,
+                                       double (&s)[6]) {
+    const int64_t mp = P.mp;
+    const double *z0 = P.zt64 + (int64_t)v[0] * mp, *z1 = P.zt64 + (int64_t)v[1] * mp;
+    const double *z2 = P.zt64 + (int64_t)v[K > 2 ? 2 : 0] * mp, *z3 = P.zt64 + (int64_t)v[K > 3 ? 3 : 0] * mp;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s[q] = 0.0;
+    // mp is a multiple of 64, so both samples of a lane are inside whenever the first is.
+#pragma unroll 2
+    for (int64_t x = x_first + 2 * lane; x < mp; x += x_step) {
+        const double2 a = *reinterpret_cast<const double2 *>(z0 + x);
+        const double2 c = *reinterpret_cast<const double2 *>(z1 + x);
+        const double2 e = K > 2 ? *reinterpret_cast<const double2 *>(z2 + x) : double2{0.0, 0.0};
+        const double2 g = K > 3 ? *reinterpret_cast<const double2 *>(z3 + x) : double2{0.0, 0.0};
+        s[0] = fma(a.y, c.y, fma(a.x, c.x, s[0]));
+        s[1] = fma(a.y, e.y, fma(a.x, e.x, s[1]));
+        s[2] = fma(c.y, e.y, fma(c.x, e.x, s[2]));
+        s[3] = fma(a.y, g.y, fma(a.x, g.x, s[3]));
+        s[4] = fma(c.y, g.y, fma(c.x, g.x, s[4]));
+        s[5] = fma(e.y, g.y, fma(e.x, g.x, s[5]));
+    }
+}
+
+// Writes the K x K Gram block (row stride 16, unit diagonal) from the pair sums of gram_small_part.
+__device__ inline void gram_small_store(const double (&s)[6], int K, double *G) {
+    const int pa[6] = {0, 0, 1, 0, 1, 2}, pb[6] = {1, 2, 2, 3, 3, 3};
+    for (int r = 0; r < K; ++r) G[r * 16 + r] = 1.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        if (pb[q] < K) {
+            G[pa[q] * 16 + pb[q]] = s[q];
+            G[pb[q] * 16 + pa[q]] = s[q];
+        }
+}
+
 // Queued tests of levels up to 14 (at most 16 variables). The FP64 Gram block of the standardized
 // rows (i, j, S) is one 16 x 16 tile Z Z^T (gram_part); rows past l + 2 stay zero. On the FP64 path
 // the block is read from C. With few queued tests a work-group takes each one and its four
@@ -85,7 +124,22 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck(Batch b, int level) {
             __syncthreads();
             const int prob = s_prob;
             Prob &P = b.probs[prob];
-            if (b.prec != PC_PREC_FP64) {
+            if (b.prec != PC_PREC_FP64 && k <= 4) {
+                double sp[6];
+                gram_small_part(P, vw, k, lane, 128 * wave, 128 * kW, sp);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) sp[q] = wave_sum64(sp[q]);
+                if (lane == 0)
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) part[wave][q] = sp[q];
+                __syncthreads();
+                if (tid == 0) {
+                    double tot[6];
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) tot[q] = (part[0][q] + part[1][q]) + (part[2][q] + part[3][q]);
+                    gram_small_store(tot, k, Gw);
+                }
+            } else if (b.prec != PC_PREC_FP64) {
                 const doublex4 acc = gram_part(P, vw[lane & 15], lane, 256 * wave, 256 * kW);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) part[wave][((lane >> 4) + 4 * t) * 16 + (lane & 15)] = acc[t];
@@ -119,7 +173,13 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck(Batch b, int level) {
             const int prob = qe->prob, cls = qe->cls;
             wave_sync();
             Prob &P = b.probs[prob];
-            if (b.prec != PC_PREC_FP64) {
+            if (b.prec != PC_PREC_FP64 && k <= 4) {
+                double sp[6];
+                gram_small_part(P, vw, k, lane, 0, 128, sp);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) sp[q] = wave_sum64(sp[q]);
+                if (lane == 0) gram_small_store(sp, k, Gw);
+            } else if (b.prec != PC_PREC_FP64) {
                 const doublex4 acc = gram_part(P, vw[lane & 15], lane, 0, 256);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
