@@ -244,20 +244,32 @@ void pc_graph_destroy(pc_graph *g);
 #define PC_MLP_PARAMS 4801
 
 typedef struct {
-    const float *params;  /* device, PC_MLP_PARAMS values */
+    const float *params;      /* edge model, device, PC_MLP_PARAMS values (NULL: no probe pass) */
+    const float *row_params;  /* shared-set model, device, PC_MLP_PARAMS values (NULL: none) */
     int32_t min_level;    /* first level that runs the probe pass (1..8; default 2) */
+    int32_t max_level;    /* last level that runs it (min_level..8; 0 = 8) */
     int32_t top;          /* candidates kept per edge direction (1..8); the probe tests their
-                             C(top, level) subsets */
-    int64_t max_rows;     /* feature rows per level (sum over rows of d_i (d_i - 1)); a level that
-                             needs more runs without the probe */
+                             C(top, level) subsets, so levels above top have no probe */
+    int32_t row_top;      /* level 1, shared-set order: the row_top best-scored candidates k of
+                             every node are tested first, as sets {k} against all its edges, then
+                             the remaining ones (1..16; 0 = off) */
 } pc_order;
 
-/* Workspace of pc_skeleton_ordered (pc_workspace_bytes plus the feature and score buffers). */
+/* Workspace of pc_skeleton_ordered (the probe keeps its features and scores on chip, so this is
+ * pc_workspace_bytes). */
 size_t pc_ordered_workspace_bytes(int64_t n, int64_t m, const pc_options *opt, const pc_order *order);
 
-/* pc_skeleton with the probe pass before every level l in [order->min_level, 8]. The adjacency
- * after every level and the skeleton are those of pc_skeleton; SepSets may differ (any separating
- * S is valid). Statistics report the probe's tests and removals separately. */
+/* pc_skeleton with a learned order of the conditioning sets (two forms, either or both):
+ *  - shared-set order (row_params, row_top): at level 1 the model scores every candidate k of node
+ *    i from (i, k) features (|C_ik|, |C_ik| over the row's largest, |N_i & N_k| / d_i and / d_k, d_i, d_k,
+ *    the level, the row mean of |C_ij|), and the sets {k} of the row_top best are tested against
+ *    every edge of the row before the rest of the enumeration (rows of degree <= 1024);
+ *  - probe pass (params): before every level l with min_level <= l <= max_level and l <= top. The probe runs in one kernel per level: for every row i of G' with l + 1 <= d_i <= 48,
+ * the MLP (BF16 weights and activations, FP32 accumulation) scores every candidate k of every
+ * edge (i, j), and for every live edge the C(top, l) subsets of its best-scored candidates are
+ * tested with the level's test (rows with more neighbours are left to the plain enumeration). The
+ * adjacency after every level and the skeleton are those of pc_skeleton; SepSets may differ (any
+ * separating S is valid). Statistics report the probe's tests and removals separately. */
 pc_status pc_skeleton_ordered(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alpha,
                               int max_level, const pc_order *order, uint64_t *adj_out,
                               const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes);
@@ -270,6 +282,16 @@ pc_status pc_skeleton_ordered(pc_ctx *ctx, const double *X, int64_t m, int64_t n
 pc_status pc_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, const uint64_t *adj,
                       float *feats, int32_t *meta, int64_t cap, int64_t *rows_out, void *ws,
                       size_t ws_bytes);
+
+/* Training rows of the shared-set order at level 1 for the snapshot adj (device bit matrix, not
+ * modified): one row per (i, k in N_i), ordered by i then position of k, with the 8 features of
+ * pc_skeleton_ordered's row model, label 1.0 when {k} separates at least one edge (i, j) by the FP32
+ * test (|rho_ij.k| <= tanh(tau_1), no re-check band) and 0.0 otherwise, and meta (i, k).
+ *   feats device rows x 8 FP32; labels device rows FP32; meta device rows x 2 int32 (optional).
+ *   level must be 1; other arguments as in pc_features. Synchronises the stream. */
+pc_status pc_row_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, const uint64_t *adj,
+                          float *feats, float *labels, int32_t *meta, int64_t cap, int64_t *rows_out,
+                          void *ws, size_t ws_bytes);
 
 /* MLP kernels (stream ordered, asynchronous), exported for training and gradient checks.
  *   forward : scores[r] = MLP(X[r]) for rows x 8 inputs; act (optional, rows x 128) keeps the

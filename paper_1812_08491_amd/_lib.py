@@ -56,8 +56,8 @@ PC_MLP_PARAMS = 4801
 
 
 class pc_order(ct.Structure):
-    _fields_ = [("params", ct.c_void_p), ("min_level", ct.c_int32), ("top", ct.c_int32),
-                ("max_rows", ct.c_int64)]
+    _fields_ = [("params", ct.c_void_p), ("row_params", ct.c_void_p), ("min_level", ct.c_int32),
+                ("max_level", ct.c_int32), ("top", ct.c_int32), ("row_top", ct.c_int32)]
 
 
 class pc_problem(ct.Structure):
@@ -163,6 +163,9 @@ def lib() -> ct.CDLL:
         L.pc_features.argtypes = [vp, ct.c_int, i64, i64, ct.c_double, vp, fp, vp, i64, ct.POINTER(i64), vp,
                                   ct.c_size_t]
         L.pc_features.restype = ct.c_int
+        L.pc_row_features.argtypes = [vp, ct.c_int, i64, i64, ct.c_double, vp, fp, fp, vp, i64, ct.POINTER(i64), vp,
+                                      ct.c_size_t]
+        L.pc_row_features.restype = ct.c_int
         L.pc_mlp_forward.argtypes = [vp, fp, fp, i64, fp, fp]
         L.pc_mlp_forward.restype = ct.c_int
         L.pc_mlp_backward.argtypes = [vp, fp, fp, i64, fp, fp, fp, fp]
@@ -184,7 +187,7 @@ EXPORTED = ["pc_create", "pc_destroy", "pc_default_options", "pc_workspace_bytes
             "pc_level", "pc_skeleton", "pc_sync_status", "pc_comb_unrank", "pc_threshold",
             "pc_abi_size", "pc_status_str", "pc_batch_workspace_bytes", "pc_batch_skeleton",
             "pc_batch_capture", "pc_graph_launch", "pc_graph_results", "pc_graph_destroy",
-            "pc_ordered_workspace_bytes", "pc_skeleton_ordered", "pc_features", "pc_mlp_forward",
+            "pc_ordered_workspace_bytes", "pc_skeleton_ordered", "pc_features", "pc_row_features", "pc_mlp_forward",
             "pc_mlp_backward", "pc_mlp_bce", "pc_mlp_adam"]
 
 
@@ -359,9 +362,17 @@ class Context:
 
     # -- learned ordering ----------------------------------------------------------------------
     @staticmethod
-    def order(params, min_level: int = 2, top: int = 4, max_rows: int = 1 << 23) -> pc_order:
-        assert params.is_cuda and params.dtype == _torch().float32 and params.numel() == PC_MLP_PARAMS
-        return pc_order(params.data_ptr(), min_level, top, max_rows)
+    def order(params=None, min_level: int = 2, top: int = 4, max_level: int = 0, row_params=None,
+              row_top: int = 0) -> pc_order:
+        """Learned order: the probe pass of the edge model `params` at levels min_level .. max_level
+        (0 = 8) that are <= top, and/or the shared-set order of the row model `row_params` at level 1
+        (its row_top best candidates per node first)."""
+        torch = _torch()
+        for p in (params, row_params):
+            assert p is None or (p.is_cuda and p.dtype == torch.float32 and p.numel() == PC_MLP_PARAMS)
+        return pc_order(params.data_ptr() if params is not None else None,
+                        row_params.data_ptr() if row_params is not None else None,
+                        min_level, max_level, top, row_top)
 
     def ordered_workspace(self, n: int, m: int, order: pc_order):
         torch = _torch()
@@ -391,6 +402,23 @@ class Context:
         if r == PC_ERR_WORKSPACE:
             return -int(rows.value)          # negative: the capacity needed
         _check(r, "pc_features")
+        return int(rows.value)
+
+    def pc_row_features(self, level: int, n: int, m: int, alpha: float, adj, feats, labels, meta, ws) -> int:
+        """Training rows of the shared-set order (see include/pc.h); returns the row count, or minus
+        the capacity needed when feats holds too few rows."""
+        torch = _torch()
+        assert feats.is_cuda and feats.dtype == torch.float32 and feats.shape[1:] == (PC_MLP_IN,)
+        assert labels.is_cuda and labels.dtype == torch.float32 and labels.numel() >= feats.shape[0]
+        assert meta is None or (meta.is_cuda and meta.dtype == torch.int32 and meta.numel() >= 2 * feats.shape[0])
+        rows = ct.c_int64()
+        r = lib().pc_row_features(self.h, level, n, m, alpha, ct.c_void_p(adj.data_ptr()),
+                                  ct.c_void_p(feats.data_ptr()), ct.c_void_p(labels.data_ptr()),
+                                  ct.c_void_p(meta.data_ptr()) if meta is not None else None,
+                                  feats.shape[0], ct.byref(rows), ct.c_void_p(ws.data_ptr()), ws.numel())
+        if r == PC_ERR_WORKSPACE:
+            return -int(rows.value)
+        _check(r, "pc_row_features")
         return int(rows.value)
 
     @staticmethod

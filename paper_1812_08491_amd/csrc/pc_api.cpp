@@ -162,15 +162,12 @@ struct Plan {
     int64_t rq_cap = 0;
     long long total_rows = 0, cs_blocks = 0, st_blocks = 0, tiles = 0;
     int64_t max_n = 0;
-    size_t foff = 0, skip = 0, feats = 0, scores = 0;   // learned-ordering buffers (if any)
-    long long order_rows = 0;
     std::vector<Region> reg;
     std::vector<long long> row_base, cs_base, st_base, tile_base;
 };
 
-// (n, m) of each problem; prec and rq_cap from the options; order_rows > 0 adds the buffers of
-// the learned ordering (feature rows per level).
-Plan make_plan(const int64_t *ns, const int64_t *ms, int count, const pc_options &o, long long order_rows = 0) {
+// (n, m) of each problem; prec and rq_cap from the options.
+Plan make_plan(const int64_t *ns, const int64_t *ms, int count, const pc_options &o) {
     Plan L;
     L.count = count;
     L.prec = o.precision;
@@ -215,13 +212,6 @@ Plan make_plan(const int64_t *ns, const int64_t *ms, int count, const pc_options
         r.adj = take(sizeof(unsigned long long) * n * (size_t)words_per_row((int64_t)n));
         r.nbr = take(sizeof(int32_t) * n * n);
         r.deg = take(sizeof(int32_t) * n);
-    }
-    if (order_rows > 0) {
-        L.order_rows = order_rows;
-        L.foff = take(sizeof(long long) * (size_t)(L.total_rows + 1));
-        L.skip = take(sizeof(int));
-        L.feats = take(sizeof(float) * PC_MLP_IN * (size_t)order_rows);
-        L.scores = take(sizeof(float) * (size_t)order_rows);
     }
     L.total = off;
     return L;
@@ -268,6 +258,9 @@ void fill_probs(const pc_ctx *ctx, const Plan &L, unsigned char *ws, const pc_pr
 
 Batch make_batch(const pc_ctx *ctx, const Plan &L, unsigned char *ws) {
     Batch b{};
+    b.rank_lo = 0;
+    b.rank_hi = ~0ull;
+    b.probe = 0;
     b.probs = reinterpret_cast<Prob *>(ws + L.table);
     b.count = L.count;
     b.prec = L.prec;
@@ -378,6 +371,13 @@ struct OrderRun {
 
 constexpr int kProbeMaxLevel = 8;
 
+// Whether level l runs the probe pass of the ordering.
+bool probe_level(const pc_order *o, int level) {
+    if (!o->params) return false;
+    const int hi = o->max_level > 0 ? o->max_level : kProbeMaxLevel;
+    return level >= o->min_level && level <= hi && level <= kProbeMaxLevel && level <= o->top;
+}
+
 // Compaction and planning of one level: the snapshot G' and the work plan (and the stop rule's
 // maximum degree) of every problem. Level PC_MAX_LEVEL + 1 is planned only, to tell whether the
 // level cap stopped a run.
@@ -395,21 +395,24 @@ pc_status enqueue_plan(pc_ctx *ctx, const Batch &b, int level, bool capturing) {
 pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, const OrderRun *ord) {
     hipStream_t s = ctx->stream;
     const int R = ranks_per_item(ctx, level);
-    // The probe tests subsets of the top candidates: none exist once the level exceeds top.
-    if (ord && level >= ord->order->min_level && level <= kProbeMaxLevel && level <= ord->order->top) {
-        const Plan &L = *ord->L;
-        long long *foff = reinterpret_cast<long long *>(ord->ws + L.foff);
-        int *skip = reinterpret_cast<int *>(ord->ws + L.skip);
-        float *feats = reinterpret_cast<float *>(ord->ws + L.feats);
-        float *scores = reinterpret_cast<float *>(ord->ws + L.scores);
-        PC_HIP(launch_feat_plan(s, b, foff, L.order_rows, skip));
-        PC_HIP(launch_features(s, b, level, foff, feats, nullptr, skip));
-        PC_HIP(launch_mlp_forward(s, ord->order->params, feats, 0, foff + L.total_rows, L.order_rows, scores,
-                                  nullptr, skip, 4 * ctx->num_cu));
-        PC_HIP(launch_probe(s, b, level, foff, scores, ord->order->top, skip));
-    }
+    // Probe pass of the learned ordering: the best-scored subsets of every edge, before the plain
+    // enumeration of the same level.
+    if (ord && probe_level(ord->order, level) && !(ord->order->row_params && level == 1))
+        PC_HIP(launch_probe(s, b, level, ord->order->params, ord->order->top, ctx->num_cu));
     if (timed(ctx, 2, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][0], s));
-    PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx), auto_grid(ctx, level)));
+    if (ord && ord->order->row_params && level == 1) {
+        // Shared-set order: each row's best-scored candidates move to the front of its neighbour
+        // list and their sets are tested first (in the ordering kernel), then the level kernel runs
+        // the remaining ranks; together they cover every set of the level once, on the same G'.
+        const int T = ord->order->row_top;
+        PC_HIP(launch_row_order(s, b, level, ord->order->row_params, T, 2 * ctx->num_cu));
+        Batch bm = b;
+        bm.rank_lo = (unsigned long long)T;
+        PC_HIP(launch_window(s, bm, level, R));
+        PC_HIP(launch_level(s, bm, level, R, level_lds_bytes(ctx), auto_grid(ctx, level)));
+    } else {
+        PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx), auto_grid(ctx, level)));
+    }
     if (timed(ctx, 2, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][1], s));
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][0], s));
     PC_HIP(launch_recheck(s, b, level, 4 * ctx->num_cu));
@@ -597,8 +600,12 @@ pc_status enqueue_skeletons(pc_ctx *ctx, const pc_problem *pp, int count, const 
 }
 
 bool valid_order(const pc_order *o) {
-    return o && o->params && o->min_level >= 1 && o->min_level <= kProbeMaxLevel && o->top >= 1 && o->top <= 8 &&
-           o->max_rows > 0;
+    if (!o || (!o->params && !o->row_params)) return false;
+    if (o->params && !(o->min_level >= 1 && o->min_level <= kProbeMaxLevel && o->top >= 1 && o->top <= 8 &&
+                       (o->max_level == 0 || (o->max_level >= o->min_level && o->max_level <= kProbeMaxLevel))))
+        return false;
+    if (o->row_params && !(o->row_top >= 1 && o->row_top <= 16)) return false;
+    return true;
 }
 
 // Validates a batch and prepares its table in the workspace.
@@ -905,9 +912,8 @@ void pc_graph_destroy(pc_graph *g) {
 }
 
 size_t pc_ordered_workspace_bytes(int64_t n, int64_t m, const pc_options *opt, const pc_order *order) {
-    pc_options o = opt ? *opt : defaults();
-    if (n < 1 || m < 1 || !order || order->max_rows <= 0) return 0;
-    return make_plan(&n, &m, 1, o, order->max_rows).total;
+    if (!valid_order(order)) return 0;
+    return pc_workspace_bytes(n, m, opt);
 }
 
 pc_status pc_skeleton_ordered(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alpha,
@@ -924,7 +930,7 @@ pc_status pc_skeleton_ordered(pc_ctx *ctx, const double *X, int64_t m, int64_t n
     p.sep = *sep;
     pc_status s = check_problem(p);
     if (s != PC_OK) return s;
-    const Plan L = make_plan(&n, &m, 1, ctx->opt, order->max_rows);
+    const Plan L = make_plan(&n, &m, 1, ctx->opt);
     if ((s = check_ws(ws, ws_bytes, L)) != PC_OK) return s;
     if ((s = ensure_binom(ctx, n)) != PC_OK) return s;
     const auto t0 = std::chrono::steady_clock::now();
@@ -944,14 +950,16 @@ pc_status pc_skeleton_ordered(pc_ctx *ctx, const double *X, int64_t m, int64_t n
     return status;
 }
 
-pc_status pc_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, const uint64_t *adj,
-                      float *feats, int32_t *meta, int64_t cap, int64_t *rows_out, void *ws,
-                      size_t ws_bytes) {
-    if (!ctx || !adj || !feats || !rows_out || cap < 0) return PC_ERR_INVALID_ARG;
+namespace {
+
+// Common part of the feature calls: the snapshot copied into the workspace, the problem table of
+// the level, and G' compacted from the snapshot.
+pc_status features_setup(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, const uint64_t *adj, void *ws,
+                         size_t ws_bytes, Plan &L, Batch &b) {
     if (level < 1 || level > PC_MAX_LEVEL || !(alpha > 0.0 && alpha < 1.0)) return PC_ERR_INVALID_ARG;
     pc_status s = check_shape(n, m);
     if (s != PC_OK) return s;
-    const Plan L = make_plan(&n, &m, 1, ctx->opt);
+    L = make_plan(&n, &m, 1, ctx->opt);
     if ((s = check_ws(ws, ws_bytes, L)) != PC_OK) return s;
     if ((s = ensure_binom(ctx, n)) != PC_OK) return s;
     unsigned char *w = static_cast<unsigned char *>(ws);
@@ -966,19 +974,53 @@ pc_status pc_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha
     std::vector<Prob> probs;
     fill_probs(ctx, L, w, &p, probs);
     if ((s = upload_table(ctx, L, w, probs)) != PC_OK) return s;
-    const Batch b = make_batch(ctx, L, w);
+    b = make_batch(ctx, L, w);
     PC_HIP(launch_rearm(ctx->stream, b));
     PC_HIP(launch_compact(ctx->stream, b, level, ranks_per_item(ctx, level)));
+    return PC_OK;
+}
+
+// Reads the feature row count (the last entry of the row offsets) and synchronises.
+pc_status feature_rows(pc_ctx *ctx, const long long *foff, long long total_rows, int64_t cap, int64_t *rows_out) {
+    long long rows = 0;
+    PC_HIP(hipMemcpyAsync(&rows, foff + total_rows, sizeof(rows), hipMemcpyDeviceToHost, ctx->stream));
+    PC_HIP(hipStreamSynchronize(ctx->stream));
+    *rows_out = rows;
+    return rows > cap ? PC_ERR_WORKSPACE : PC_OK;
+}
+
+}  // namespace
+
+pc_status pc_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, const uint64_t *adj,
+                      float *feats, int32_t *meta, int64_t cap, int64_t *rows_out, void *ws,
+                      size_t ws_bytes) {
+    if (!ctx || !adj || !feats || !rows_out || cap < 0) return PC_ERR_INVALID_ARG;
+    Plan L;
+    Batch b;
+    pc_status s = features_setup(ctx, level, n, m, alpha, adj, ws, ws_bytes, L, b);
+    if (s != PC_OK) return s;
+    unsigned char *w = static_cast<unsigned char *>(ws);
     // Feature offsets go to the level's item-offset buffer (free until the level runs).
     long long *foff = reinterpret_cast<long long *>(w + L.item_off);
     int *skip = reinterpret_cast<int *>(w + L.nitems);
     PC_HIP(launch_feat_plan(ctx->stream, b, foff, cap, skip));
     PC_HIP(launch_features(ctx->stream, b, level, foff, feats, meta, skip));
-    long long rows = 0;
-    PC_HIP(hipMemcpyAsync(&rows, foff + L.total_rows, sizeof(rows), hipMemcpyDeviceToHost, ctx->stream));
-    PC_HIP(hipStreamSynchronize(ctx->stream));
-    *rows_out = rows;
-    return rows > cap ? PC_ERR_WORKSPACE : PC_OK;
+    return feature_rows(ctx, foff, L.total_rows, cap, rows_out);
+}
+
+pc_status pc_row_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, const uint64_t *adj,
+                          float *feats, float *labels, int32_t *meta, int64_t cap, int64_t *rows_out,
+                          void *ws, size_t ws_bytes) {
+    if (!ctx || !adj || !feats || !labels || !rows_out || cap < 0 || level != 1) return PC_ERR_INVALID_ARG;
+    Plan L;
+    Batch b;
+    pc_status s = features_setup(ctx, level, n, m, alpha, adj, ws, ws_bytes, L, b);
+    if (s != PC_OK) return s;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    long long *foff = reinterpret_cast<long long *>(w + L.item_off);
+    int *skip = reinterpret_cast<int *>(w + L.nitems);
+    PC_HIP(launch_row_features(ctx->stream, b, level, foff, cap, skip, feats, labels, meta));
+    return feature_rows(ctx, foff, L.total_rows, cap, rows_out);
 }
 
 pc_status pc_mlp_forward(pc_ctx *ctx, const float *params, const float *X, int64_t rows, float *scores,

@@ -119,7 +119,20 @@ struct Batch {
     RqEntry *rq;
     long long rq_cap;
     long long total_rows;
+    // Conditioning-set ranks a level launch covers: [rank_lo, rank_hi) of each row's lexicographic
+    // enumeration (0 and ~0 for all of them); probe = 1 marks the probe pass of a learned order,
+    // whose tests and removals are also counted as probe statistics.
+    unsigned long long rank_lo, rank_hi;
+    int probe;
+    int pad2;
 };
+
+// The ranks [lo, hi) of a row with nS conditioning sets that a launch covers.
+__host__ __device__ inline void rank_window(const Batch &b, unsigned long long nS, unsigned long long &lo,
+                                            unsigned long long &hi) {
+    lo = b.rank_lo < nS ? b.rank_lo : nS;
+    hi = b.rank_hi < nS ? b.rank_hi : nS;
+}
 
 // Conditioning sets per work item of a row of degree d at level l, from the base count R. A set
 // costs about d - l tests (one per j), so rows with long neighbour lists get fewer sets per item,
@@ -168,6 +181,9 @@ hipError_t launch_corr(hipStream_t s, const Batch &b, long long tiles);
 // pc_level.hip
 hipError_t launch_compact(hipStream_t s, const Batch &b, int level, int ranks_per_item);
 hipError_t launch_plan(hipStream_t s, const Batch &b, int level);
+// Work items of a rank window over the current G' (no compaction), then its queue; the level's
+// stop flag, statistics and re-check queue are left as they are.
+hipError_t launch_window(hipStream_t s, const Batch &b, int level, int ranks_per_item);
 hipError_t launch_level(hipStream_t s, const Batch &b, int level, int ranks_per_item, int lds_bytes,
                         int grid);
 hipError_t launch_recheck(hipStream_t s, const Batch &b, int level, int grid);
@@ -187,7 +203,12 @@ hipError_t launch_adam(hipStream_t s, float *params, const float *grads, float *
 hipError_t launch_feat_plan(hipStream_t s, const Batch &b, long long *foff, long long cap, int *skip);
 hipError_t launch_features(hipStream_t s, const Batch &b, int level, const long long *foff, float *feats,
                            int *meta, const int *skip);
-hipError_t launch_probe(hipStream_t s, const Batch &b, int level, const long long *foff, const float *scores,
-                        int topq, const int *skip);
+// Shared-set order: reorders each row's neighbour list, the `top` best-scored candidates first.
+hipError_t launch_row_order(hipStream_t s, const Batch &b, int level, const float *params, int top, int grid);
+// Training rows of the shared-set order (features, labels, meta (i, k)) after a compaction.
+hipError_t launch_row_features(hipStream_t s, const Batch &b, int level, long long *foff, long long cap, int *skip,
+                               float *feats, float *labels, int *meta);
+// grid: compute units; the probe launches as many work-groups per unit as fit.
+hipError_t launch_probe(hipStream_t s, const Batch &b, int level, const float *params, int topq, int grid);
 
 }  // namespace pcg

@@ -50,9 +50,13 @@ __device__ inline long long wave_sum_ll(long long v) {
 
 // Adds a work-group's test and removal counts of level L to its problem and clears them.
 template <int L>
-__device__ inline void flush_stats(Prob &P, long long &tests, long long &removed) {
+__device__ inline void flush_stats(const Batch &b, Prob &P, long long &tests, long long &removed) {
     if (tests) add_ll(&P.tests[L], tests);
     if (removed) add_ll(&P.removed[L], removed);
+    if (b.probe) {
+        if (tests) add_ll(&P.probe_tests[L], tests);
+        if (removed) add_ll(&P.probe_removed[L], removed);
+    }
     tests = 0;
     removed = 0;
 }
@@ -322,6 +326,8 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
     __shared__ int s_stage_j[kStageCap];
     __shared__ unsigned long long s_stage_t[kStageCap];
     __shared__ unsigned long long s_rec_base;
+    __shared__ int s_livepos[kDcap];   // positions p whose edge (i, N_i[p]) is live at item start
+    __shared__ long long s_scan[kLevelThreads / 64];
 
     DevState *st = b.st;
     if (st->done) return;
@@ -378,7 +384,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         const int pd = find_base(b.row_base, b.count, grow);
         if (pd != stats_pd) {
             // Counts are kept per work-group and written once per problem it worked on.
-            if (tid == 0 && stats_pd >= 0) flush_stats<L>(b.probs[stats_pd], s_tests, s_removed);
+            if (tid == 0 && stats_pd >= 0) flush_stats<L>(b, b.probs[stats_pd], s_tests, s_removed);
             stats_pd = pd;
         }
         const Prob &P = b.probs[pd];
@@ -427,13 +433,35 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         __syncthreads();
         const int mode = __builtin_amdgcn_readfirstlane(s_mode);
         const glb_ptr<const int> nbg = (glb_ptr<const int>)(P.nbr + (int64_t)row * n);
+        // When the neighbour list and live bits sit in LDS, the j loops run over the positions whose
+        // edge is still live at item start (edges removed earlier cannot be tested), in order.
+        int nlive = d;
+        if ((mode & 5) == 5) {
+            int base = 0;
+            for (int p0 = 0; p0 < d; p0 += kLevelThreads) {
+                const int p = p0 + tid;
+                bool f = false;
+                if (p < d) {
+                    const int j = lds_nb[p];
+                    f = (lds_live[j >> 6] >> (j & 63)) & 1ull;
+                }
+                long long tot = 0;
+                const long long pre = block_exclusive_scan<kLevelThreads>(f ? 1 : 0, s_scan, tot);
+                if (f) s_livepos[base + (int)pre] = p;
+                base += (int)tot;
+                __syncthreads();
+            }
+            nlive = base;
+        }
         const double tau = P.tau[L];
         const float tl = P.t[L], band = P.band[L];
 
         const unsigned long long nS = binom(d, L);
+        unsigned long long wlo, whi;
+        rank_window(b, nS, wlo, whi);
         const long long Rr = item_sets(d, L, R, b.lane_tests);
-        const long long r0 = s_item * Rr;
-        const long long r1 = (long long)nS < r0 + Rr ? (long long)nS : r0 + Rr;
+        const long long r0 = (long long)wlo + s_item * Rr;
+        const long long r1 = (long long)whi < r0 + Rr ? (long long)whi : r0 + Rr;
         const long long nr = r1 - r0;
         // `split` threads share each conditioning set and divide its j loop; each group of them
         // takes qn consecutive sets. At level 1 a set needs no factor, so a whole wavefront shares
@@ -450,7 +478,6 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         const int qn = (int)((nr + groups - 1) / groups);
         const long long my_t = r0 + (long long)(tid / split) * qn;
         const long long my_end = my_t + qn < r1 ? my_t + qn : r1;
-        const int psteps = (d + split - 1) / split;
         int since_refresh = 0;
 
         int P_[L];
@@ -462,6 +489,13 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         // together instead of waiting on each one.
         auto run_sets = [&](auto kind) {
             constexpr int K = decltype(kind)::value;
+            // Candidate positions: the live list (K != 0) or all of N_i.
+            const int ncand = K != 0 ? nlive : d;
+            const int psteps = (ncand + split - 1) / split;
+            auto POS = [&](int idx) -> int {
+                if constexpr (K != 0) return s_livepos[idx];
+                else return idx;
+            };
             auto NB = [&](int p) -> int {
                 if constexpr (K != 0) return lds_nb[p];
                 else return (mode & 1) ? lds_nb[p] : nbg[p];
@@ -504,9 +538,9 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                     if ((K != 0 || (mode & 4)) && (since_refresh += kBatch) >= 16) {
                         // Fold in removals made by other work-groups since the row was staged.
                         since_refresh = 0;
-                        const int p = pp0 * split + slice;
-                        if (p < d) {
-                            const int j = NB(p);
+                        const int idx = pp0 * split + slice;
+                        if (idx < ncand) {
+                            const int j = NB(POS(idx));
                             lds_and(lds_live + (j >> 6), live_word(adj_row + (j >> 6)));
                         }
                     }
@@ -515,8 +549,9 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                     bool go[kBatch];
     #pragma unroll
                     for (int u = 0; u < kBatch; ++u) {
-                        const int p = (pp0 + u) * split + slice;
-                        bool ok = pp0 + u < psteps && p < d;
+                        const int idx = (pp0 + u) * split + slice;
+                        bool ok = pp0 + u < psteps && idx < ncand;
+                        const int p = ok ? POS(idx) : 0;
     #pragma unroll
                         for (int c = 0; c < L; ++c) ok &= P_[c] != p;
                         const int j = ok ? NB(p) : 0;
@@ -609,7 +644,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         my_tests = 0;
         my_removed = 0;
     }
-    if (tid == 0 && stats_pd >= 0) flush_stats<L>(b.probs[stats_pd], s_tests, s_removed);
+    if (tid == 0 && stats_pd >= 0) flush_stats<L>(b, b.probs[stats_pd], s_tests, s_removed);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -676,7 +711,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level_deep(Batch b, int R) {
                 }
                 if (tid == 0) {
                     s_grow = lo;
-                    s_r0 = (long long)(g - (unsigned long long)b.item_off[lo]) * R;
+                    s_r0 = (long long)(g - (unsigned long long)b.item_off[lo]);
                 }
             }
         }
@@ -687,7 +722,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level_deep(Batch b, int R) {
         last_row = grow;
         const int pd = find_base(b.row_base, b.count, grow);
         if (pd != stats_pd) {
-            if (tid == 0 && stats_pd >= 0) flush_stats<L>(b.probs[stats_pd], s_tests, s_removed);
+            if (tid == 0 && stats_pd >= 0) flush_stats<L>(b, b.probs[stats_pd], s_tests, s_removed);
             stats_pd = pd;
         }
         const Prob &P = b.probs[pd];
@@ -725,8 +760,10 @@ __global__ __launch_bounds__(kLevelThreads) void k_level_deep(Batch b, int R) {
         const double tol = sizeof(T) == 8 ? 1e-12 : 1e-4;
 
         const unsigned long long nS = binom(d, L);
-        const long long r0 = s_r0;
-        const long long r1 = (long long)nS < r0 + R ? (long long)nS : r0 + R;
+        unsigned long long wlo, whi;
+        rank_window(b, nS, wlo, whi);
+        const long long r0 = (long long)wlo + s_r0 * R;
+        const long long r1 = (long long)whi < r0 + R ? (long long)whi : r0 + R;
         for (long long t = r0 + wave; t < r1; t += kDeepWaves) {
             int Q[L];
             comb_unrank<L>(d, (unsigned long long)t, Q, binom);
@@ -858,7 +895,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level_deep(Batch b, int R) {
         my_tests = 0;
         my_removed = 0;
     }
-    if (tid == 0 && stats_pd >= 0) flush_stats<L>(b.probs[stats_pd], s_tests, s_removed);
+    if (tid == 0 && stats_pd >= 0) flush_stats<L>(b, b.probs[stats_pd], s_tests, s_removed);
 }
 
 template <typename T, int L>

@@ -9,6 +9,21 @@ namespace pcg {
 // ---------------------------------------------------------------------------------------------
 constexpr unsigned long long kMaxSetsPerRow = 1ull << 40;
 
+// Work items of a row of degree `count` at `level` within the launch's rank window (0 when the
+// row has fewer than level + 1 neighbours or the level is disabled for its problem).
+__device__ inline long long row_items(const Batch &b, const Prob &P, int count, int level, int R) {
+    if (count < level + 1 || !level_enabled(P, level)) return 0;
+    const unsigned long long nS = b.binom[(int64_t)count * kBinomCols + level];
+    if (nS > kMaxSetsPerRow) {
+        atomicOr(&b.st->overflow, 1);
+        return 0;
+    }
+    unsigned long long lo, hi;
+    rank_window(b, nS, lo, hi);
+    const unsigned long long r = (unsigned long long)item_sets(count, level, R, b.lane_tests);
+    return (long long)((hi - lo + r - 1) / r);
+}
+
 __global__ __launch_bounds__(256) void k_compact(Batch b, int level, int R) {
     if (b.st->done) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -44,18 +59,18 @@ __global__ __launch_bounds__(256) void k_compact(Batch b, int level, int R) {
     }
     if (lane == 0) {
         P.deg[i] = count;
-        long long items = 0;
-        if (count >= level + 1 && level_enabled(P, level)) {
-            const unsigned long long nS = b.binom[(int64_t)count * kBinomCols + level];
-            if (nS > kMaxSetsPerRow) {
-                atomicOr(&b.st->overflow, 1);
-            } else {
-                const unsigned long long r = (unsigned long long)item_sets(count, level, R, b.lane_tests);
-                items = (long long)((nS + r - 1) / r);
-            }
-        }
-        b.nitems[grow] = items;
+        b.nitems[grow] = row_items(b, P, count, level, R);
     }
+}
+
+// Per row of G': work items of a launch's rank window, from the degree the compaction stored.
+__global__ __launch_bounds__(256) void k_window(Batch b, int level, int R) {
+    if (b.st->done) return;
+    const long long grow = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (grow >= b.total_rows) return;
+    const int d = find_base(b.row_base, b.count, grow);
+    const Prob &P = b.probs[d];
+    b.nitems[grow] = row_items(b, P, P.deg[grow - b.row_base[d]], level, R);
 }
 
 hipError_t launch_compact(hipStream_t s, const Batch &b, int level, int ranks_per_item) {
@@ -67,7 +82,7 @@ hipError_t launch_compact(hipStream_t s, const Batch &b, int level, int ranks_pe
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanLdsProbs = 4096;     // problems whose max degree is reduced in LDS
 
-__global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level) {
+__global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level, int window) {
     __shared__ long long part[kPlanThreads / 64];
     DevState *st = b.st;
     if (st->done) return;
@@ -87,9 +102,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level) {
         b.item_off[N] = total;
         st->total_items = (unsigned long long)total;
         st->next_item = 0ull;
-        st->rq_count = 0ull;
-        if (total == 0) st->done = 1;
+        if (!window) {
+            st->rq_count = 0ull;
+            if (total == 0) st->done = 1;
+        }
     }
+    if (window) return;   // a window of a planned level: its statistics and stop flag stand
     __syncthreads();
     for (int d = tid; d < b.count; d += kPlanThreads)
         b.probs[d].items[level] = b.item_off[b.row_base[d + 1]] - b.item_off[b.row_base[d]];
@@ -128,7 +146,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level) {
 }
 
 hipError_t launch_plan(hipStream_t s, const Batch &b, int level) {
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, b, level);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, b, level, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_window(hipStream_t s, const Batch &b, int level, int ranks_per_item) {
+    hipLaunchKernelGGL(k_window, dim3((unsigned)((b.total_rows + 255) / 256)), dim3(256), 0, s, b, level,
+                       ranks_per_item);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, b, level, 1);
     return hipGetLastError();
 }
 

@@ -295,7 +295,8 @@ hipError_t launch_adam(hipStream_t s, float *params, const float *grads, float *
 // Exclusive offsets of the feature rows of each flattened row (d_i (d_i - 1) candidate pairs of
 // the level's G'); foff[total_rows] is the total. Sets *skip when the total exceeds the capacity
 // (the level then runs without a probe) or when the level has no work.
-__global__ __launch_bounds__(1024) void k_feat_plan(Batch b, long long *foff, long long cap, int *skip) {
+// per_node = 0: d(d - 1) rows per node (edge features); 1: d rows (candidate features of a node).
+__global__ __launch_bounds__(1024) void k_feat_plan(Batch b, long long *foff, long long cap, int *skip, int per_node) {
     __shared__ long long part[1024 / 64];
     const int tid = threadIdx.x;
     if (b.st->done) {
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(1024) void k_feat_plan(Batch b, long long *foff, lo
     auto cnt = [&](long long k) -> long long {
         const int d = find_base(b.row_base, b.count, k);
         const long long dg = b.probs[d].deg[k - b.row_base[d]];
-        return dg * (dg - 1);
+        return per_node ? dg : dg * (dg - 1);
     };
     long long s = 0;
     for (long long k = lo; k < hi; ++k) s += cnt(k);
@@ -367,127 +368,8 @@ __global__ __launch_bounds__(256) void k_features(Batch b, int level, const long
     }
 }
 
-// ---------------------------------------------------------------------------------------------
-// Probe: per directed edge, the subsets of its top-Q candidates
-// ---------------------------------------------------------------------------------------------
-constexpr int kTopMax = 8;
-
-struct SmallBinom {
-    __device__ unsigned long long operator()(int a, int b) const {
-        if (b < 0 || a < b) return 0ull;
-        unsigned long long c = 1;
-        for (int k = 0; k < b; ++k) c = c * (unsigned long long)(a - k) / (unsigned long long)(k + 1);
-        return c;
-    }
-};
-
-// One work-group per flattened row i; wave w takes the edges (i, N_i[p]) with p = w (mod 4).
-template <typename T, int L>
-__global__ __launch_bounds__(256) void k_probe(Batch b, const long long *foff, const float *scores,
-                                               int topq, const int *skip) {
-    __shared__ long long s_tests, s_removed;
-    if (*skip) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) { s_tests = 0; s_removed = 0; }
-    __syncthreads();
-    const long long grow = blockIdx.x;
-    const int pd = find_base(b.row_base, b.count, grow);
-    const Prob &P = b.probs[pd];
-    const int64_t n = P.n, W = P.W;
-    const int row = (int)(grow - b.row_base[pd]);
-    const int d = P.deg[row];
-    long long my_tests = 0, my_removed = 0;
-    if (d >= L + 1 && L <= P.max_level && P.tau[L] == P.tau[L]) {
-        const T *C = static_cast<const T *>(P.C);
-        const int *nb = P.nbr + (int64_t)row * n;
-        unsigned long long *adj_row = P.adj + (int64_t)row * W;
-        auto CS = [&](int p, int q) -> T { return p == q ? (T)1 : C[(int64_t)nb[p] * n + nb[q]]; };
-        auto CI = [&](int p) -> T { return C[(int64_t)row * n + nb[p]]; };
-        const double tau = P.tau[L];
-        const float tl = P.t[L], band = P.band[L];
-        const int Q = d - 1 <= 64 * 64 ? min(min(topq, kTopMax), d - 1) : 0;  // 64-bit taken mask
-        const unsigned long long nsub = SmallBinom()(Q, L);
-        for (int p = wave; p < d; p += 4) {
-            const int j = nb[p];
-            if (!((live_word(adj_row + (j >> 6)) >> (j & 63)) & 1ull)) continue;
-            // Top-Q candidates by score (ties: lower position first), by Q rounds of wave argmax.
-            const float *sc = scores + foff[grow] + (long long)p * (d - 1);
-            unsigned long long taken = 0ull;  // this lane's entries qq = lane + 64 t already chosen
-            int top[kTopMax];
-#pragma unroll
-            for (int u = 0; u < kTopMax; ++u) {
-                top[u] = -1;
-                if (u >= Q) continue;
-                float best = -INFINITY;
-                int bi = 0x7fffffff;
-                for (int t = 0; lane + 64 * t < d - 1; ++t) {
-                    if ((taken >> t) & 1ull) continue;
-                    const float v = sc[lane + 64 * t];
-                    if (v > best) { best = v; bi = lane + 64 * t; }
-                }
-                for (int o = 32; o >= 1; o >>= 1) {
-                    const float ob = __shfl_xor(best, o, 64);
-                    const int oi = __shfl_xor(bi, o, 64);
-                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-                }
-                if (bi != 0x7fffffff && (bi & 63) == lane) taken |= 1ull << (bi >> 6);
-                top[u] = bi == 0x7fffffff ? -1 : (bi < p ? bi : bi + 1);   // candidate position
-            }
-            // Ascending positions, so every S is in lexicographic (id) order.
-#pragma unroll
-            for (int u = 1; u < kTopMax; ++u)
-#pragma unroll
-                for (int v = u; v > 0; --v)
-                    if (top[v - 1] > top[v] && top[v] >= 0) { const int t = top[v]; top[v] = top[v - 1]; top[v - 1] = t; }
-            for (unsigned long long t0 = 0; t0 < nsub; t0 += 64) {
-                const unsigned long long t = t0 + lane;
-                if (t >= nsub) continue;
-                int idx[L];
-                comb_unrank<L>(Q, t, idx, SmallBinom());
-                int P_[L];
-#pragma unroll
-                for (int c = 0; c < L; ++c) {
-                    int v = -1;
-#pragma unroll
-                    for (int u = 0; u < kTopMax; ++u) v = idx[c] == u ? top[u] : v;
-                    P_[c] = v;
-                }
-                bool valid = true;
-#pragma unroll
-                for (int c = 0; c < L; ++c) valid = valid && P_[c] >= 0;
-                if (!valid) continue;
-                if (!((live_word(adj_row + (j >> 6)) >> (j & 63)) & 1ull)) continue;
-                SetFactor<T, L> f;
-                f.build(P_, CS, CI);
-                int sid[L];
-#pragma unroll
-                for (int c = 0; c < L; ++c) sid[c] = nb[P_[c]];
-                ++my_tests;
-                const int dec = f.test(P_, p, CS, CI, tau, tl, band);
-                if (dec == 2) {
-                    push_recheck<L>(b, pd, row, j, sid, 2);
-                } else if (dec == 1) {
-                    const int lo = row < j ? row : j, hi = row < j ? j : row;
-                    if (take_edge(P.adj, W, lo, hi)) {
-                        ++my_removed;
-                        write_record(P, lo, hi, L, sid);
-                    }
-                }
-            }
-        }
-    }
-    if (my_tests) add_ll(&s_tests, my_tests);
-    if (my_removed) add_ll(&s_removed, my_removed);
-    __syncthreads();
-    if (tid == 0) {
-        Prob &Pw = b.probs[pd];
-        if (s_tests) { add_ll(&Pw.tests[L], s_tests); add_ll(&Pw.probe_tests[L], s_tests); }
-        if (s_removed) { add_ll(&Pw.removed[L], s_removed); add_ll(&Pw.probe_removed[L], s_removed); }
-    }
-}
-
 hipError_t launch_feat_plan(hipStream_t s, const Batch &b, long long *foff, long long cap, int *skip) {
-    hipLaunchKernelGGL(k_feat_plan, dim3(1), dim3(1024), 0, s, b, foff, cap, skip);
+    hipLaunchKernelGGL(k_feat_plan, dim3(1), dim3(1024), 0, s, b, foff, cap, skip, 0);
     return hipGetLastError();
 }
 
@@ -502,30 +384,780 @@ hipError_t launch_features(hipStream_t s, const Batch &b, int level, const long 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------------
+// Probe: per directed edge, the subsets of its top-Q candidates, scored by the MLP in one kernel
+// ---------------------------------------------------------------------------------------------
+constexpr int kTopMax = 8;
+constexpr int kProbeRowCap = 24;   // rows with more neighbours skip the probe (row block in LDS)
+constexpr int kProbeThreads = 256;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// C(a, b) for a, b <= kTopMax (subsets of the top candidates).
+struct TopBinom {
+    __device__ unsigned long long operator()(int a, int b) const {
+        if (b < 0 || a < b) return 0ull;
+        unsigned long long c = 1;
+#pragma unroll
+        for (int k = 0; k < kTopMax; ++k)
+            if (k < b) c = c * (unsigned long long)(a - k);
+        unsigned long long f = 1;
+#pragma unroll
+        for (int k = 2; k <= kTopMax; ++k)
+            if (k <= b) f *= (unsigned long long)k;
+        return c / f;
+    }
+};
+
+// Orders the LDS accesses of the lanes of one wavefront around a cooperative step.
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Round-to-nearest-even BF16 bits of a finite float.
+__device__ inline uint16_t bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+constexpr int kProbeStage = 256;   // independent probe tests of a row settled together
+
+template <typename T>
+struct __align__(16) ProbeSmem {
+    uint16_t W1[kHid][8];              // layer-1 weights as the B operand rows ([out][in]), BF16
+    uint16_t W2[kHid][kHid + 8];       // layer-2 weights ([out][in]), BF16, rows padded to 144 B
+    uint16_t X[4][64][8];              // per wavefront: features of its 64 candidate rows
+    uint16_t H1[4][16][kHid + 8];      // per wavefront: layer-1 activations of one 16-row tile
+    float b1[kHid], b2[kHid], W3[kHid];
+    float b3;
+    float sc[kProbeRowCap * (kProbeRowCap - 1)];   // MLP score of every (p, q != p) of the row
+    T blk[kProbeRowCap][kProbeRowCap + 1];         // C[N_i, N_i]
+    T ci[kProbeRowCap];                            // C[i, N_i]
+    int nb[kProbeRowCap];
+    float dg[kProbeRowCap];
+    int live[kProbeRowCap];                        // edge (i, N_i[p]) still in G at the test phase
+    unsigned char top[kProbeRowCap][kTopMax];      // best candidate positions of each edge, by rank
+    int stage[kProbeStage];                        // (p, subset) of the independent tests
+    int nstage, nwin;
+    unsigned long long rec_base;
+    long long tests, removed;
+};
+
+// One work-group per row i of G' (grid-stride, persistent), for rows with L + 1 <= d_i <= 48
+// (the row's block C[N_i, N_i], C[i, N_i] and all scores are staged in LDS):
+//  1. the MLP scores every candidate k = N_i[q] of every directed edge (i, N_i[p]), q != p: each
+//     wavefront takes 64 candidate rows at a time, computes their features in FP32, and runs the
+//     8 -> 64 -> 64 -> 1 network on v_mfma_f32_16x16x32_bf16 in 16-row tiles (layer 1 with K
+//     padded to 32, layer 2 in two K-steps; BF16 weights and activations, FP32 accumulation), the
+//     last layer as a reduction over the 16 lanes that hold a candidate's hidden units;
+//  2. every candidate row counts the candidates of its edge that score higher (ties: lower
+//     position first); those with rank < Q = min(top, d_i - 1) are the edge's top candidates;
+//  3. the threads share the (live edge, subset of its top-Q) pairs and test them with the FP32
+//     test of the level kernel (same band, same re-check queue); the independent ones are staged
+//     and settled together: the atomic AND on the edge bit picks one winner per edge, and the
+//     winners take consecutive SepSet slots with one atomic add.
+template <typename T, int L>
+__global__ __launch_bounds__(kProbeThreads) void k_probe(Batch b, const float *params, int topq) {
+    __shared__ ProbeSmem<T> sm;
+    if (b.st->done) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // Parameters: BF16 weights, FP32 biases.
+    for (int e = tid; e < kHid * kIn; e += kProbeThreads) sm.W1[e / kIn][e % kIn] = bf16_rne(params[oW1 + e]);
+    for (int e = tid; e < kHid * kHid; e += kProbeThreads) sm.W2[e / kHid][e % kHid] = bf16_rne(params[oW2 + e]);
+    if (tid < kHid) {
+        sm.b1[tid] = params[oB1 + tid];
+        sm.b2[tid] = params[oB2 + tid];
+        sm.W3[tid] = params[oW3 + tid];
+    }
+    if (tid == 0) {
+        sm.b3 = params[oB3];
+        sm.tests = 0;
+        sm.removed = 0;
+        sm.nstage = 0;
+        sm.nwin = 0;
+    }
+    int stats_pd = -1;
+    for (long long grow = blockIdx.x; grow < b.total_rows; grow += gridDim.x) {
+        const int pd = find_base(b.row_base, b.count, grow);
+        Prob &P = b.probs[pd];
+        const int row = (int)(grow - b.row_base[pd]);
+        const int d = P.deg[row];
+        if (d < L + 1 || d > kProbeRowCap || !(L <= P.max_level && P.tau[L] == P.tau[L])) continue;
+        __syncthreads();   // the previous row's LDS contents and statistics are no longer read
+        if (tid == 0 && pd != stats_pd) {
+            if (stats_pd >= 0) {
+                Prob &Ps = b.probs[stats_pd];
+                if (sm.tests) { add_ll(&Ps.tests[L], sm.tests); add_ll(&Ps.probe_tests[L], sm.tests); }
+                if (sm.removed) { add_ll(&Ps.removed[L], sm.removed); add_ll(&Ps.probe_removed[L], sm.removed); }
+            }
+            sm.tests = 0;
+            sm.removed = 0;
+        }
+        stats_pd = pd;
+        const int64_t n = P.n, W = P.W;
+        const T *C = static_cast<const T *>(P.C);
+        const int *nbg = P.nbr + (int64_t)row * n;
+        if (tid < d) {
+            const int k = nbg[tid];
+            sm.nb[tid] = k;
+            sm.dg[tid] = (float)P.deg[k] / 64.0f;
+            sm.ci[tid] = C[(int64_t)row * n + k];
+        }
+        __syncthreads();
+        // The row's block C[N_i, N_i], every gather issued before any store.
+        {
+            constexpr int kPer = (kProbeRowCap * kProbeRowCap + kProbeThreads - 1) / kProbeThreads;
+            T v[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int e = tid + u * kProbeThreads;
+                v[u] = (T)0;
+                if (e < d * d) v[u] = C[(int64_t)sm.nb[e / d] * n + sm.nb[e % d]];
+            }
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int e = tid + u * kProbeThreads;
+                if (e < d * d) sm.blk[e / d][e % d] = v[u];
+            }
+        }
+        __syncthreads();
+        const float di = (float)d / 64.0f, lv = (float)L / 8.0f;
+        const int ncand = d - 1, nrows = d * ncand;
+        // 1. Scores: 64 candidate rows per wavefront pass.
+        for (int b0 = 64 * wave; b0 < nrows; b0 += 256) {
+            {
+                const int r = b0 + lane;
+                float x[kIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                if (r < nrows) {
+                    const int p = r / ncand, qq = r - p * ncand, q = qq < p ? qq : qq + 1;
+                    const float cij = (float)sm.ci[p], cik = (float)sm.ci[q], cjk = (float)sm.blk[p][q];
+                    const float den = (1.0f - cik * cik) * (1.0f - cjk * cjk);
+                    const float rho = den > 0.0f ? (cij - cik * cjk) * rsqrtf(den) : 0.0f;
+                    x[0] = fabsf(cij);
+                    x[1] = fabsf(cik);
+                    x[2] = fabsf(cjk);
+                    x[3] = fminf(fabsf(rho), 1.0f);
+                    x[4] = di;
+                    x[5] = sm.dg[p];
+                    x[6] = sm.dg[q];
+                    x[7] = lv;
+                }
+#pragma unroll
+                for (int u = 0; u < kIn; ++u) sm.X[wave][lane][u] = bf16_rne(x[u]);
+            }
+            wave_sync_lds();
+            const bf16x8 zero8 = {};
+            const int tiles = (nrows - b0 + 15) / 16 < 4 ? (nrows - b0 + 15) / 16 : 4;
+            for (int mt = 0; mt < tiles; ++mt) {
+                // Layer 1: H1 = relu(X W1^T + b1); only lanes 0-15 carry K (the 8 features).
+                const bf16x8 ax = lane < 16 ? *reinterpret_cast<const bf16x8 *>(&sm.X[wave][16 * mt + lane][0]) : zero8;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const bf16x8 bw = lane < 16 ? *reinterpret_cast<const bf16x8 *>(&sm.W1[16 * nt + lane][0]) : zero8;
+                    const floatx4 z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, bw, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                    const int col = 16 * nt + (lane & 15);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float h = z[v] + sm.b1[col];
+                        sm.H1[wave][4 * (lane >> 4) + v][col] = bf16_rne(h > 0.0f ? h : 0.0f);
+                    }
+                }
+                wave_sync_lds();
+                // Layer 2: H2 = relu(H1 W2^T + b2), K = 64 in two steps of 32.
+                floatx4 acc[4];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(&sm.H1[wave][lane & 15][32 * ks + 8 * (lane >> 4)]);
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const bf16x8 bw =
+                            *reinterpret_cast<const bf16x8 *>(&sm.W2[16 * nt + (lane & 15)][32 * ks + 8 * (lane >> 4)]);
+                        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bw, acc[nt], 0, 0, 0);
+                    }
+                }
+                wave_sync_lds();   // H1 of this tile is read; the next tile may overwrite it
+                // Layer 3: score = W3 . H2 + b3; lane l holds rows 4 (l / 16) + v, column l % 16 of
+                // each 16-column block, so the 16 lanes of a row group reduce together.
+                float part[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float sacc = 0.0f;
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int col = 16 * nt + (lane & 15);
+                        const float h = acc[nt][v] + sm.b2[col];
+                        sacc += (h > 0.0f ? h : 0.0f) * sm.W3[col];
+                    }
+                    part[v] = sacc;
+                }
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) part[v] += __shfl_xor(part[v], o, 64);
+                if ((lane & 15) == 0)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = b0 + 16 * mt + 4 * (lane >> 4) + v;
+                        if (r < nrows) sm.sc[r] = part[v] + sm.b3;
+                    }
+            }
+        }
+        // Live bits of the row's edges, read once the scores are done (removals made meanwhile by
+        // other work-groups are seen).
+        if (tid < d) {
+            const int j = sm.nb[tid];
+            sm.live[tid] = (int)((live_word(P.adj + (int64_t)row * W + (j >> 6)) >> (j & 63)) & 1ull);
+        }
+        __syncthreads();
+        // 2. Rank of every candidate row within its edge; the top Q are kept.
+        const int Q = topq < ncand ? topq : ncand;
+        for (int r = tid; r < nrows; r += kProbeThreads) {
+            const int p = r / ncand, qq = r - p * ncand;
+            const float s0 = sm.sc[r];
+            const float *seg = sm.sc + p * ncand;
+            int rank = 0;
+            for (int u = 0; u < ncand; ++u) {
+                const float su = seg[u];
+                rank += (su > s0 || (su == s0 && u < qq)) ? 1 : 0;
+            }
+            if (rank < Q) sm.top[p][rank] = (unsigned char)(qq < p ? qq : qq + 1);
+        }
+        __syncthreads();
+        // 3. The C(Q, L) subsets of the top candidates of every live edge.
+        const double tau = P.tau[L];
+        const float tl = P.t[L], band = P.band[L];
+        const int nsub = (int)TopBinom()(Q, L);
+        auto CS = [&](int a, int c) -> T { return a == c ? (T)1 : sm.blk[a][c]; };
+        auto CI = [&](int a) -> T { return sm.ci[a]; };
+        // Positions of subset s of edge p, in ascending order (so S is in id order).
+        auto subset = [&](int p, int s, int (&P_)[L]) {
+            int idx[L];
+            comb_unrank<L>(Q, (unsigned long long)s, idx, TopBinom());
+#pragma unroll
+            for (int c = 0; c < L; ++c) P_[c] = sm.top[p][idx[c]];
+#pragma unroll
+            for (int u = 1; u < L; ++u)
+#pragma unroll
+                for (int v = u; v > 0; --v)
+                    if (P_[v - 1] > P_[v]) { const int t = P_[v]; P_[v] = P_[v - 1]; P_[v - 1] = t; }
+        };
+        long long my_tests = 0;
+        for (int e = tid; e < d * nsub; e += kProbeThreads) {
+            const int p = e / nsub, si = e - p * nsub;
+            if (!sm.live[p]) continue;
+            int P_[L];
+            subset(p, si, P_);
+            SetFactor<T, L> f;
+            f.build(P_, CS, CI);
+            ++my_tests;
+            const int dec = f.test(P_, p, CS, CI, tau, tl, band);
+            if (dec == 2) {
+                int sid[L];
+#pragma unroll
+                for (int c = 0; c < L; ++c) sid[c] = sm.nb[P_[c]];
+                push_recheck<L>(b, pd, row, sm.nb[p], sid, 2);
+            } else if (dec == 1) {
+                const int slot = atomicAdd(&sm.nstage, 1);
+                if (slot < kProbeStage) {
+                    sm.stage[slot] = e;
+                } else {
+                    const int j = sm.nb[p], lo = row < j ? row : j, hi = row < j ? j : row;
+                    int sid[L];
+#pragma unroll
+                    for (int c = 0; c < L; ++c) sid[c] = sm.nb[P_[c]];
+                    if (take_edge(P.adj, W, lo, hi)) {
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&sm.removed), 1ull);
+                        write_record(P, lo, hi, L, sid);
+                    }
+                }
+            }
+        }
+        if (my_tests) atomicAdd(reinterpret_cast<unsigned long long *>(&sm.tests), (unsigned long long)my_tests);
+        __syncthreads();
+        // Settle the staged independent tests: one winner per edge, consecutive SepSet slots.
+        const int nst = sm.nstage < kProbeStage ? sm.nstage : kProbeStage;
+        if (nst > 0) {
+            int myslot = -1, e = 0;
+            if (tid < nst) {
+                e = sm.stage[tid];
+                const int j = sm.nb[e / nsub], lo = row < j ? row : j, hi = row < j ? j : row;
+                if (take_edge(P.adj, W, lo, hi)) myslot = atomicAdd(&sm.nwin, 1);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const int nw = sm.nwin;
+                sm.rec_base = nw ? atomicAdd(reinterpret_cast<unsigned long long *>(P.rec_count), (unsigned long long)nw)
+                                 : 0ull;
+                sm.removed += nw;
+            }
+            __syncthreads();
+            if (myslot >= 0) {
+                const long long k = (long long)(sm.rec_base + (unsigned long long)myslot);
+                if (k < P.rec_cap) {
+                    const int p = e / nsub, j = sm.nb[p];
+                    int P_[L], sid[L];
+                    subset(p, e - p * nsub, P_);
+#pragma unroll
+                    for (int c = 0; c < L; ++c) sid[c] = sm.nb[P_[c]];
+                    store_record(P.recs + k, row < j ? row : j, row < j ? j : row, L, sid);
+                }
+            }
+            if (tid == 0) {
+                sm.nstage = 0;
+                sm.nwin = 0;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && stats_pd >= 0) {
+        Prob &Ps = b.probs[stats_pd];
+        if (sm.tests) { add_ll(&Ps.tests[L], sm.tests); add_ll(&Ps.probe_tests[L], sm.tests); }
+        if (sm.removed) { add_ll(&Ps.removed[L], sm.removed); add_ll(&Ps.probe_removed[L], sm.removed); }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Row order: the MLP ranks the candidates k of every node i (the shared-set form of the ordering)
+// ---------------------------------------------------------------------------------------------
+// A conditioning set of the level kernel serves every edge of its row (the set sharing of cuPC-S,
+// Sec. 3.4), so the unit the model ranks here is the candidate k of node i. Its features, all
+// from quantities the method computes (C and G' at the start of the level):
+//   |C_ik|, |C_ik| / max_q |C_iq|, |N_i & N_k| / d_i, |N_i & N_k| / d_k, d_i / 256, d_k / 256,
+//   level / 8, the mean of |C_ij| over the row.
+constexpr int kRowCap = 1024;     // rows up to this degree are ranked (neighbour list in LDS)
+constexpr int kRowWords = 256;    // adjacency words of a row staged in LDS (n <= 16384)
+constexpr int kRowTopMax = 16;
+
+template <typename T>
+struct __align__(16) RowSmem {
+    uint16_t W1[kHid][8];
+    uint16_t W2[kHid][kHid + 8];
+    uint16_t X[4][64][8];
+    uint16_t H1[4][16][kHid + 8];
+    int nb[kRowCap];
+    float ac[kRowCap];     // |C_ik| (entries past d hold -1, so rank counts can read in fours)
+    float sc[kRowCap];     // MLP score (entries past d hold -inf)
+    T ci[kRowCap];         // C_ik
+    unsigned long long arow[kRowWords];
+    float b1[kHid], b2[kHid], W3[kHid];
+    int toppos[kRowTopMax];
+    int stage[kProbeStage];    // (top index, position) of the independent tests of the row
+    int nstage, nwin;
+    unsigned long long rec_base;
+    long long tests, removed;
+    float red[4], redmax[4];
+    float b3;
+    int taken[kRowCap];    // candidate already among the top (argmax rounds)
+    float bestv[4];
+    int besti[4];
+};
+
+// Loads the MLP parameters into LDS (BF16 weights, FP32 biases).
+template <class Smem>
+__device__ inline void load_mlp_bf16(Smem &sm, const float *params, int tid, int nthreads) {
+    for (int e = tid; e < kHid * kIn; e += nthreads) sm.W1[e / kIn][e % kIn] = bf16_rne(params[oW1 + e]);
+    for (int e = tid; e < kHid * kHid; e += nthreads) sm.W2[e / kHid][e % kHid] = bf16_rne(params[oW2 + e]);
+    if (tid < kHid) {
+        sm.b1[tid] = params[oB1 + tid];
+        sm.b2[tid] = params[oB2 + tid];
+        sm.W3[tid] = params[oW3 + tid];
+    }
+    if (tid == 0) sm.b3 = params[oB3];
+}
+
+// Scores the 64 feature rows in sm.X[wave] (BF16) with the MLP; writes rows r < nrows of them to
+// out[r - r0] for r = r0 .. r0 + 63 (one wavefront).
+template <class Smem>
+__device__ inline void mlp_score64(Smem &sm, int wave, int lane, int r0, int nrows, float *out) {
+    const bf16x8 zero8 = {};
+    const int tiles = (nrows - r0 + 15) / 16 < 4 ? (nrows - r0 + 15) / 16 : 4;
+    for (int mt = 0; mt < tiles; ++mt) {
+        const bf16x8 ax = lane < 16 ? *reinterpret_cast<const bf16x8 *>(&sm.X[wave][16 * mt + lane][0]) : zero8;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const bf16x8 bw = lane < 16 ? *reinterpret_cast<const bf16x8 *>(&sm.W1[16 * nt + lane][0]) : zero8;
+            const floatx4 z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, bw, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            const int col = 16 * nt + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float h = z[v] + sm.b1[col];
+                sm.H1[wave][4 * (lane >> 4) + v][col] = bf16_rne(h > 0.0f ? h : 0.0f);
+            }
+        }
+        wave_sync_lds();
+        floatx4 acc[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(&sm.H1[wave][lane & 15][32 * ks + 8 * (lane >> 4)]);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(&sm.W2[16 * nt + (lane & 15)][32 * ks + 8 * (lane >> 4)]);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bw, acc[nt], 0, 0, 0);
+            }
+        }
+        wave_sync_lds();
+        float part[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float sacc = 0.0f;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int col = 16 * nt + (lane & 15);
+                const float h = acc[nt][v] + sm.b2[col];
+                sacc += (h > 0.0f ? h : 0.0f) * sm.W3[col];
+            }
+            part[v] = sacc;
+        }
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) part[v] += __shfl_xor(part[v], o, 64);
+        if ((lane & 15) == 0)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = r0 + 16 * mt + 4 * (lane >> 4) + v;
+                if (r < nrows) out[r - r0] = part[v] + sm.b3;
+            }
+    }
+}
+
+// Stages row i (neighbours, |C_ik|, its adjacency words) and returns the row mean of |C_ik|.
+template <typename T, class Smem>
+__device__ inline float stage_row(Smem &sm, const Prob &P, int row, int d, int tid, int nthreads, float &rowmax) {
+    const int64_t n = P.n, W = P.W;
+    const T *C = static_cast<const T *>(P.C);
+    float s = 0.0f;
+    for (int p = tid; p < d; p += nthreads) {
+        const int k = P.nbr[(int64_t)row * n + p];
+        sm.nb[p] = k;
+        const T c = C[(int64_t)row * n + k];
+        sm.ci[p] = c;
+        const float a = fabsf((float)c);
+        sm.ac[p] = a;
+        s += a;
+    }
+    for (int p = d + tid; p < ((d + 3) & ~3); p += nthreads) sm.ac[p] = -1.0f;
+    for (int w = tid; w < W && w < kRowWords; w += nthreads) sm.arow[w] = P.adj[(int64_t)row * W + w];
+    float mx = 0.0f;
+    for (int p = tid; p < d; p += nthreads) mx = fmaxf(mx, sm.ac[p]);
+    for (int o = 32; o >= 1; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    }
+    if ((tid & 63) == 0) {
+        sm.red[tid >> 6] = s;
+        sm.redmax[tid >> 6] = mx;
+    }
+    __syncthreads();
+    rowmax = fmaxf(fmaxf(sm.redmax[0], sm.redmax[1]), fmaxf(sm.redmax[2], sm.redmax[3]));
+    return ((sm.red[0] + sm.red[1]) + (sm.red[2] + sm.red[3])) / (float)d;
+}
+
+// Features of candidate position p of the staged row (see above).
+template <class Smem>
+__device__ inline void row_features(const Smem &sm, const Prob &P, int d, int p, int level, float rowmean,
+                                    float rowmax, float (&x)[kIn]) {
+    const int64_t W = P.W;
+    const float a = sm.ac[p];
+    const int k = sm.nb[p];
+    // G is not written while the order is computed (before the level's tests), so plain loads.
+    const unsigned long long *ak = P.adj + (int64_t)k * W;
+    int cn = 0;   // |N_i & N_k| (the caller guarantees W <= kRowWords)
+#pragma unroll 8
+    for (int64_t w = 0; w < W; ++w) cn += __popcll(sm.arow[w] & ak[w]);
+    const float dk = (float)P.deg[k];
+    x[0] = a;
+    x[1] = rowmax > 0.0f ? a / rowmax : 0.0f;
+    x[2] = (float)cn / (float)d;
+    x[3] = dk > 0.0f ? (float)cn / dk : 0.0f;
+    x[4] = (float)d / 256.0f;
+    x[5] = dk / 256.0f;
+    x[6] = (float)level / 8.0f;
+    x[7] = rowmean;
+}
+
+// One work-group per row of G' at level 1 (grid-stride), the first part of the level with the
+// shared-set order:
+//  1. rows with 2 <= d <= kRowCap (and n <= 64 kRowWords): the MLP scores every candidate k of the
+//     row (features staged in LDS), and the row's neighbour list is rewritten with the `top`
+//     best-scored candidates first (best first; the others keep their ascending order);
+//  2. every row with d >= 2: the sets {k} of its first `top` positions (the best-scored, or simply
+//     the first for rows too long to score) are tested against every live edge (i, j) of the row
+//     with the level's FP32 test (same band and re-check queue). Independent tests are staged and
+//     settled together (one winner per edge, one SepSet slot reservation per row).
+// The rest of the level then runs over the ranks top .. d - 1 of the rewritten lists.
+template <typename T>
+__global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const float *params, int top) {
+    __shared__ RowSmem<T> sm;
+    if (b.st->done) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    load_mlp_bf16(sm, params, tid, 256);
+    if (tid == 0) {
+        sm.tests = 0;
+        sm.removed = 0;
+        sm.nstage = 0;
+        sm.nwin = 0;
+    }
+    int stats_pd = -1;
+    for (long long grow = blockIdx.x; grow < b.total_rows; grow += gridDim.x) {
+        const int pd = find_base(b.row_base, b.count, grow);
+        Prob &P = b.probs[pd];
+        const int row = (int)(grow - b.row_base[pd]);
+        const int d = P.deg[row];
+        if (d < 2 || !(level <= P.max_level && P.tau[level] == P.tau[level])) continue;
+        __syncthreads();   // the previous row's LDS contents and statistics are no longer read
+        if (tid == 0 && pd != stats_pd) {
+            if (stats_pd >= 0) {
+                Prob &Ps = b.probs[stats_pd];
+                if (sm.tests) { add_ll(&Ps.tests[level], sm.tests); add_ll(&Ps.probe_tests[level], sm.tests); }
+                if (sm.removed) {
+                    add_ll(&Ps.removed[level], sm.removed);
+                    add_ll(&Ps.probe_removed[level], sm.removed);
+                }
+            }
+            sm.tests = 0;
+            sm.removed = 0;
+        }
+        stats_pd = pd;
+        const int64_t n = P.n, W = P.W;
+        const T *C = static_cast<const T *>(P.C);
+        int *nbr = P.nbr + (int64_t)row * n;
+        const bool scored = d <= kRowCap && W <= kRowWords;
+        const int T_ = top < d ? top : d;
+        if (scored) {
+            float rowmax = 0.0f;
+            const float rowmean = stage_row<T>(sm, P, row, d, tid, 256, rowmax);
+            for (int r0 = 64 * wave; r0 < d; r0 += 256) {
+                float x[kIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                if (r0 + lane < d) row_features(sm, P, d, r0 + lane, level, rowmean, rowmax, x);
+#pragma unroll
+                for (int u = 0; u < kIn; ++u) sm.X[wave][lane][u] = bf16_rne(x[u]);
+                wave_sync_lds();
+                mlp_score64(sm, wave, lane, r0, d, sm.sc + r0);
+                wave_sync_lds();
+            }
+            for (int p = d + tid; p < ((d + 3) & ~3); p += 256) sm.sc[p] = -INFINITY;
+            __syncthreads();
+            // The top T_ by score: T_ rounds of a work-group argmax (ties: lower position first).
+            for (int p = tid; p < d; p += 256) sm.taken[p] = 0;
+            __syncthreads();
+            for (int u = 0; u < T_; ++u) {
+                float bv = -INFINITY;
+                int bi = 0x7fffffff;
+                for (int p = tid; p < d; p += 256)
+                    if (!sm.taken[p] && (sm.sc[p] > bv || (sm.sc[p] == bv && p < bi))) {
+                        bv = sm.sc[p];
+                        bi = p;
+                    }
+                for (int o = 32; o >= 1; o >>= 1) {
+                    const float ov = __shfl_xor(bv, o, 64);
+                    const int oi = __shfl_xor(bi, o, 64);
+                    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+                }
+                if (lane == 0) {
+                    sm.bestv[wave] = bv;
+                    sm.besti[wave] = bi;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    float v = sm.bestv[0];
+                    int i = sm.besti[0];
+                    for (int w = 1; w < 4; ++w)
+                        if (sm.bestv[w] > v || (sm.bestv[w] == v && sm.besti[w] < i)) { v = sm.bestv[w]; i = sm.besti[w]; }
+                    sm.toppos[u] = i;
+                    sm.taken[i] = 1;
+                }
+                __syncthreads();
+            }
+            // New order: the top candidates by rank, then the others in their (ascending) order.
+            for (int p = tid; p < d; p += 256) {
+                int pos = -1, below = 0;
+                for (int u = 0; u < T_; ++u) {
+                    const int tp = sm.toppos[u];
+                    if (tp == p) pos = u;
+                    below += tp < p ? 1 : 0;
+                }
+                nbr[pos >= 0 ? pos : T_ + p - below] = sm.nb[p];
+            }
+        } else if (tid < T_) {
+            sm.toppos[tid] = tid;   // too long to score: the first positions, order unchanged
+        }
+        __syncthreads();
+        // 2. The sets {k} of the top candidates against every live edge of the row.
+        auto NB = [&](int q) -> int { return scored ? sm.nb[q] : nbr[q]; };
+        auto CIv = [&](int q) -> T { return scored ? sm.ci[q] : C[(int64_t)row * n + nbr[q]]; };
+        auto LIVE = [&](int j) -> bool {
+            const unsigned long long wv = scored ? sm.arow[j >> 6] : live_word(P.adj + (int64_t)row * W + (j >> 6));
+            return (wv >> (j & 63)) & 1ull;
+        };
+        const double tau = P.tau[level];
+        const float tl = P.t[level], band = P.band[level];
+        long long my_tests = 0;
+        for (int e = tid; e < T_ * d; e += 256) {
+            const int u = e / d, q = e - u * d, kp = sm.toppos[u];
+            if (q == kp) continue;
+            const int j = NB(q);
+            if (!LIVE(j)) continue;
+            const int k = NB(kp);
+            const int P1[1] = {kp};
+            auto CS1 = [&](int a, int c) -> T { return (T)1; };   // only the diagonal of M2 = [1]
+            auto CI1 = [&](int a) -> T { return CIv(a); };
+            SetFactor<T, 1> f;
+            f.build(P1, CS1, CI1);
+            const T col[1] = {C[(int64_t)j * n + k]};
+            ++my_tests;
+            const int dec = f.test_vals(col, CIv(q), tau, tl, band);
+            if (dec == 2) {
+                const int sid[1] = {k};
+                push_recheck<1>(b, pd, row, j, sid, 2);
+            } else if (dec == 1) {
+                const int slot = atomicAdd(&sm.nstage, 1);
+                if (slot < kProbeStage) {
+                    sm.stage[slot] = e;
+                } else {
+                    const int lo = row < j ? row : j, hi = row < j ? j : row;
+                    const int sid[1] = {k};
+                    if (take_edge(P.adj, W, lo, hi)) {
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&sm.removed), 1ull);
+                        write_record(P, lo, hi, 1, sid);
+                    }
+                }
+            }
+        }
+        if (my_tests) atomicAdd(reinterpret_cast<unsigned long long *>(&sm.tests), (unsigned long long)my_tests);
+        __syncthreads();
+        // Settle the staged independent tests: one winner per edge, consecutive SepSet slots.
+        const int nst = sm.nstage < kProbeStage ? sm.nstage : kProbeStage;
+        if (nst > 0) {
+            int myslot = -1, e = 0;
+            if (tid < nst) {
+                e = sm.stage[tid];
+                const int j = NB(e % d), lo = row < j ? row : j, hi = row < j ? j : row;
+                if (take_edge(P.adj, W, lo, hi)) myslot = atomicAdd(&sm.nwin, 1);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const int nw = sm.nwin;
+                sm.rec_base = nw ? atomicAdd(reinterpret_cast<unsigned long long *>(P.rec_count), (unsigned long long)nw)
+                                 : 0ull;
+                sm.removed += nw;
+            }
+            __syncthreads();
+            if (myslot >= 0) {
+                const long long kk = (long long)(sm.rec_base + (unsigned long long)myslot);
+                if (kk < P.rec_cap) {
+                    const int j = NB(e % d), sid[1] = {NB(sm.toppos[e / d])};
+                    store_record(P.recs + kk, row < j ? row : j, row < j ? j : row, 1, sid);
+                }
+            }
+            if (tid == 0) {
+                sm.nstage = 0;
+                sm.nwin = 0;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && stats_pd >= 0) {
+        Prob &Ps = b.probs[stats_pd];
+        if (sm.tests) { add_ll(&Ps.tests[level], sm.tests); add_ll(&Ps.probe_tests[level], sm.tests); }
+        if (sm.removed) { add_ll(&Ps.removed[level], sm.removed); add_ll(&Ps.probe_removed[level], sm.removed); }
+    }
+}
+
+// Training rows of the shared-set order at level 1: the features of every candidate k of every
+// node i, and label 1 when {k} separates at least one edge (i, j), j in N_i \ {k}, by the FP32 test
+// |rho_ij.k| <= tanh(tau_1) (Eq. 3-6 at l = 1, without the re-check band). meta gets (i, k).
+template <typename T>
+__global__ __launch_bounds__(256) void k_row_features(Batch b, int level, const long long *foff, float *feats,
+                                                      float *labels, int *meta, const int *skip) {
+    __shared__ RowSmem<T> sm;
+    if (*skip) return;
+    const int tid = threadIdx.x;
+    const long long grow = blockIdx.x;
+    const int pd = find_base(b.row_base, b.count, grow);
+    const Prob &P = b.probs[pd];
+    const int row = (int)(grow - b.row_base[pd]);
+    const int d = P.deg[row];
+    if (d < 1 || d > kRowCap || P.W > kRowWords) return;
+    float rowmax = 0.0f;
+    const float rowmean = stage_row<T>(sm, P, row, d, tid, 256, rowmax);
+    const int64_t n = P.n;
+    const T *C = static_cast<const T *>(P.C);
+    const float tl = (float)tanh(P.tau[1]);
+    const long long base = foff[grow];
+    for (int p = tid; p < d; p += 256) {
+        float x[kIn];
+        row_features(sm, P, d, p, level, rowmean, rowmax, x);
+        float *f = feats + (base + p) * kIn;
+#pragma unroll
+        for (int u = 0; u < kIn; ++u) f[u] = x[u];
+        const int k = sm.nb[p];
+        const float cik = (float)C[(int64_t)row * n + k];
+        bool sep = false;
+        for (int q = 0; q < d && !sep; ++q) {
+            if (q == p) continue;
+            const int j = sm.nb[q];
+            const float cij = (float)C[(int64_t)row * n + j], cjk = (float)C[(int64_t)j * n + k];
+            const float den = (1.0f - cik * cik) * (1.0f - cjk * cjk);
+            sep = den > 0.0f && fabsf(cij - cik * cjk) <= tl * sqrtf(den);
+        }
+        labels[base + p] = sep ? 1.0f : 0.0f;
+        if (meta) {
+            meta[(base + p) * 2 + 0] = row;
+            meta[(base + p) * 2 + 1] = k;
+        }
+    }
+}
+
+hipError_t launch_row_order(hipStream_t s, const Batch &b, int level, const float *params, int top, int grid) {
+    if (top < 1 || top > kRowTopMax) return hipErrorInvalidValue;
+    if (b.prec == PC_PREC_FP64)
+        hipLaunchKernelGGL(k_row_order<double>, dim3(grid), dim3(256), 0, s, b, level, params, top);
+    else
+        hipLaunchKernelGGL(k_row_order<float>, dim3(grid), dim3(256), 0, s, b, level, params, top);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_features(hipStream_t s, const Batch &b, int level, long long *foff, long long cap, int *skip,
+                               float *feats, float *labels, int *meta) {
+    hipLaunchKernelGGL(k_feat_plan, dim3(1), dim3(1024), 0, s, b, foff, cap, skip, 1);
+    if (b.prec == PC_PREC_FP64)
+        hipLaunchKernelGGL(k_row_features<double>, dim3((unsigned)b.total_rows), dim3(256), 0, s, b, level, foff, feats,
+                           labels, meta, skip);
+    else
+        hipLaunchKernelGGL(k_row_features<float>, dim3((unsigned)b.total_rows), dim3(256), 0, s, b, level, foff, feats,
+                           labels, meta, skip);
+    return hipGetLastError();
+}
+
 template <typename T, int L>
 struct ProbeDispatch {
-    static hipError_t run(hipStream_t s, const Batch &b, int level, const long long *foff, const float *sc,
-                          int topq, const int *skip) {
+    static hipError_t run(hipStream_t s, const Batch &b, int level, const float *params, int topq, int grid) {
         if (level == L) {
-            hipLaunchKernelGGL((k_probe<T, L>), dim3((unsigned)b.total_rows), dim3(256), 0, s, b, foff, sc, topq,
-                               skip);
+            // As many work-groups as fit at once (each keeps its row's block and scores in LDS).
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_probe<T, L>, kProbeThreads, 0) == hipSuccess &&
+                per_cu > 0)
+                grid = per_cu * grid;
+            hipLaunchKernelGGL((k_probe<T, L>), dim3(grid), dim3(kProbeThreads), 0, s, b, params, topq);
             return hipGetLastError();
         }
-        return ProbeDispatch<T, L + 1>::run(s, b, level, foff, sc, topq, skip);
+        return ProbeDispatch<T, L + 1>::run(s, b, level, params, topq, grid);
     }
 };
 template <typename T>
 struct ProbeDispatch<T, kTopMax + 1> {
-    static hipError_t run(hipStream_t, const Batch &, int, const long long *, const float *, int, const int *) {
-        return hipErrorInvalidValue;
-    }
+    static hipError_t run(hipStream_t, const Batch &, int, const float *, int, int) { return hipErrorInvalidValue; }
 };
 
-hipError_t launch_probe(hipStream_t s, const Batch &b, int level, const long long *foff, const float *scores,
-                        int topq, const int *skip) {
-    if (level < 1 || level > kTopMax) return hipErrorInvalidValue;
-    if (b.prec == PC_PREC_FP64) return ProbeDispatch<double, 1>::run(s, b, level, foff, scores, topq, skip);
-    return ProbeDispatch<float, 1>::run(s, b, level, foff, scores, topq, skip);
+hipError_t launch_probe(hipStream_t s, const Batch &b, int level, const float *params, int topq, int grid) {
+    if (level < 1 || level > kTopMax || topq < 1 || topq > kTopMax) return hipErrorInvalidValue;
+    if (b.prec == PC_PREC_FP64) return ProbeDispatch<double, 1>::run(s, b, level, params, topq, grid);
+    return ProbeDispatch<float, 1>::run(s, b, level, params, topq, grid);
 }
 
 }  // namespace pcg

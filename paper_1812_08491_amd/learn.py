@@ -28,6 +28,7 @@ from ._lib import (PC_MAX_LEVEL, PC_MLP_HID, PC_MLP_IN, PC_MLP_PARAMS, Context, 
 
 WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
 DEFAULT_WEIGHTS = os.path.join(WEIGHTS_DIR, "order_mlp_n200.npy")
+ROW_WEIGHTS = os.path.join(WEIGHTS_DIR, "order_row_mlp_n200.npy")
 PROBE_MAX_LEVEL = 8     # the probe pass runs for levels 1 .. 8
 
 
@@ -237,58 +238,225 @@ def collect(datasets, n: int, m: int, cap_per_level: int, seed: int = 0, log=Non
     return torch.cat(feats), torch.cat(labels)
 
 
+class NodeRowCollector:
+    """Level-1 training rows of the shared-set order (one per candidate k of node i) for datasets
+    of one shape: level 0 through pc_corr, then pc_row_features on its G'."""
+
+    def __init__(self, n: int, m: int, precision: str = "fp32"):
+        torch = _torch()
+        self.n, self.m = n, m
+        self.ctx = Context(precision=precision)
+        self.ws = self.ctx.workspace(n, m)
+        self.adj = self.ctx.adjacency(n)
+        self.cap = 1 << 16
+        self._alloc()
+
+    def _alloc(self):
+        torch = _torch()
+        self.feats = torch.empty((self.cap, PC_MLP_IN), dtype=torch.float32, device="cuda")
+        self.labels = torch.empty(self.cap, dtype=torch.float32, device="cuda")
+        self.meta = torch.empty((self.cap, 2), dtype=torch.int32, device="cuda")
+
+    def run(self, X, alpha: float):
+        """(feats [r, 8], labels [r], node i [r], candidate k [r], C) of dataset X."""
+        torch = _torch()
+        Xd = X if torch.is_tensor(X) else torch.from_numpy(np.ascontiguousarray(X)).cuda()
+        C = torch.empty((self.n, self.n), dtype=torch.float32, device="cuda")
+        self.ctx.pc_corr(Xd, alpha, self.ws, C_out=C, adj_out=self.adj)
+        while True:
+            rows = self.ctx.pc_row_features(1, self.n, self.m, alpha, self.adj, self.feats, self.labels, self.meta,
+                                            self.ws)
+            if rows >= 0:
+                break
+            self.cap = max(-rows, 2 * self.cap)
+            self._alloc()
+        mi, mk = self.meta[:rows].long().unbind(1)
+        return self.feats[:rows].clone(), self.labels[:rows].clone(), mi, mk, C
+
+    def close(self):
+        self.ctx.close()
+
+
+def edge_coverage(scores, node, cand, C, adj_dense, alpha: float, m: int, tops=(1, 2, 4, 8)) -> dict:
+    """For one dataset: the fraction of level-1-separable edges (i, j) of G' (some k in N_i or N_j
+    gives |rho_ij.k| <= tanh(tau_1)) that a set {k} of the T best-scored candidates of i or of j
+    separates, for each T in tops."""
+    torch = _torch()
+    from ._lib import pc_threshold
+    n = C.shape[0]
+    th = math.tanh(pc_threshold(alpha, m, 1))
+    G = adj_dense
+    Cd = C.double()
+    # independence of (i, j) given k for all triples with k adjacent to i or j
+    ii, jj = torch.nonzero(torch.triu(G, 1), as_tuple=True)
+    if ii.numel() == 0:
+        return {T: float("nan") for T in tops}
+    cij, cik, cjk = Cd[ii, jj].unsqueeze(1), Cd[ii], Cd[jj]
+    den = ((1 - cik ** 2) * (1 - cjk ** 2)).clamp_min(0)
+    indep = ((cij - cik * cjk).abs() <= th * den.sqrt()) & (den > 0)
+    kmask = (G[ii] | G[jj])
+    kmask[torch.arange(ii.numel()), ii] = False
+    kmask[torch.arange(ii.numel()), jj] = False
+    sep = (indep & kmask).any(1)
+    # rank of each candidate within its node by score (ties: lower candidate id first)
+    rank = torch.full((n, n), 1 << 30, dtype=torch.long, device="cuda")
+    order = torch.argsort(cand.double() - scores.double() * 1e6, stable=True)   # score desc, then id
+    order = order[torch.argsort(node[order], stable=True)]
+    nd = node[order]
+    start = torch.ones_like(nd, dtype=torch.bool)
+    start[1:] = nd[1:] != nd[:-1]
+    seg = torch.cumsum(start.long(), 0) - 1
+    first = torch.nonzero(start).squeeze(1)
+    rank[nd, cand[order]] = torch.arange(nd.numel(), device="cuda") - first[seg]
+    out = {}
+    for T in tops:
+        topk = (rank < T)
+        cover = indep & ((topk[ii] & G[ii]) | (topk[jj] & G[jj]))
+        cover[torch.arange(ii.numel()), ii] = False
+        cover[torch.arange(ii.numel()), jj] = False
+        out[T] = float((cover.any(1) & sep).sum().item() / max(int(sep.sum().item()), 1))
+    return out
+
+
 def compare_orders(X, alpha: float, params, precision: str = "fp32", min_level: int = 2, top: int = 4,
-                   repeats: int = 3):
+                   repeats: int = 3, max_level: int = 0, row_params=None, row_top: int = 0):
     """Plain vs learned-order skeleton on the same data: identical adjacency is required; returns
-    per-run tests and wall times (median over repeats after one warm-up)."""
+    per-run tests and wall times (median over repeats after one warm-up of each, the two orders
+    alternating so that both see the same device state)."""
     torch = _torch()
     Xd = X if torch.is_tensor(X) else torch.from_numpy(np.ascontiguousarray(X)).cuda()
     m, n = Xd.shape
-    res = {}
+    runs = {}
     for mode in ("plain", "learned"):
         ctx = Context(precision=precision)
         adj = ctx.adjacency(n)
         recs, count = ctx.sepsets(n * (n - 1) // 2)
+        order = None
         if mode == "plain":
             ws = ctx.workspace(n, m)
         else:
-            order = ctx.order(params, min_level=min_level, top=top)
+            order = ctx.order(params, min_level=min_level, top=top, max_level=max_level, row_params=row_params,
+                              row_top=row_top)
             ws = ctx.ordered_workspace(n, m, order)
-        walls, st = [], None
-        for r in range(repeats + 1):
-            st = pc_run_stats()
-            torch.cuda.synchronize()
-            if mode == "plain":
-                ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st)
-            else:
-                ctx.pc_skeleton_ordered(Xd, alpha, adj, recs, count, ws, order, stats=st)
-            torch.cuda.synchronize()
-            if r > 0:
-                walls.append(st.wall_ms)
-        d = st.as_dict()
-        res[mode] = {"adj": adj.cpu().numpy(), "wall_ms": float(np.median(walls)), "tests": d["tests"],
+        runs[mode] = dict(ctx=ctx, adj=adj, recs=recs, count=count, ws=ws, order=order, walls=[], st=None)
+
+    def once(mode):
+        r = runs[mode]
+        st = pc_run_stats()
+        torch.cuda.synchronize()
+        if mode == "plain":
+            r["ctx"].pc_skeleton(Xd, alpha, r["adj"], r["recs"], r["count"], r["ws"], stats=st)
+        else:
+            r["ctx"].pc_skeleton_ordered(Xd, alpha, r["adj"], r["recs"], r["count"], r["ws"], r["order"], stats=st)
+        torch.cuda.synchronize()
+        r["st"] = st
+        return st.wall_ms
+
+    for rep in range(repeats + 1):
+        for mode in ("plain", "learned"):
+            w = once(mode)
+            if rep > 0:
+                runs[mode]["walls"].append(w)
+    res = {}
+    for mode, r in runs.items():
+        d = r["st"].as_dict()
+        res[mode] = {"adj": r["adj"].cpu().numpy(), "wall_ms": float(np.median(r["walls"])), "tests": d["tests"],
                      "probe_tests": d["probe_tests"], "probe_removed": d["probe_removed"],
                      "levels_run": d["levels_run"]}
-        ctx.close()
+        r["ctx"].close()
     same = bool(np.array_equal(res["plain"].pop("adj"), res["learned"].pop("adj")))
     return {"same_skeleton": same, **res}
 
 
+def train_rows(args, log) -> None:
+    """Shared-set (row) model: level-1 rows of generated n = 200 SEMs, weighted BCE, and the edge
+    coverage of its top-T candidates per node against |C_ik| order and a random order."""
+    torch = _torch()
+    import semgen
+    from ._lib import bits_to_dense
+    t0 = time.time()
+    coll = NodeRowCollector(200, 1000)
+    feats, labels = [], []
+    for k, (X, _, a) in enumerate(semgen.training_sems(args.sems, instance=0)):
+        f, y, _, _, _ = coll.run(X, a)
+        feats.append(f)
+        labels.append(y)
+        if (k + 1) % 200 == 0:
+            log(f"collected {k + 1} datasets, {sum(x.shape[0] for x in feats)} rows, {time.time() - t0:.1f} s")
+    X = torch.cat(feats)
+    y = torch.cat(labels)
+    t_collect = time.time() - t0
+    pos = float(y.sum().item())
+    pos_weight = float(min(50.0, max(1.0, (y.numel() - pos) / max(pos, 1.0))))
+    log(f"{X.shape[0]} training rows, {pos / max(y.numel(), 1):.3f} positive, pos_weight {pos_weight:.2f}")
+    val = []
+    for Xv, _, a in semgen.training_sems(args.val_sems, instance=1):
+        f, yv, mi, mk, C = coll.run(Xv, a)
+        G = torch.from_numpy(bits_to_dense(coll.adj.cpu().numpy(), 200).astype(bool)).cuda()
+        val.append((f, yv, mi, mk, C, G, a))
+    trainer = Trainer(seed=args.seed, lr=args.lr)
+
+    def coverage(score_fn):
+        acc = {T: [] for T in (1, 2, 4, 8)}
+        for f, yv, mi, mk, C, G, a in val:
+            cov = edge_coverage(score_fn(f), mi, mk, C, G, a, 1000)
+            for T in acc:
+                if cov[T] == cov[T]:
+                    acc[T].append(cov[T])
+        return {T: float(np.mean(v)) if v else float("nan") for T, v in acc.items()}
+
+    base_abs = coverage(lambda f: f[:, 0].contiguous())
+    base_rand = coverage(lambda f: torch.rand(f.shape[0], device="cuda"))
+    log(f"|C_ik| order coverage@1/2/4/8: {base_abs[1]:.3f} {base_abs[2]:.3f} {base_abs[4]:.3f} {base_abs[8]:.3f}")
+    log(f"random order coverage@1/2/4/8: {base_rand[1]:.3f} {base_rand[2]:.3f} {base_rand[4]:.3f} {base_rand[8]:.3f}")
+    vX = torch.cat([v[0] for v in val])
+    vy = torch.cat([v[1] for v in val])
+    history = []
+    t1 = time.time()
+    for ep in range(args.epochs):
+        tl = trainer.epoch(X, y, pos_weight)
+        vl = bce_loss(trainer, vX, vy, pos_weight)
+        cov = coverage(lambda f: trainer.scores_of(f))
+        history.append({"epoch": ep + 1, "train_loss": tl, "val_loss": vl, "coverage": cov})
+        log(f"epoch {ep + 1}: train {tl:.4f} val {vl:.4f} coverage@1/2/4/8 {cov[1]:.3f} {cov[2]:.3f} {cov[4]:.3f} "
+            f"{cov[8]:.3f}")
+    t_train = time.time() - t1
+    coll.close()
+    out = args.out or ROW_WEIGHTS
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    np.save(out, trainer.params.cpu().numpy().astype(np.float32), allow_pickle=False)
+    meta = {"model": "row", "sems": args.sems, "n": 200, "m": 1000, "degree": "U[2,10]", "alpha": 0.01,
+            "rows": int(X.shape[0]), "positive_fraction": pos / max(y.numel(), 1), "pos_weight": pos_weight,
+            "epochs": args.epochs, "lr": args.lr, "batch": trainer.batch, "collect_s": t_collect, "train_s": t_train,
+            "abs_corr_coverage": base_abs, "random_coverage": base_rand, "history": history}
+    with open(os.path.splitext(out)[0] + ".json", "w") as f:
+        json.dump(meta, f, indent=1)
+    log(f"saved {out} (collect {t_collect:.1f} s, train {t_train:.1f} s)")
+    trainer.close()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Train the conditioning-set scorer on generated SEMs.")
+    ap.add_argument("--model", choices=("edge", "row"), default="edge",
+                    help="edge: the probe pass's per-edge scorer; row: the level-1 shared-set order")
     ap.add_argument("--sems", type=int, default=2000)
     ap.add_argument("--val-sems", type=int, default=100)
     ap.add_argument("--cap", type=int, default=2048, help="labelled rows kept per level and SEM")
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     import semgen  # the project's seeded SEM generator (repository root)
     torch = _torch()
 
     def log(msg):
         print(f"[learn] {msg}", flush=True)
+
+    if args.model == "row":
+        train_rows(args, log)
+        return
+    args.out = args.out or DEFAULT_WEIGHTS
 
     train_sets = ((X, a) for X, _, a in semgen.training_sems(args.sems, instance=0))
     t0 = time.time()

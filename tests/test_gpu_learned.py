@@ -193,3 +193,84 @@ def test_training_pipeline_beats_random_order_and_keeps_skeleton():
     assert cmp["same_skeleton"]
     assert sum(cmp["learned"]["probe_removed"]) > 0
     tr.close()
+
+
+def test_row_features_match_recomputation():
+    """Shared-set (row) features and labels of level 1 against values recomputed on the host from
+    the same FP32 C and G'."""
+    rng = np.random.default_rng(21)
+    n, m, alpha = 90, 400, 0.05
+    X = semgen.sample(semgen.random_dag(n, 0.08, rng), m, rng)
+    ctx = pc.Context(precision="fp32")
+    ws = ctx.workspace(n, m)
+    adj = ctx.adjacency(n)
+    C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    ctx.pc_corr(dev(X, torch.float64), alpha, ws, C_out=C, adj_out=adj)
+    G = pc.bits_to_dense(adj.cpu().numpy(), n).astype(bool)
+    Cn = C.cpu().numpy().astype(np.float64)
+    deg = G.sum(1)
+    need = int(deg.sum())
+    feats = torch.empty((need, 8), device="cuda")
+    labels = torch.empty(need, device="cuda")
+    meta = torch.empty((need, 2), dtype=torch.int32, device="cuda")
+    rows = ctx.pc_row_features(1, n, m, alpha, adj, feats, labels, meta, ws)
+    assert rows == need
+    F, Y, M = feats.cpu().numpy(), labels.cpu().numpy(), meta.cpu().numpy()
+    assert [tuple(r) for r in M] == [(i, k) for i in range(n) for k in np.flatnonzero(G[i])]
+    th = math.tanh(pc.pc_threshold(alpha, m, 1))
+    checked = 0
+    for r, (i, k) in enumerate(M):
+        Ni = np.flatnonzero(G[i])
+        d = Ni.size
+        a = np.abs(Cn[i, Ni])
+        p = int(np.flatnonzero(Ni == k)[0])
+        cn = int(np.sum(G[i] & G[k]))
+        want = [a[p], a[p] / a.max(), cn / d, cn / deg[k] if deg[k] else 0.0, d / 256, deg[k] / 256, 1 / 8, a.mean()]
+        assert np.allclose(F[r], want, atol=2e-5), (i, k, F[r], want)
+        js = Ni[Ni != k]
+        lhs = np.abs(Cn[i, js] - Cn[i, k] * Cn[js, k])
+        rhs = th * np.sqrt((1 - Cn[i, k] ** 2) * (1 - Cn[js, k] ** 2))
+        if js.size and np.min(np.abs(lhs - rhs)) < 1e-5:
+            continue   # FP32 tie: either label is right
+        assert Y[r] == float(np.any(lhs <= rhs)), (i, k)
+        checked += 1
+    assert checked > 0.9 * rows and Y.sum() > 0
+
+
+@pytest.mark.parametrize("seed,prec,row_top,with_edge", [(0, "fp32", 4, False), (1, "fp64", 1, False),
+                                                         (2, "bf16x3", 16, False), (3, "fp32", 3, True)])
+def test_row_order_skeleton_equals_oracle_for_any_weights(seed, prec, row_top, with_edge):
+    """The shared-set order (any weights) reorders level 1's sets only: the skeleton is the oracle's,
+    every SepSet separates, and the probe part of level 1 ran."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(60, 200))
+    X = semgen.sample(semgen.random_dag(n, float(rng.uniform(0.05, 0.2)), rng), int(rng.integers(300, 1500)), rng)
+    alpha = 0.05
+    row_params = dev(mlp.init(rng) * rng.uniform(0.1, 3.0))
+    params = dev(mlp.init(rng)) if with_edge else None
+    G, seps, st, status = ordered_run(X, alpha, params, prec, min_level=2, top=4, row_params=row_params,
+                                      row_top=row_top)
+    C = oracle.corr(X)
+    ref = oracle.skeleton_corr(C, X.shape[0], alpha, keep_levels=True)
+    assert np.array_equal(G, ref.G)
+    assert set(seps) == set(ref.sepsets.as_dict())
+    for e, (l, S) in seps.items():
+        assert ref.sepsets.as_dict()[e][0] == l
+        assert oracle.ci_test(C, e[0], e[1], list(S), X.shape[0], alpha)[0]
+    if st["levels_run"] > 1:
+        assert st["probe_tests"][1] > 0
+        assert st["tests"][1] >= st["probe_tests"][1]
+
+
+def test_row_order_n2000_matches_oracle_with_trained_weights():
+    """The n = 2000 workload with the trained row model (or fresh weights if none is stored)."""
+    import os
+    from paper_1812_08491_amd import learn
+    X, sem, alpha = semgen.workload("n2000_d10_m1000_apply")
+    row = learn.load_weights(learn.ROW_WEIGHTS) if os.path.exists(learn.ROW_WEIGHTS) else dev(
+        mlp.init(np.random.default_rng(5)))
+    G, seps, st, status = ordered_run(X, alpha, None, "fp32", row_params=row, row_top=4)
+    ref = oracle.skeleton(X, alpha)
+    assert np.array_equal(G, ref.G)
+    assert set(seps) == set(ref.sepsets.as_dict())
+    print("level-1 tests", st["tests"][1], "probe", st["probe_tests"][1], "probe removed", st["probe_removed"][1])
