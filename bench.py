@@ -38,6 +38,7 @@ APPLY_WORKLOAD = "n2000_d10_m1000_apply"
 PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_level1_n1000_d4_m500.json")
+ROW_TOP = 2   # candidates per node the learned order tests first at level 1
 LEVEL_SOURCES = ["paper_1812_08491_amd/csrc/pc_level.h", "paper_1812_08491_amd/csrc/pc_level_f32.hip",
                  "paper_1812_08491_amd/csrc/pc_citest.h", "paper_1812_08491_amd/csrc/pc_dev.h",
                  "paper_1812_08491_amd/csrc/pc_comb.h"]
@@ -256,7 +257,10 @@ def main() -> int:
         # -- plain vs learned conditioning-set order (same data, identical skeleton required) ------
         from paper_1812_08491_amd import learn
         Xa, _, alpha_a = semgen.workload(APPLY_WORKLOAD)
-        cmp = learn.compare_orders(Xa, alpha_a, learn.load_weights(), min_level=2, top=4, repeats=5)
+        # The shared-set (row) model orders level 1, where this workload's tests are: each node's
+        # ROW_TOP best-scored candidates are tested first as sets {k}, then the rest.
+        cmp = learn.compare_orders(Xa, alpha_a, None, row_params=learn.load_weights(learn.ROW_WEIGHTS),
+                                   row_top=ROW_TOP, repeats=9)
         tp, tl = sum(cmp["plain"]["tests"]), sum(cmp["learned"]["tests"])
         out["learned_vs_plain"] = {
             "workload": "n2000_deg10_m1000_alpha0.01_fp32", "same_skeleton": cmp["same_skeleton"],
@@ -266,7 +270,9 @@ def main() -> int:
             "learned_tests_per_s": tl / (cmp["learned"]["wall_ms"] * 1e-3),
             "probe_tests": sum(cmp["learned"]["probe_tests"]),
             "probe_removed": sum(cmp["learned"]["probe_removed"]),
-            "order": {"min_level": 2, "top": 4, "weights": "weights/order_mlp_n200.npy"}}
+            "level1_tests": [cmp["plain"]["tests"][1], cmp["learned"]["tests"][1]],
+            "order": {"form": "shared-set (row) model at level 1", "row_top": ROW_TOP,
+                      "weights": "weights/order_row_mlp_n200.npy"}}
         # -- 256 uneven datasets in one captured graph --------------------------------------------
         batch = semgen.batch_problems(256)
         bstream = torch.cuda.Stream()

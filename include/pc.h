@@ -285,8 +285,8 @@ pc_status pc_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha
 
 /* Training rows of the shared-set order at level 1 for the snapshot adj (device bit matrix, not
  * modified): one row per (i, k in N_i), ordered by i then position of k, with the 8 features of
- * pc_skeleton_ordered's row model, label 1.0 when {k} separates at least one edge (i, j) by the FP32
- * test (|rho_ij.k| <= tanh(tau_1), no re-check band) and 0.0 otherwise, and meta (i, k).
+ * pc_skeleton_ordered's row model, as label the fraction of the other edges (i, j) of the row that
+ * {k} separates by the FP32 test (|rho_ij.k| <= tanh(tau_1), no re-check band), and meta (i, k).
  *   feats device rows x 8 FP32; labels device rows FP32; meta device rows x 2 int32 (optional).
  *   level must be 1; other arguments as in pc_features. Synchronises the stream. */
 pc_status pc_row_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, const uint64_t *adj,

@@ -1069,8 +1069,9 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
 }
 
 // Training rows of the shared-set order at level 1: the features of every candidate k of every
-// node i, and label 1 when {k} separates at least one edge (i, j), j in N_i \ {k}, by the FP32 test
-// |rho_ij.k| <= tanh(tau_1) (Eq. 3-6 at l = 1, without the re-check band). meta gets (i, k).
+// node i, and as label the fraction of the other edges (i, j), j in N_i \ {k}, that {k} separates by
+// the FP32 test |rho_ij.k| <= tanh(tau_1) (Eq. 3-6 at l = 1, without the re-check band), so the
+// model ranks first the candidates that remove the most edges. meta gets (i, k).
 template <typename T>
 __global__ __launch_bounds__(256) void k_row_features(Batch b, int level, const long long *foff, float *feats,
                                                       float *labels, int *meta, const int *skip) {
@@ -1097,15 +1098,15 @@ __global__ __launch_bounds__(256) void k_row_features(Batch b, int level, const 
         for (int u = 0; u < kIn; ++u) f[u] = x[u];
         const int k = sm.nb[p];
         const float cik = (float)C[(int64_t)row * n + k];
-        bool sep = false;
-        for (int q = 0; q < d && !sep; ++q) {
+        int sep = 0;
+        for (int q = 0; q < d; ++q) {
             if (q == p) continue;
             const int j = sm.nb[q];
             const float cij = (float)C[(int64_t)row * n + j], cjk = (float)C[(int64_t)j * n + k];
             const float den = (1.0f - cik * cik) * (1.0f - cjk * cjk);
-            sep = den > 0.0f && fabsf(cij - cik * cjk) <= tl * sqrtf(den);
+            sep += (den > 0.0f && fabsf(cij - cik * cjk) <= tl * sqrtf(den)) ? 1 : 0;
         }
-        labels[base + p] = sep ? 1.0f : 0.0f;
+        labels[base + p] = d > 1 ? (float)sep / (float)(d - 1) : 0.0f;
         if (meta) {
             meta[(base + p) * 2 + 0] = row;
             meta[(base + p) * 2 + 1] = k;

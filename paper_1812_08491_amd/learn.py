@@ -387,8 +387,8 @@ def train_rows(args, log) -> None:
     y = torch.cat(labels)
     t_collect = time.time() - t0
     pos = float(y.sum().item())
-    pos_weight = float(min(50.0, max(1.0, (y.numel() - pos) / max(pos, 1.0))))
-    log(f"{X.shape[0]} training rows, {pos / max(y.numel(), 1):.3f} positive, pos_weight {pos_weight:.2f}")
+    pos_weight = 1.0   # soft labels (fractions of the row's edges separated): plain cross-entropy
+    log(f"{X.shape[0]} training rows, mean label {pos / max(y.numel(), 1):.3f}")
     val = []
     for Xv, _, a in semgen.training_sems(args.val_sems, instance=1):
         f, yv, mi, mk, C = coll.run(Xv, a)
