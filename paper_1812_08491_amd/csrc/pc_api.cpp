@@ -405,7 +405,7 @@ pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, co
         // list and their sets are tested first (in the ordering kernel), then the level kernel runs
         // the remaining ranks; together they cover every set of the level once, on the same G'.
         const int T = ord->order->row_top;
-        PC_HIP(launch_row_order(s, b, level, ord->order->row_params, T, 2 * ctx->num_cu));
+        PC_HIP(launch_row_order(s, b, level, ord->order->row_params, T, ctx->num_cu));
         Batch bm = b;
         bm.rank_lo = (unsigned long long)T;
         PC_HIP(launch_window(s, bm, level, R));

@@ -203,7 +203,8 @@ hipError_t launch_adam(hipStream_t s, float *params, const float *grads, float *
 hipError_t launch_feat_plan(hipStream_t s, const Batch &b, long long *foff, long long cap, int *skip);
 hipError_t launch_features(hipStream_t s, const Batch &b, int level, const long long *foff, float *feats,
                            int *meta, const int *skip);
-// Shared-set order: reorders each row's neighbour list, the `top` best-scored candidates first.
+// Shared-set order: reorders each row's neighbour list, the `top` best-scored candidates first, and
+// tests their sets. grid: compute units (the launch fills them).
 hipError_t launch_row_order(hipStream_t s, const Batch &b, int level, const float *params, int top, int grid);
 // Training rows of the shared-set order (features, labels, meta (i, k)) after a compaction.
 hipError_t launch_row_features(hipStream_t s, const Batch &b, int level, long long *foff, long long cap, int *skip,

@@ -1114,13 +1114,21 @@ __global__ __launch_bounds__(256) void k_row_features(Batch b, int level, const 
     }
 }
 
+// grid: compute units; as many work-groups per unit as fit are launched.
+template <typename T>
+static hipError_t launch_row_order_t(hipStream_t s, const Batch &b, int level, const float *params, int top,
+                                     int grid) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_row_order<T>, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 2;
+    hipLaunchKernelGGL(k_row_order<T>, dim3(per_cu * grid), dim3(256), 0, s, b, level, params, top);
+    return hipGetLastError();
+}
+
 hipError_t launch_row_order(hipStream_t s, const Batch &b, int level, const float *params, int top, int grid) {
     if (top < 1 || top > kRowTopMax) return hipErrorInvalidValue;
-    if (b.prec == PC_PREC_FP64)
-        hipLaunchKernelGGL(k_row_order<double>, dim3(grid), dim3(256), 0, s, b, level, params, top);
-    else
-        hipLaunchKernelGGL(k_row_order<float>, dim3(grid), dim3(256), 0, s, b, level, params, top);
-    return hipGetLastError();
+    if (b.prec == PC_PREC_FP64) return launch_row_order_t<double>(s, b, level, params, top, grid);
+    return launch_row_order_t<float>(s, b, level, params, top, grid);
 }
 
 hipError_t launch_row_features(hipStream_t s, const Batch &b, int level, long long *foff, long long cap, int *skip,
