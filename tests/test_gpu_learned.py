@@ -262,6 +262,37 @@ def test_row_order_skeleton_equals_oracle_for_any_weights(seed, prec, row_top, w
         assert st["tests"][1] >= st["probe_tests"][1]
 
 
+def test_row_order_rows_beyond_scorer_capacity():
+    """Rows of more than 1024 neighbours are not scored: they keep their order, the ordering pass
+    tests their first sets and the level kernel the rest, so the skeleton is still the oracle's."""
+    rng = np.random.default_rng(41)
+    F = rng.standard_normal(300)
+    X = F[:, None] + rng.standard_normal((300, 1100))
+    X[:, 0] = F
+    X = np.ascontiguousarray(X)
+    row_params = dev(mlp.init(np.random.default_rng(6)))
+    m, n = X.shape
+    ctx = pc.Context(precision="fp32")
+    order = ctx.order(None, row_params=row_params, row_top=2)
+    ws = ctx.ordered_workspace(n, m, order)
+    adj = ctx.adjacency(n)
+    recs, count = ctx.sepsets(n * (n - 1) // 2)
+    st = pc.pc_run_stats()
+    status = ctx.pc_skeleton_ordered(dev(X, torch.float64), 0.001, adj, recs, count, ws, order, max_level=1,
+                                     stats=st)
+    assert status == 0
+    k = int(count.item())
+    G, seps, st = pc.bits_to_dense(adj.cpu().numpy(), n), pc.decode_sepsets(recs[:k].cpu().numpy(), k), st.as_dict()
+    C = oracle.corr(X)
+    ref = oracle.skeleton_corr(C, m, 0.001, max_level=1)
+    assert np.array_equal(G, ref.G)
+    assert set(seps) == set(ref.sepsets.as_dict())
+    for e, (l, S) in seps.items():
+        assert ref.sepsets.as_dict()[e][0] == l
+        assert oracle.ci_test(C, e[0], e[1], list(S), m, 0.001)[0]
+    assert st["probe_tests"][1] > 0
+
+
 def test_row_order_n2000_matches_oracle_with_trained_weights():
     """The n = 2000 workload with the trained row model (or fresh weights if none is stored)."""
     import os

@@ -213,6 +213,27 @@ def test_skeleton_max_level_and_global_gather_path():
     compare_with_oracle(X, 0.05, "fp32", ranks_per_lane=1, grid=3)
 
 
+def factor_data(n, m, seed):
+    """One latent factor F = X_0 shared by every other variable (X_i = F + noise): level 0 keeps the
+    complete graph, so every row has n - 1 neighbours, and level 1 separates the pairs (i, j) by
+    {0}. With n - 1 > 1024 no row's neighbour list fits in LDS: the level kernel takes its
+    global-memory placement for every item."""
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal(m)
+    X = F[:, None] + rng.standard_normal((m, n))
+    X[:, 0] = F
+    return np.ascontiguousarray(X)
+
+
+@pytest.mark.parametrize("prec,opt", [("fp32", {}), ("fp64", {}), ("fp32", {"tests_per_lane": 1})])
+def test_skeleton_rows_beyond_lds_capacity(prec, opt):
+    X = factor_data(1100, 300, 41)
+    print(f"rows beyond LDS capacity prec={prec} {opt}", flush=True)
+    st, ref = compare_with_oracle(X, 0.001, prec, max_level=1, **opt)
+    assert ref.G_after[0].sum(1).min() == 1099
+    assert st["tests"][1] >= 604450 - 1100
+
+
 def test_skeleton_sample_limit_warning():
     X = sem_data(5, 12, 0.9, 7)
     compare_with_oracle(X, 0.5, "fp64")
