@@ -5,8 +5,9 @@ level until the stop rule, FP64 re-checks included) of a synthetic linear-Gaussi
 is already resident in HBM: n = 1000 variables, expected degree 4, m = 500 samples, alpha = 0.01,
 FP32 CI tests with FP64 re-checks of borderline tests. The skeleton is captured once as a hipGraph
 (pc_batch_capture) and each step is one replay; `ms_per_step` is the replay time. The graph records
-as many levels as an untimed pc_skeleton run on the same data needed (graph_levels), and the run
-asserts that no replay needed the stream continuation of pc_graph_results.
+the levels with many tests (those above TAIL_TESTS in an untimed pc_skeleton run on the same data)
+as level kernels, and the small levels after them as the tail kernel (one work-group per problem);
+the run asserts that no replay needed the stream continuation of pc_graph_results.
 
 `value` is CI tests per second: the tests the sequential PC-stable enumeration performs on this
 input (canonical order, early stop per edge; counted by the CPU oracle in the cpu_baseline leg, on
@@ -39,6 +40,8 @@ PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_level1_n1000_d4_m500.json")
 ROW_TOP = 2   # candidates per node the learned order tests first at level 1
+TAIL_TESTS = 16384    # levels with more CI tests than this run as level kernels in the graph
+TAIL_MAX_LEVEL = 8    # deepest level the tail kernel runs
 LEVEL_SOURCES = ["paper_1812_08491_amd/csrc/pc_level.h", "paper_1812_08491_amd/csrc/pc_level_f32.hip",
                  "paper_1812_08491_amd/csrc/pc_citest.h", "paper_1812_08491_amd/csrc/pc_dev.h",
                  "paper_1812_08491_amd/csrc/pc_comb.h"]
@@ -124,6 +127,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the learned-order and batch legs")
+    ap.add_argument("--graph-levels", type=int, default=0,
+                    help="levels recorded as level kernels before the tail kernel (0: from TAIL_TESTS)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                          "COPY_WRITE_CSV"))
@@ -168,15 +173,19 @@ def main() -> int:
     stream_sec = (time.perf_counter() - t0) / args.steps
     assert status == 0, pc.status_str(status)
     L = runs[-1]["levels_run"]
-    graph_levels = max(1, L - 1)
+    # Levels with many tests go to the level kernels, the rest to the tail kernel (levels <= 8).
+    big = [l for l in range(1, L) if runs[-1]["tests"][l] > TAIL_TESTS]
+    graph_levels = args.graph_levels or max([1] + big)
+    if L - 1 > TAIL_MAX_LEVEL:
+        graph_levels = max(graph_levels, L - 1)
 
     # -- timed region: graph replays of the whole skeleton ----------------------------------------
     gstream = torch.cuda.Stream()
     with torch.cuda.stream(gstream):
-        # The graph records as many levels as the eager run needed (levels 1 .. L-1, then the
-        # planning pass of level L that finds no work); a deeper replay would be continued by
+        # Levels 1 .. graph_levels as level kernels, then the tail kernel (with a budget that
+        # covers any level here) up to level 8; a replay needing more would be continued by
         # pc_graph_results, which the check below rules out for the timed replays.
-        gctx = pc.Context(stream=gstream, precision="fp32", graph_levels=graph_levels)
+        gctx = pc.Context(stream=gstream, precision="fp32", graph_levels=graph_levels, tail_tests=1 << 30)
         gadj = gctx.adjacency(n)
         grecs, gcount = gctx.sepsets(n * (n - 1) // 2)
         probs = gctx.problems([(Xd, alpha, -1, gadj, grecs, gcount)])
@@ -196,7 +205,7 @@ def main() -> int:
     assert r == 0 and gstatus[0] == 0, (r, gstatus)
     G = pc.bits_to_dense(gadj.cpu().numpy(), n)
     gstats = gst[0].as_dict()
-    assert gstats["levels_run"] - 1 <= graph_levels, "the recorded graph did not cover every level"
+    assert gstats["levels_run"] - 1 <= max(graph_levels, TAIL_MAX_LEVEL), "the recorded graph did not cover every level"
 
     gpu_tests = int(sum(gstats["tests"]))
 
@@ -227,7 +236,7 @@ def main() -> int:
         "config": {"workload": "pc_stable_skeleton_n1000_deg4_m500_alpha0.01_fp32_recheck",
                    "n": n, "m": m, "expected_degree": 4, "alpha": alpha, "precision": "fp32+fp64 recheck",
                    "step": "one hipGraph replay of the whole skeleton",
-                   "graph_levels": graph_levels,
+                   "graph_levels": graph_levels, "tail_from_level": graph_levels + 1,
                    "levels_run": gstats["levels_run"], "edges": int(G.sum()) // 2},
         "gpu_tests_per_step": gpu_tests,
         "gpu_executed_tests_per_s": gpu_tests / sec_per_step,
@@ -286,17 +295,20 @@ def main() -> int:
             bprobs = bctx.problems(items)
             bws = bctx.batch_workspace(bprobs)
             bgraph = bctx.pc_batch_capture(bprobs, bws)
+            bst = (pc.pc_run_stats * len(items))()
             for _ in range(2):
                 bgraph.pc_graph_launch()
+                bgraph.pc_graph_results(bst)
             torch.cuda.synchronize()
             reps = max(3, args.steps // 5)
             b0 = time.perf_counter()
             for _ in range(reps):
+                # a replay and its results: levels some datasets need beyond the recorded ones
+                # run inside pc_graph_results, so both are timed
                 bgraph.pc_graph_launch()
+                br, bstatus = bgraph.pc_graph_results(bst)
             torch.cuda.synchronize()
             bms = (time.perf_counter() - b0) / reps * 1e3
-            bst = (pc.pc_run_stats * len(items))()
-            br, bstatus = bgraph.pc_graph_results(bst)
             bgraph.close()
         out["batch256_graph"] = {"workload": "256 datasets, n~U[20,400], degree~U[2,8], m~U[200,5000], alpha 0.01",
                                  "ms_per_batch": bms, "status": br,

@@ -38,7 +38,8 @@ class pc_options(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("max_level", ct.c_int32), ("margin_scale", ct.c_float),
                 ("force_recheck_all", ct.c_int32), ("lds_budget", ct.c_int32),
                 ("ranks_per_lane", ct.c_int32), ("grid", ct.c_int32), ("timing", ct.c_int32),
-                ("recheck_cap", ct.c_int64), ("graph_levels", ct.c_int32), ("tests_per_lane", ct.c_int32)]
+                ("recheck_cap", ct.c_int64), ("graph_levels", ct.c_int32), ("tests_per_lane", ct.c_int32),
+                ("tail_tests", ct.c_int32)]
 
 
 class pc_sep_rec(ct.Structure):

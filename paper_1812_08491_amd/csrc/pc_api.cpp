@@ -37,6 +37,8 @@ struct pc_ctx {
     hipEvent_t ev_compact[kLevels][2], ev_level[kLevels][2], ev_recheck[kLevels][2];
     int top_run;                    // highest level enqueued by the current call
     int level_grid[kLevels];        // work-groups of the level kernels: all that fit at once
+    int recheck_grid;               // work-groups of the re-check kernel: at most 4 per CU, all resident
+    bool tail_enqueued;             // the last enqueue_skeletons ended its levels with the tail kernel
 };
 
 struct pc_graph {
@@ -50,6 +52,7 @@ struct pc_graph {
     std::vector<pc_problem> probs;  // descriptors it was captured with (for continuation)
     int captured;                   // levels recorded in the graph
     int top;                        // last level any dataset may need (PC_MAX_LEVEL + 1 = planning)
+    bool tail;                      // the graph ends with the tail kernel (from level captured + 1)
 };
 
 namespace {
@@ -76,6 +79,7 @@ pc_options defaults() {
     o.timing = 0;
     o.recheck_cap = 0;
     o.graph_levels = 0;
+    o.tail_tests = 0;
     return o;
 }
 
@@ -97,6 +101,15 @@ int64_t rq_cap_of(const pc_options &o, double sum_n2) {
 }
 
 int graph_levels_of(const pc_options &o) { return o.graph_levels > 0 ? o.graph_levels : 10; }
+
+constexpr long long kAutoTailTests = 16384;
+constexpr int kTailMaxLevel = 8;   // the tail kernel's deepest level (its register budget)
+
+// Test budget of the tail kernel (0: not used).
+long long tail_cap(const pc_options &o) {
+    if (o.tail_tests < 0 || o.force_recheck_all) return 0;
+    return o.tail_tests == 0 ? kAutoTailTests : std::min<long long>(o.tail_tests, 1ll << 30);
+}
 
 // Standard normal CDF from erfc, and its inverse by Halley's method started from the rational
 // approximation of Abramowitz & Stegun 26.2.23 (|error| < 4.5e-4); a few Halley steps reach full
@@ -378,6 +391,13 @@ bool probe_level(const pc_order *o, int level) {
     return level >= o->min_level && level <= hi && level <= kProbeMaxLevel && level <= o->top;
 }
 
+// Whether the tail kernel may take over from `level`: enabled, and no per-edge probe pass would
+// have run at that level or later.
+bool tail_allowed(const pc_ctx *ctx, const OrderRun *ord, int level) {
+    if (tail_cap(ctx->opt) <= 0 || level < 2 || level > kTailMaxLevel) return false;
+    return !(ord && ord->order->params);
+}
+
 // Compaction and planning of one level: the snapshot G' and the work plan (and the stop rule's
 // maximum degree) of every problem. Level PC_MAX_LEVEL + 1 is planned only, to tell whether the
 // level cap stopped a run.
@@ -415,7 +435,7 @@ pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, co
     }
     if (timed(ctx, 2, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][1], s));
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][0], s));
-    PC_HIP(launch_recheck(s, b, level, 4 * ctx->num_cu));
+    PC_HIP(launch_recheck(s, b, level, ctx->recheck_grid));
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][1], s));
     ctx->top_run = std::max(ctx->top_run, level);
     return PC_OK;
@@ -446,16 +466,33 @@ pc_status run_levels_eager(pc_ctx *ctx, const Batch &b, const Plan &L, unsigned 
     std::vector<Prob> host;
     DevState ds;
     int l = from;
+    int tail_after = 1;   // the tail kernel is tried only above the level where it last stopped
     while (l <= top) {
         pc_status s = read_table(ctx, L, ws, host, ds);
         if (s != PC_OK) return s;
         if (ds.done) break;
         int last = 0;
+        long long est = 0;   // bound on the tests of level l: items x sets per item x candidates
         for (const Prob &P : host) {
             const int md = P.maxdeg[l];
             if (md - 1 >= l) last = std::max(last, std::min(std::min(P.max_level, PC_MAX_LEVEL + 1), md - 1));
+            if (l <= PC_MAX_LEVEL) est += P.items[l] * (long long)ranks_per_item(ctx, l) * std::max(md - l, 0);
         }
         if (last < l) break;
+        if (l > tail_after && l <= top && tail_allowed(ctx, ord, l) && est <= tail_cap(ctx->opt)) {
+            // Few tests left: the rest of every problem in one work-group each; problems the tail
+            // leaves at a larger level continue here from the smallest such level.
+            PC_HIP(launch_tail(ctx->stream, b, l, tail_cap(ctx->opt)));
+            if ((s = read_table(ctx, L, ws, host, ds)) != PC_OK) return s;
+            int next = 0;
+            for (const Prob &P : host)
+                if (P.tail_next > 0) next = next == 0 ? P.tail_next : std::min(next, P.tail_next);
+            if (next == 0 || next > top) break;
+            tail_after = next;
+            l = next;
+            if ((s = enqueue_plan(ctx, b, l, false)) != PC_OK) return s;
+            continue;
+        }
         const int upto = std::min(top, last - l >= 6 ? l + 3 : last);
         for (; l <= upto; ++l) {
             if (l <= PC_MAX_LEVEL && (s = enqueue_run(ctx, b, l, false, ord)) != PC_OK) return s;
@@ -584,12 +621,22 @@ pc_status enqueue_skeletons(pc_ctx *ctx, const pc_problem *pp, int count, const 
     const OrderRun *po = order ? &ord : nullptr;
     const int top = levels_to_enqueue(pp, count);
     ctx->top_run = 0;
+    ctx->tail_enqueued = false;
     if (capturing) {
-        // A graph holds levels 1..G and the planning of G + 1; pc_graph_results continues the rest.
+        // A graph holds levels 1..G and then either the tail kernel from G + 1 (which runs the
+        // rest while levels stay small) or the planning of G + 1; pc_graph_results continues
+        // whatever is left.
         const int G = std::min(top, graph_levels_of(ctx->opt));
         for (int l = 1; l <= G; ++l)
             if ((s = enqueue_level(ctx, b, l, true, po)) != PC_OK) return s;
-        if (G < top && (s = enqueue_plan(ctx, b, G + 1, true)) != PC_OK) return s;
+        if (G < top) {
+            if (tail_allowed(ctx, po, G + 1)) {
+                PC_HIP(launch_tail(ctx->stream, b, G + 1, tail_cap(ctx->opt)));
+                ctx->tail_enqueued = true;
+            } else if ((s = enqueue_plan(ctx, b, G + 1, true)) != PC_OK) {
+                return s;
+            }
+        }
         return PC_OK;
     }
     if (top < 1) return PC_OK;
@@ -680,6 +727,10 @@ pc_status pc_create(pc_ctx **out, void *stream, const pc_options *opt) {
     for (int l = 0; l < kLevels; ++l) {
         const int nb = l >= 1 && l <= PC_MAX_LEVEL ? level_blocks_per_cu(o.precision, l, level_lds_bytes(c)) : 0;
         c->level_grid[l] = nb > 0 ? nb * c->num_cu : 0;
+    }
+    {
+        const int nb = recheck_blocks_per_cu();
+        c->recheck_grid = (nb > 0 ? std::min(nb, 4) : 4) * c->num_cu;
     }
     if (ok && ensure_binom(c, 8191) != PC_OK) ok = false;
     if (ok && hipStreamSynchronize(c->stream) != hipSuccess) ok = false;
@@ -867,6 +918,7 @@ pc_status pc_batch_capture(pc_ctx *ctx, const pc_problem *probs, int count, void
         return PC_ERR_HIP;
     }
     s = enqueue_skeletons(ctx, probs, count, L, g->ws, true);
+    g->tail = ctx->tail_enqueued;
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
     if (s != PC_OK || ec != hipSuccess) {
@@ -897,8 +949,22 @@ pc_status pc_graph_results(pc_graph *g, pc_run_stats *st, pc_status *status) {
         // Datasets that still have work after the recorded levels continue on the stream.
         const Plan L = plan_of(g->probs.data(), g->count, ctx->opt);
         const Batch b = make_batch(ctx, L, g->ws);
-        pc_status s = run_levels_eager(ctx, b, L, g->ws, g->captured + 1, g->top, nullptr);
-        if (s != PC_OK) return s;
+        int from = g->captured + 1;
+        if (g->tail) {
+            // after the tail kernel: from the smallest level it left to the level kernels
+            std::vector<Prob> host;
+            DevState ds;
+            pc_status s = read_table(ctx, L, g->ws, host, ds);
+            if (s != PC_OK) return s;
+            from = 0;
+            for (const Prob &P : host)
+                if (P.tail_next > 0) from = from == 0 ? P.tail_next : std::min(from, P.tail_next);
+            if (from > 0 && from <= g->top && !ds.done && (s = enqueue_plan(ctx, b, from, false)) != PC_OK) return s;
+        }
+        if (from > 0 && from <= g->top) {
+            pc_status s = run_levels_eager(ctx, b, L, g->ws, from, g->top, nullptr);
+            if (s != PC_OK) return s;
+        }
     }
     std::vector<Prob> host;
     return collect(ctx, g->table_off, g->st_off, g->count, g->ws, st, status, host);

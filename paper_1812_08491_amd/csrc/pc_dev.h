@@ -71,6 +71,8 @@ struct Prob {
     long long *rec_count;
     int max_level;                 // last level to run (PC_MAX_LEVEL + 1: until the stop rule)
     int err;                       // device-detected input error (pc_status)
+    int tail_next;                 // after the tail kernel: level it left to the level kernels (0: none)
+    int tail_done;                 // levels up to this one were run (or found empty) by the tail kernel
     double t0, eps_c;              // level 0: tanh(tau_0) and the C error bound (low precision)
     double tau[kLevels];           // tau_l; NaN when m - l - 3 <= 0
     float t[kLevels];              // tanh(tau_l) in FP32
@@ -187,6 +189,12 @@ hipError_t launch_window(hipStream_t s, const Batch &b, int level, int ranks_per
 hipError_t launch_level(hipStream_t s, const Batch &b, int level, int ranks_per_item, int lds_bytes,
                         int grid);
 hipError_t launch_recheck(hipStream_t s, const Batch &b, int level, int grid);
+int recheck_blocks_per_cu();                                    // resident re-check work-groups per CU
+
+// pc_tail.hip
+// The remaining levels from `level` of every problem, one work-group per problem, as long as a
+// level has at most cap_tests CI tests (an upper bound from the degrees) and l <= kFastLevels.
+hipError_t launch_tail(hipStream_t s, const Batch &b, int level, long long cap_tests);
 int level_blocks_per_cu(int prec, int level, int lds_bytes);   // resident work-groups per CU
 size_t level_lds_fixed(int prec);
 

@@ -61,9 +61,10 @@ __device__ inline void flush_stats(const Batch &b, Prob &P, long long &tests, lo
     removed = 0;
 }
 
-// Whether level l runs for problem P (the level cap, Eq. 6 needing m - l - 3 > 0).
+// Whether level l runs for problem P (the level cap, Eq. 6 needing m - l - 3 > 0), and was not
+// already run by the tail kernel.
 __device__ inline bool level_enabled(const Prob &P, int l) {
-    return l <= P.max_level && l <= PC_MAX_LEVEL && P.tau[l] == P.tau[l];
+    return l <= P.max_level && l <= PC_MAX_LEVEL && P.tau[l] == P.tau[l] && l > P.tail_done;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -200,18 +201,20 @@ constexpr int kRcChunk = 16;   // consecutive samples per lane per round
 // reads the 16 consecutive samples 64 q + 16 (l / 16) of round q = 0..3, all loads issued before
 // the products, and each round feeds its own accumulator so the four product chains overlap.
 // Returns the tile in the D layout of the instruction (lane l: rows l / 16 + 4 t, column l % 16).
+// R < 4 rounds per block (blocks of 64 R samples) hold fewer samples in registers at once.
+template <int R = 4>
 __device__ inline doublex4 gram_part(const Prob &P, int vr, int lane, int64_t x_first, int64_t x_step) {
     const int64_t mp = P.mp;
     const double *z = P.zt64 + (int64_t)(vr < 0 ? 0 : vr) * mp;
     const int64_t off = (int64_t)(lane >> 4) * kRcChunk;
-    doublex4 acc[4];
+    doublex4 acc[R];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < R; ++q) acc[q] = doublex4{0.0, 0.0, 0.0, 0.0};
     // mp is a multiple of 64, so a lane's chunk of 16 is either wholly inside or outside.
     for (int64_t x0 = x_first; x0 < mp; x0 += x_step) {
-        double v[4][kRcChunk];
+        double v[R][kRcChunk];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < R; ++q) {
             const int64_t x = x0 + 64 * q + off;
             if (vr >= 0 && x < mp) {
                 const double2 *src = reinterpret_cast<const double2 *>(z + x);
@@ -229,9 +232,11 @@ __device__ inline doublex4 gram_part(const Prob &P, int vr, int lane, int64_t x_
 #pragma unroll
         for (int u = 0; u < kRcChunk; ++u)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[q][u], v[q][u], acc[q], 0, 0, 0);
+            for (int q = 0; q < R; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[q][u], v[q][u], acc[q], 0, 0, 0);
     }
-    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    if constexpr (R == 4) return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    else if constexpr (R == 2) return acc[0] + acc[1];
+    else return acc[0];
 }
 
 // Broadcast of lane `src`'s double (src uniform) through two scalar reads.
@@ -275,6 +280,94 @@ __device__ inline int decide_elim(const double *G, int ld, int K, double tau, in
 }
 
 // ---------------------------------------------------------------------------------------------
+// Re-check helpers (re-check and tail kernels)
+// ---------------------------------------------------------------------------------------------
+// Statistics of the re-checks a worker settled, written once per problem.
+struct RcStats {
+    int cur = -1;
+    long long rc = 0, rm = 0, viol = 0;
+    __device__ void flush(const Batch &b, int l) {
+        if (cur < 0) return;
+        Prob &Pc = b.probs[cur];
+        add_ll(&Pc.rechecks[l], rc);
+        if (rm) add_ll(&Pc.removed[l], rm);
+        if (viol) add_ll(&Pc.audit_viol[l], viol);
+        rc = rm = viol = 0;
+    }
+    __device__ void at(const Batch &b, int l, int prob) {
+        if (prob != cur) {
+            flush(b, l);
+            cur = prob;
+        }
+    }
+};
+
+// Statistics and removal of one re-checked test with FP64 decision res (one lane).
+__device__ inline void settle_recheck(const Batch &b, Prob &P, int l, int res, int i, int j, int cls, const int *S,
+                                      RcStats &rs) {
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    ++rs.rc;
+    if (b.force_recheck && cls != 2 && cls != res) ++rs.viol;
+    // The atomic on the canonical bit decides: an edge another test already removed stays
+    // removed and keeps that test's SepSet.
+    if (res && take_edge(P.adj, P.W, lo, hi)) {
+        ++rs.rm;
+        write_record(P, lo, hi, l, S);
+    }
+}
+
+// FP64 decision of the Gram block G by one wavefront (all lanes get it): the register elimination,
+// or, when M2 is numerically singular, the pseudo-inverse route on lane 0 with scratch `work`.
+template <int KMAX>
+__device__ inline int decide_wave(const double *G, int ld, int l, double tau, double *work, int mm, int lane) {
+    int res = decide_elim<KMAX>(G, ld, l + 2, tau, lane);
+    if (res < 0) {
+        if (lane == 0) res = decide_gram64(G, ld, l, tau, work, mm);
+        res = __shfl(res, 0, 64);
+    }
+    return res;
+}
+
+// Pairwise dot products of up to four FP64 standardized rows v[0..K) (levels 1 and 2, where the
+// 16 x 16 MFMA tile would be mostly zero rows): each lane takes two consecutive samples of every
+// block of 128 starting at x_first (blocks x_step apart) and returns its partial sums of the pairs
+// (0,1), (0,2), (1,2), (0,3), (1,3), (2,3) in s.
+__device__ inline void gram_small_part(const Prob &P, const int *v, int K, int lane, int64_t x_first, int64_t x_step,
+                                       double (&s)[6]) {
+    const int64_t mp = P.mp;
+    const double *z0 = P.zt64 + (int64_t)v[0] * mp, *z1 = P.zt64 + (int64_t)v[1] * mp;
+    const double *z2 = P.zt64 + (int64_t)v[K > 2 ? 2 : 0] * mp, *z3 = P.zt64 + (int64_t)v[K > 3 ? 3 : 0] * mp;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s[q] = 0.0;
+    // mp is a multiple of 64, so both samples of a lane are inside whenever the first is.
+#pragma unroll 2
+    for (int64_t x = x_first + 2 * lane; x < mp; x += x_step) {
+        const double2 a = *reinterpret_cast<const double2 *>(z0 + x);
+        const double2 c = *reinterpret_cast<const double2 *>(z1 + x);
+        const double2 e = K > 2 ? *reinterpret_cast<const double2 *>(z2 + x) : double2{0.0, 0.0};
+        const double2 g = K > 3 ? *reinterpret_cast<const double2 *>(z3 + x) : double2{0.0, 0.0};
+        s[0] = fma(a.y, c.y, fma(a.x, c.x, s[0]));
+        s[1] = fma(a.y, e.y, fma(a.x, e.x, s[1]));
+        s[2] = fma(c.y, e.y, fma(c.x, e.x, s[2]));
+        s[3] = fma(a.y, g.y, fma(a.x, g.x, s[3]));
+        s[4] = fma(c.y, g.y, fma(c.x, g.x, s[4]));
+        s[5] = fma(e.y, g.y, fma(e.x, g.x, s[5]));
+    }
+}
+
+// Writes the K x K Gram block (row stride 16, unit diagonal) from the pair sums of gram_small_part.
+__device__ inline void gram_small_store(const double (&s)[6], int K, double *G) {
+    const int pa[6] = {0, 0, 1, 0, 1, 2}, pb[6] = {1, 2, 2, 3, 3, 3};
+    for (int r = 0; r < K; ++r) G[r * 16 + r] = 1.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        if (pb[q] < K) {
+            G[pa[q] * 16 + pb[q]] = s[q];
+            G[pb[q] * 16 + pa[q]] = s[q];
+        }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Address-space-typed pointers
 // ---------------------------------------------------------------------------------------------
 // Accessors that pick LDS or global memory at run time would otherwise be merged by the compiler
@@ -308,6 +401,17 @@ struct TableBinom {
     }
 };
 
+// The same table staged in LDS for one row: C(a, b) for a <= d, b <= L, row stride `cols`. An
+// unranking is a chain of dependent table reads, so each read costs LDS latency instead of L2's.
+struct LdsBinom {
+    lds_ptr<const unsigned long long> t;
+    int cols;
+    __device__ unsigned long long operator()(int a, int b) const {
+        if (b < 0 || a < b) return 0ull;
+        return t[a * cols + b];
+    }
+};
+
 template <typename T>
 __host__ __device__ constexpr size_t lds_fixed_bytes() {
     return (sizeof(int) * kDcap + 15) / 16 * 16 + (sizeof(T) * kDcap + 15) / 16 * 16 +
@@ -319,6 +423,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long s_grow, s_item;
     __shared__ int s_mode;  // bit 0: nb/ci in LDS, bit 1: C[N_i,N_i] in LDS, bit 2: live bits in LDS
+    __shared__ int s_binoff;  // byte offset of the row's binomials in the dynamic LDS, or -1
     __shared__ long long s_tests, s_removed;
     // Removals found while testing are staged here and settled at the end of the item, so a
     // wavefront never waits on a device-scope atomic inside the test loop.
@@ -330,8 +435,9 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
     __shared__ long long s_scan[kLevelThreads / 64];
 
     DevState *st = b.st;
-    if (st->done) return;
+    const int done = st->done;
     const unsigned long long total = st->total_items;
+    if (done) return;
     const int tid = threadIdx.x;
     // Typed LDS pointers: every access below compiles to a ds_* instruction, never a flat one.
     const lds_ptr<int> lds_nb = (lds_ptr<int>)(smem);
@@ -353,9 +459,13 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         if (tid < 64) {
             // Wave 0 takes the next item and finds its row: the largest r with item_off[r] <= g,
             // by 64-way probing (each round narrows the range 64-fold with one load per lane).
-            // The first item of a work-group is its own index; later ones come from the queue.
+            // The first item of a work-group is its own index; later ones come from the queue
+            // (which has none when every item had a work-group of its own).
             unsigned long long g = blockIdx.x;
-            if (!first && tid == 0) g = gridDim.x + atomicAdd(&st->next_item, 1ull);
+            if (!first) {
+                if (total <= gridDim.x) g = total;
+                else if (tid == 0) g = gridDim.x + atomicAdd(&st->next_item, 1ull);
+            }
             g = __shfl(g, 0, 64);
             if (g >= total) {
                 if (tid == 0) s_grow = -1;
@@ -402,6 +512,18 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                     lds_nb[p] = k;
                     lds_ci[p] = C[(int64_t)row * n + k];
                 }
+            if constexpr (L >= 2) {
+                // The binomials this row's unranking reads, after the block when they fit.
+                const long long off = (long long)lds_fixed_bytes<T>() +
+                                      (blk_lds ? ((long long)d * d * (long long)sizeof(T) + 7) / 8 * 8 : 0);
+                const int nbin = (d + 1) * (L + 1);
+                const bool bin_lds = nb_lds && off + 8ll * nbin <= (long long)lds_bytes;
+                if (bin_lds) {
+                    const lds_ptr<unsigned long long> lb = (lds_ptr<unsigned long long>)(smem + off);
+                    for (int e = tid; e < nbin; e += kLevelThreads) lb[e] = binom(e / (L + 1), e % (L + 1));
+                }
+                if (tid == 0) s_binoff = bin_lds ? (int)off : -1;
+            }
             __syncthreads();
             if (blk_lds) {
                 // C[N_i, N_i]: each thread issues 8 independent gathers before storing any.
@@ -480,9 +602,16 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         const long long my_end = my_t + qn < r1 ? my_t + qn : r1;
         int since_refresh = 0;
 
+        int binoff = -1;
+        if constexpr (L >= 2) binoff = __builtin_amdgcn_readfirstlane(s_binoff);
+        const LdsBinom lbinom{(lds_ptr<const unsigned long long>)(smem + (binoff > 0 ? binoff : 0)), L + 1};
         int P_[L];
 #pragma unroll
         for (int c = 0; c < L; ++c) P_[c] = 0;
+        if (my_t < my_end) {
+            if (binoff > 0) comb_unrank<L>(d, (unsigned long long)my_t, P_, lbinom);
+            else comb_unrank<L>(d, (unsigned long long)my_t, P_, binom);
+        }
         // The set loop, specialised on where the row's data sits: K = 7 all of it in LDS, K = 5 all
         // but the block C[N_i, N_i] (gathered from global C), K = 0 any mix (decided per access). In
         // the specialised forms every load of a set is branch-free, so the compiler issues them
@@ -521,8 +650,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
             for (int step = 0; step < qn; ++step) {
                 const long long t = my_t + step;
                 if (t >= my_end) break;
-                if (step == 0) comb_unrank<L>(d, (unsigned long long)t, P_, binom);
-                else comb_next<L>(d, P_);
+                if (step > 0) comb_next<L>(d, P_);
 
                 // Shared per-S work: Cholesky of M2 = C[S,S], y = L^-1 C[S,i]^T, H11 = 1 - y.y.
                 SetFactor<T, L> f;
@@ -627,7 +755,8 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                 const long long k = (long long)(s_rec_base + (unsigned long long)myslot);
                 if (k < P.rec_cap) {
                     int Q[L];
-                    comb_unrank<L>(d, srank, Q, binom);
+                    if (binoff > 0) comb_unrank<L>(d, srank, Q, lbinom);
+                    else comb_unrank<L>(d, srank, Q, binom);
                     int qs[L];
 #pragma unroll
                     for (int c = 0; c < L; ++c) qs[c] = (mode & 1) ? lds_nb[Q[c]] : nbg[Q[c]];
@@ -677,8 +806,9 @@ __global__ __launch_bounds__(kLevelThreads) void k_level_deep(Batch b, int R) {
     __shared__ double s_M[kDeepWaves][L][L + 1];
 
     DevState *st = b.st;
-    if (st->done) return;
+    const int done = st->done;
     const unsigned long long total = st->total_items;
+    if (done) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const TableBinom binom{b.binom};
     if (tid == 0) { s_tests = 0; s_removed = 0; }
@@ -694,7 +824,10 @@ __global__ __launch_bounds__(kLevelThreads) void k_level_deep(Batch b, int R) {
         __syncthreads();
         if (tid < 64) {
             unsigned long long g = blockIdx.x;
-            if (!first && tid == 0) g = gridDim.x + atomicAdd(&st->next_item, 1ull);
+            if (!first) {
+                if (total <= gridDim.x) g = total;
+                else if (tid == 0) g = gridDim.x + atomicAdd(&st->next_item, 1ull);
+            }
             g = __shfl(g, 0, 64);
             if (g >= total) {
                 if (tid == 0) s_grow = -1;

@@ -109,8 +109,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level, int w
     }
     if (window) return;   // a window of a planned level: its statistics and stop flag stand
     __syncthreads();
+    // Levels the tail kernel already ran keep the statistics it recorded.
     for (int d = tid; d < b.count; d += kPlanThreads)
-        b.probs[d].items[level] = b.item_off[b.row_base[d + 1]] - b.item_off[b.row_base[d]];
+        if (level > b.probs[d].tail_done)
+            b.probs[d].items[level] = b.item_off[b.row_base[d + 1]] - b.item_off[b.row_base[d]];
     // Max degree of G' per problem (what the stop rule of Algorithm 1 looks at). Each thread scans
     // its chunk of rows segment by segment; segment maxima meet in LDS (one slot per problem) when
     // the batch is small enough, so no global address sees more than one write per problem.
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level, int w
             while (k >= b.row_base[d + 1]) {
                 if (best > 0) {
                     if (in_lds) atomicMax(&s_maxdeg[d], best);
-                    else atomicMax(&b.probs[d].maxdeg[level], best);
+                    else if (level > b.probs[d].tail_done) atomicMax(&b.probs[d].maxdeg[level], best);
                 }
                 best = 0;
                 ++d;
@@ -136,12 +138,13 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level, int w
         }
         if (best > 0) {
             if (in_lds) atomicMax(&s_maxdeg[d], best);
-            else atomicMax(&b.probs[d].maxdeg[level], best);
+            else if (level > b.probs[d].tail_done) atomicMax(&b.probs[d].maxdeg[level], best);
         }
     }
     if (in_lds) {
         __syncthreads();
-        for (int d = tid; d < b.count; d += kPlanThreads) b.probs[d].maxdeg[level] = s_maxdeg[d];
+        for (int d = tid; d < b.count; d += kPlanThreads)
+            if (level > b.probs[d].tail_done) b.probs[d].maxdeg[level] = s_maxdeg[d];
     }
 }
 

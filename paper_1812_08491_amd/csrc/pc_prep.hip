@@ -56,6 +56,8 @@ __global__ __launch_bounds__(256) void k_init(Batch b) {
     }
     if (tid == 0) {
         p.err = 0;
+        p.tail_next = 0;
+        p.tail_done = 0;
         if (p.rec_count) *p.rec_count = 0;
     }
 }

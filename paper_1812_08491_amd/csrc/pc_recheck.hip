@@ -9,91 +9,6 @@ namespace pcg {
 // ---------------------------------------------------------------------------------------------
 constexpr int kRcThreads = 256;            // re-check work-group: 4 wavefronts per queued test
 
-// Statistics of the re-checks a worker settled, written once per problem.
-struct RcStats {
-    int cur = -1;
-    long long rc = 0, rm = 0, viol = 0;
-    __device__ void flush(const Batch &b, int l) {
-        if (cur < 0) return;
-        Prob &Pc = b.probs[cur];
-        add_ll(&Pc.rechecks[l], rc);
-        if (rm) add_ll(&Pc.removed[l], rm);
-        if (viol) add_ll(&Pc.audit_viol[l], viol);
-        rc = rm = viol = 0;
-    }
-    __device__ void at(const Batch &b, int l, int prob) {
-        if (prob != cur) {
-            flush(b, l);
-            cur = prob;
-        }
-    }
-};
-
-// Statistics and removal of one re-checked test with FP64 decision res (one lane).
-__device__ inline void settle_recheck(const Batch &b, Prob &P, int l, int res, int i, int j, int cls, const int *S,
-                                      RcStats &rs) {
-    const int lo = i < j ? i : j, hi = i < j ? j : i;
-    ++rs.rc;
-    if (b.force_recheck && cls != 2 && cls != res) ++rs.viol;
-    // The atomic on the canonical bit decides: an edge another test already removed stays
-    // removed and keeps that test's SepSet.
-    if (res && take_edge(P.adj, P.W, lo, hi)) {
-        ++rs.rm;
-        write_record(P, lo, hi, l, S);
-    }
-}
-
-// FP64 decision of the Gram block G by one wavefront (all lanes get it): the register elimination,
-// or, when M2 is numerically singular, the pseudo-inverse route on lane 0 with scratch `work`.
-template <int KMAX>
-__device__ inline int decide_wave(const double *G, int ld, int l, double tau, double *work, int mm, int lane) {
-    int res = decide_elim<KMAX>(G, ld, l + 2, tau, lane);
-    if (res < 0) {
-        if (lane == 0) res = decide_gram64(G, ld, l, tau, work, mm);
-        res = __shfl(res, 0, 64);
-    }
-    return res;
-}
-
-// Pairwise dot products of up to four FP64 standardized rows v[0..K) (levels 1 and 2, where the
-// 16 x 16 MFMA tile would be mostly zero rows): each lane takes two consecutive samples of every
-// block of 128 starting at x_first (blocks x_step apart) and returns its partial sums of the pairs
-// (0,1), (0,2), (1,2), (0,3), (1,3), (2,3) in s.
-__device__ inline void gram_small_part(const Prob &P, const int *v, int K, int lane, int64_t x_first, int64_t x_step,
-                                       double (&s)[6]) {
-    const int64_t mp = P.mp;
-    const double *z0 = P.zt64 + (int64_t)v[0] * mp, *z1 = P.zt64 + (int64_t)v[1] * mp;
-    const double *z2 = P.zt64 + (int64_t)v[K > 2 ? 2 : 0] * mp, *z3 = P.zt64 + (int64_t)v[K > 3 ? 3 : 0] * mp;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) s[q] = 0.0;
-    // mp is a multiple of 64, so both samples of a lane are inside whenever the first is.
-#pragma unroll 2
-    for (int64_t x = x_first + 2 * lane; x < mp; x += x_step) {
-        const double2 a = *reinterpret_cast<const double2 *>(z0 + x);
-        const double2 c = *reinterpret_cast<const double2 *>(z1 + x);
-        const double2 e = K > 2 ? *reinterpret_cast<const double2 *>(z2 + x) : double2{0.0, 0.0};
-        const double2 g = K > 3 ? *reinterpret_cast<const double2 *>(z3 + x) : double2{0.0, 0.0};
-        s[0] = fma(a.y, c.y, fma(a.x, c.x, s[0]));
-        s[1] = fma(a.y, e.y, fma(a.x, e.x, s[1]));
-        s[2] = fma(c.y, e.y, fma(c.x, e.x, s[2]));
-        s[3] = fma(a.y, g.y, fma(a.x, g.x, s[3]));
-        s[4] = fma(c.y, g.y, fma(c.x, g.x, s[4]));
-        s[5] = fma(e.y, g.y, fma(e.x, g.x, s[5]));
-    }
-}
-
-// Writes the K x K Gram block (row stride 16, unit diagonal) from the pair sums of gram_small_part.
-__device__ inline void gram_small_store(const double (&s)[6], int K, double *G) {
-    const int pa[6] = {0, 0, 1, 0, 1, 2}, pb[6] = {1, 2, 2, 3, 3, 3};
-    for (int r = 0; r < K; ++r) G[r * 16 + r] = 1.0;
-#pragma unroll
-    for (int q = 0; q < 6; ++q)
-        if (pb[q] < K) {
-            G[pa[q] * 16 + pb[q]] = s[q];
-            G[pb[q] * 16 + pa[q]] = s[q];
-        }
-}
-
 // Queued tests of levels up to 14 (at most 16 variables). The FP64 Gram block of the standardized
 // rows (i, j, S) is one 16 x 16 tile Z Z^T (gram_part); rows past l + 2 stay zero. On the FP64 path
 // the block is read from C. With few queued tests a work-group takes each one and its four
@@ -280,6 +195,12 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_deep(Batch b, int level)
         __syncthreads();
     }
     if (tid == 0) rs.flush(b, l);
+}
+
+int recheck_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_recheck, kRcThreads, 0) != hipSuccess) return 0;
+    return nb;
 }
 
 hipError_t launch_recheck(hipStream_t s, const Batch &b, int level, int grid) {

@@ -234,6 +234,25 @@ def test_skeleton_rows_beyond_lds_capacity(prec, opt):
     assert st["tests"][1] >= 604450 - 1100
 
 
+@pytest.mark.parametrize("prec,tail_tests", [("fp32", -1), ("fp32", 1), ("fp32", 1 << 24), ("bf16x3", 1 << 24),
+                                             ("fp64", 1 << 24)])
+def test_skeleton_tail_kernel_modes(prec, tail_tests):
+    """The small levels in one work-group per problem: off (-1), handed back at once (1), or every
+    level up to 8 from level 2 on (a budget above any level's test count here)."""
+    X, sem, alpha = semgen.workload("n1000_d4_m500_fp32")
+    print(f"tail modes prec={prec} tail_tests={tail_tests}", flush=True)
+    st, ref = compare_with_oracle(X, alpha, prec, tail_tests=tail_tests)
+    assert st["tests"][0] == 1000 * 999 // 2
+
+
+def test_skeleton_tail_with_rechecks_and_max_level():
+    """The tail's FP64 re-checks (audit-free band tests of BF16x3) and a level cap inside it."""
+    X = sem_data(19, 300, 0.04, 400)
+    for ml in (-1, 3):
+        print(f"tail recheck max_level={ml}", flush=True)
+        st, ref = compare_with_oracle(X, 0.05, "bf16x3", max_level=ml, tail_tests=1 << 24)
+
+
 def test_skeleton_sample_limit_warning():
     X = sem_data(5, 12, 0.9, 7)
     compare_with_oracle(X, 0.5, "fp64")
