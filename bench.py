@@ -40,7 +40,7 @@ PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_level1_n1000_d4_m500.json")
 ROW_TOP = 2   # candidates per node the learned order tests first at level 1
-TAIL_TESTS = 16384    # levels with more CI tests than this run as level kernels in the graph
+TAIL_TESTS = 2048     # levels with more CI tests than this run as level kernels in the graph
 TAIL_MAX_LEVEL = 8    # deepest level the tail kernel runs
 LEVEL_SOURCES = ["paper_1812_08491_amd/csrc/pc_level.h", "paper_1812_08491_amd/csrc/pc_level_f32.hip",
                  "paper_1812_08491_amd/csrc/pc_citest.h", "paper_1812_08491_amd/csrc/pc_dev.h",

@@ -82,12 +82,14 @@ typedef struct {
                                   stream in pc_graph_results. */
     int32_t tests_per_lane;    /* levels up to 13: rows with long neighbour lists get work items of
                                   fewer conditioning sets, so one lane runs about this many CI
-                                  tests per item (0 = automatic, 128) */
-    int32_t tail_tests;        /* once a level of a problem (level >= 2, <= 8) has at most this many
-                                  CI tests (bounded by sum C(d_i, l)(d_i - l)), that level and the
-                                  following ones run in one work-group per problem instead of four
-                                  launches per level (0 = automatic, 16384; -1 = never). Not used
-                                  with force_recheck_all or a per-edge ordering model. */
+                                  tests per item (0 = automatic: 32 when every problem of the call
+                                  has n <= 1024, else 128) */
+    int32_t tail_tests;        /* > 0: once a level of a problem (level >= 2, <= 8) has at most this
+                                  many CI tests (bounded by sum C(d_i, l)(d_i - l)), that level and
+                                  the following ones run in one work-group per problem instead of
+                                  four launches per level; in a captured graph the tail kernel runs
+                                  after the graph_levels recorded levels. 0 (default) = never. Not
+                                  used with force_recheck_all or a per-edge ordering model. */
 } pc_options;
 
 /* One SepSet record, written for every edge removed at a level >= 1 (Algorithm 1: "store S").

@@ -58,7 +58,12 @@ struct pc_graph {
 namespace {
 
 constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24, unit roundoff of FP32
-constexpr int kAutoLaneTests = 128;               // default bound on CI tests per lane and item
+// Default bound on the CI tests of a lane per work item. Small problems have few heavy rows, and a
+// level's launch lasts as long as its heaviest item, so their heavy rows are cut finer; large ones
+// have many more items than work-groups already, and finer items only repeat the row staging.
+constexpr int kAutoLaneTests = 128;
+constexpr int kAutoLaneTestsSmall = 32;             // when every problem has n <= kSmallN
+constexpr int64_t kSmallN = 1024;
 
 #define PC_HIP(call)                                                       \
     do {                                                                   \
@@ -102,13 +107,13 @@ int64_t rq_cap_of(const pc_options &o, double sum_n2) {
 
 int graph_levels_of(const pc_options &o) { return o.graph_levels > 0 ? o.graph_levels : 10; }
 
-constexpr long long kAutoTailTests = 16384;
 constexpr int kTailMaxLevel = 8;   // the tail kernel's deepest level (its register budget)
 
-// Test budget of the tail kernel (0: not used).
+// Test budget of the tail kernel (0: not used). It is opt-in: one work-group per problem beats the
+// level kernels only on the last few levels of a run, which the caller can tell from a first run.
 long long tail_cap(const pc_options &o) {
-    if (o.tail_tests < 0 || o.force_recheck_all) return 0;
-    return o.tail_tests == 0 ? kAutoTailTests : std::min<long long>(o.tail_tests, 1ll << 30);
+    if (o.tail_tests <= 0 || o.force_recheck_all) return 0;
+    return std::min<long long>(o.tail_tests, 1ll << 30);
 }
 
 // Standard normal CDF from erfc, and its inverse by Halley's method started from the rational
@@ -278,7 +283,8 @@ Batch make_batch(const pc_ctx *ctx, const Plan &L, unsigned char *ws) {
     b.count = L.count;
     b.prec = L.prec;
     b.force_recheck = L.prec != PC_PREC_FP64 && ctx->opt.force_recheck_all;
-    b.lane_tests = ctx->opt.tests_per_lane > 0 ? ctx->opt.tests_per_lane : kAutoLaneTests;
+    b.lane_tests = ctx->opt.tests_per_lane > 0 ? ctx->opt.tests_per_lane
+                                               : (L.max_n <= kSmallN ? kAutoLaneTestsSmall : kAutoLaneTests);
     const long long *bases = reinterpret_cast<const long long *>(ws + L.table + sizeof(Prob) * L.count);
     b.row_base = bases;
     b.cs_base = bases + (L.count + 1);
@@ -371,7 +377,7 @@ pc_status enqueue_corr(pc_ctx *ctx, const Batch &b, const Plan &L, bool capturin
     PC_HIP(launch_standardize(s, b, L.st_blocks));
     if (timed(ctx, 16, capturing)) PC_HIP(hipEventRecord(ctx->ev_prep[1], s));
     if (timed(ctx, 1, capturing)) PC_HIP(hipEventRecord(ctx->ev_corr[0], s));
-    PC_HIP(launch_corr(s, b, L.tiles));
+    PC_HIP(launch_corr(s, b, L.tiles, ctx->num_cu));
     if (timed(ctx, 1, capturing)) PC_HIP(hipEventRecord(ctx->ev_corr[1], s));
     return PC_OK;
 }

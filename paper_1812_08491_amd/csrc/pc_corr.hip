@@ -202,7 +202,10 @@ __device__ inline void mma_step(const Smem<PREC> &sm, typename Tr<PREC>::acc_t (
     }
 }
 
-template <int PREC>
+// PF: K blocks staged per barrier. PF = 1 double-buffers single blocks (several work-groups per
+// CU hide the load latency); PF > 1 stages 64 samples at a time, for launches with few tiles (or
+// BF16x3), where one work-group per CU has to cover the latency by itself.
+template <int PREC, int PF>
 __global__ __launch_bounds__(256) void k_corr(Batch bt) {
     using T = typename Tr<PREC>::T;
     using acc_t = typename Tr<PREC>::acc_t;
@@ -228,7 +231,9 @@ __global__ __launch_bounds__(256) void k_corr(Batch bt) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
 
-    __shared__ Smem<PREC> sm[2];   // double buffer: block k + 1 is staged while block k is multiplied
+    constexpr int kPF = PF;
+    static_assert(PF == 1 || PF * BK == 64, "groups of blocks span 64 samples");
+    __shared__ Smem<PREC> sm[PF == 1 ? 2 : PF];
     __shared__ unsigned long long rowbits[kT], colbits[kT];
     __shared__ unsigned int blist[kT * kT];
     __shared__ int bcount;
@@ -247,15 +252,7 @@ __global__ __launch_bounds__(256) void k_corr(Batch bt) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[mi][nj][v] = sum[mi][nj][v] = cmp[mi][nj][v] = 0;
 
-    Frag<PREC> frag;
-    fetch_tiles<PREC>(frag, ops, a0, b0, 0, tid);
-    stage_tiles<PREC>(sm[0], frag, tid);
-    __syncthreads();
-    int cur = 0;
-    for (int64_t k0 = 0; k0 < a.mp; k0 += BK) {
-        const bool more = k0 + BK < a.mp;
-        if (more) fetch_tiles<PREC>(frag, ops, a0, b0, k0 + BK, tid);
-        mma_step<PREC>(sm[cur], acc, lane, wr, wc);
+    auto compensate = [&]() {
         if constexpr (PREC != PC_PREC_FP64) {
 #pragma unroll
             for (int mi = 0; mi < 2; ++mi)
@@ -270,9 +267,48 @@ __global__ __launch_bounds__(256) void k_corr(Batch bt) {
                         acc[mi][nj][v] = 0.0f;
                     }
         }
-        if (more) stage_tiles<PREC>(sm[cur ^ 1], frag, tid);
+    };
+    if constexpr (PF == 1) {
+        // Double buffer: block k + 1 is loaded and staged while block k is multiplied.
+        Frag<PREC> frag;
+        fetch_tiles<PREC>(frag, ops, a0, b0, 0, tid);
+        stage_tiles<PREC>(sm[0], frag, tid);
         __syncthreads();
-        cur ^= 1;
+        int cur = 0;
+        for (int64_t k0 = 0; k0 < a.mp; k0 += BK) {
+            const bool more = k0 + BK < a.mp;
+            if (more) fetch_tiles<PREC>(frag, ops, a0, b0, k0 + BK, tid);
+            mma_step<PREC>(sm[cur], acc, lane, wr, wc);
+            compensate();
+            if (more) stage_tiles<PREC>(sm[cur ^ 1], frag, tid);
+            __syncthreads();
+            cur ^= 1;
+        }
+    } else {
+        // mp is a multiple of 64, so every group of kPF blocks is whole.
+        Frag<PREC> frag[kPF];
+#pragma unroll
+        for (int j = 0; j < kPF; ++j) fetch_tiles<PREC>(frag[j], ops, a0, b0, (int64_t)j * BK, tid);
+#pragma unroll
+        for (int j = 0; j < kPF; ++j) stage_tiles<PREC>(sm[j], frag[j], tid);
+        __syncthreads();
+        for (int64_t k0 = 0; k0 < a.mp; k0 += kPF * BK) {
+            const bool more = k0 + kPF * BK < a.mp;
+            if (more)
+#pragma unroll
+                for (int j = 0; j < kPF; ++j) fetch_tiles<PREC>(frag[j], ops, a0, b0, k0 + (int64_t)(kPF + j) * BK, tid);
+#pragma unroll
+            for (int j = 0; j < kPF; ++j) {
+                mma_step<PREC>(sm[j], acc, lane, wr, wc);
+                compensate();
+            }
+            __syncthreads();   // every wavefront is done with this group's LDS tiles
+            if (more) {
+#pragma unroll
+                for (int j = 0; j < kPF; ++j) stage_tiles<PREC>(sm[j], frag[j], tid);
+            }
+            __syncthreads();
+        }
     }
     if constexpr (PREC != PC_PREC_FP64) {
 #pragma unroll
@@ -374,14 +410,20 @@ __global__ __launch_bounds__(256) void k_corr(Batch bt) {
     }
 }
 
-hipError_t launch_corr(hipStream_t s, const Batch &b, long long tiles) {
+// Deep staging (64 samples per barrier) when the tiles do not fill the CUs, or on BF16x3, whose
+// three products per block keep a CU busy long enough to cover the loads of the next group.
+hipError_t launch_corr(hipStream_t s, const Batch &b, long long tiles, int num_cu) {
     const dim3 grid((unsigned)tiles);
-    if (b.prec == PC_PREC_FP64)
-        hipLaunchKernelGGL(k_corr<PC_PREC_FP64>, grid, dim3(256), 0, s, b);
-    else if (b.prec == PC_PREC_FP32)
-        hipLaunchKernelGGL(k_corr<PC_PREC_FP32>, grid, dim3(256), 0, s, b);
-    else
-        hipLaunchKernelGGL(k_corr<PC_PREC_BF16X3>, grid, dim3(256), 0, s, b);
+    const bool deep = tiles <= num_cu;
+    if (b.prec == PC_PREC_FP64) {
+        if (deep) hipLaunchKernelGGL((k_corr<PC_PREC_FP64, 4>), grid, dim3(256), 0, s, b);
+        else hipLaunchKernelGGL((k_corr<PC_PREC_FP64, 1>), grid, dim3(256), 0, s, b);
+    } else if (b.prec == PC_PREC_FP32) {
+        if (deep) hipLaunchKernelGGL((k_corr<PC_PREC_FP32, 4>), grid, dim3(256), 0, s, b);
+        else hipLaunchKernelGGL((k_corr<PC_PREC_FP32, 1>), grid, dim3(256), 0, s, b);
+    } else {
+        hipLaunchKernelGGL((k_corr<PC_PREC_BF16X3, 2>), grid, dim3(256), 0, s, b);
+    }
     return hipGetLastError();
 }
 

@@ -178,7 +178,7 @@ hipError_t launch_colstats(hipStream_t s, const Batch &b, long long blocks);
 hipError_t launch_standardize(hipStream_t s, const Batch &b, long long blocks);
 
 // pc_corr.hip
-hipError_t launch_corr(hipStream_t s, const Batch &b, long long tiles);
+hipError_t launch_corr(hipStream_t s, const Batch &b, long long tiles, int num_cu);
 
 // pc_level.hip
 hipError_t launch_compact(hipStream_t s, const Batch &b, int level, int ranks_per_item);

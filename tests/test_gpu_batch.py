@@ -122,12 +122,12 @@ def test_batch_reports_per_dataset_errors():
     check_one(*batch[2], items[2], status[2])
 
 
-@pytest.mark.parametrize("tail_tests", [0, -1, 1, 1 << 20])
+@pytest.mark.parametrize("tail_tests", [0, 1, 2048, 1 << 20])
 def test_graph_continues_past_recorded_levels(tail_tests):
     """A graph that records only 2 levels still yields whole skeletons: the tail kernel recorded
-    after them runs the small levels (tail_tests 0: default budget, 1 << 20: nearly all of them;
-    -1: no tail), and pc_graph_results runs whatever the datasets still need on the stream (with
-    tail_tests = 1 the tail hands every level back at once), on every replay."""
+    after them runs the small levels (budget 2048 tests, or 1 << 20: every level up to 8; 0: no
+    tail), and pc_graph_results runs whatever the datasets still need on the stream (with budget 1
+    the tail hands every level back at once), on every replay."""
     batch = uneven_batch(6, seed=91, nmax=160)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):

@@ -234,11 +234,12 @@ def test_skeleton_rows_beyond_lds_capacity(prec, opt):
     assert st["tests"][1] >= 604450 - 1100
 
 
-@pytest.mark.parametrize("prec,tail_tests", [("fp32", -1), ("fp32", 1), ("fp32", 1 << 24), ("bf16x3", 1 << 24),
+@pytest.mark.parametrize("prec,tail_tests", [("fp32", 2048), ("fp32", 1), ("fp32", 1 << 24), ("bf16x3", 1 << 24),
                                              ("fp64", 1 << 24)])
 def test_skeleton_tail_kernel_modes(prec, tail_tests):
-    """The small levels in one work-group per problem: off (-1), handed back at once (1), or every
-    level up to 8 from level 2 on (a budget above any level's test count here)."""
+    """The small levels in one work-group per problem: from the first small level the stream run
+    looks at (2048), handed back at once (1), or every level up to 8 from level 2 on (a budget
+    above any level's test count here)."""
     X, sem, alpha = semgen.workload("n1000_d4_m500_fp32")
     print(f"tail modes prec={prec} tail_tests={tail_tests}", flush=True)
     st, ref = compare_with_oracle(X, alpha, prec, tail_tests=tail_tests)
