@@ -58,12 +58,13 @@ struct pc_graph {
 namespace {
 
 constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24, unit roundoff of FP32
-// Default bound on the CI tests of a lane per work item. Small problems have few heavy rows, and a
-// level's launch lasts as long as its heaviest item, so their heavy rows are cut finer; large ones
-// have many more items than work-groups already, and finer items only repeat the row staging.
+// Default bound on the CI tests of a lane per work item. A call with few rows has few heavy rows,
+// and a level's launch lasts as long as its heaviest item, so they are cut finer; with many rows
+// (large problems, or batches) items already outnumber work-groups, and finer items only repeat
+// the row staging.
 constexpr int kAutoLaneTests = 128;
-constexpr int kAutoLaneTestsSmall = 32;             // when every problem has n <= kSmallN
-constexpr int64_t kSmallN = 1024;
+constexpr int kAutoLaneTestsSmall = 32;             // when the call has at most kSmallRows rows
+constexpr int64_t kSmallRows = 2048;
 
 #define PC_HIP(call)                                                       \
     do {                                                                   \
@@ -284,7 +285,7 @@ Batch make_batch(const pc_ctx *ctx, const Plan &L, unsigned char *ws) {
     b.prec = L.prec;
     b.force_recheck = L.prec != PC_PREC_FP64 && ctx->opt.force_recheck_all;
     b.lane_tests = ctx->opt.tests_per_lane > 0 ? ctx->opt.tests_per_lane
-                                               : (L.max_n <= kSmallN ? kAutoLaneTestsSmall : kAutoLaneTests);
+                                               : (L.total_rows <= kSmallRows ? kAutoLaneTestsSmall : kAutoLaneTests);
     const long long *bases = reinterpret_cast<const long long *>(ws + L.table + sizeof(Prob) * L.count);
     b.row_base = bases;
     b.cs_base = bases + (L.count + 1);
