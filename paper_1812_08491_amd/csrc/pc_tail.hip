@@ -24,9 +24,10 @@ namespace pcg {
 constexpr int kTailThreads = 512;
 constexpr int kTailWaves = kTailThreads / 64;
 constexpr int kTailRows = 1024;   // rows that can still be tested, held in LDS
-constexpr int kTailBin = 1024;    // binomials C(a, b), a <= max degree, b <= l, staged per level
+constexpr int kTailBin = 1024;    // binomials C(a, b), a <= max degree, b <= kTailMaxLevel + 1, in LDS
 constexpr int kTailRcWaves = 4;   // wavefronts that run the FP64 re-checks
 constexpr int kTailMaxLevel = 8;  // deeper levels go back to the level kernels (register budget)
+constexpr int kTailBinCols = kTailMaxLevel + 2;
 
 struct TailSmem {
     int rows[kTailRows];              // rows of G' with degree >= l + 1 (ascending)
@@ -37,7 +38,7 @@ struct TailSmem {
     double work[kTailRcWaves][kWorks];
     int v[kTailRcWaves][16];
     long long scan_a[kTailWaves], scan_b[kTailWaves];
-    int nrows, nnew, maxdeg, nrq;
+    int nrows, nnew, maxdeg, nrq, md0;
     unsigned sets;
     unsigned long long bound;
 };
@@ -64,7 +65,7 @@ __device__ void tail_tests(const Batch &b, Prob &P, int pd, TailSmem &sm, RqEntr
     const double tau = P.tau[L];
     const float tl = P.t[L], band = P.band[L];
     const TableBinom gbin{b.binom};
-    const LdsBinom lbin{(lds_ptr<const unsigned long long>)sm.bin, L + 1};
+    const LdsBinom lbin{(lds_ptr<const unsigned long long>)sm.bin, kTailBinCols};
     int split = 1;
     while (split < 64 && (unsigned long long)split * 2 * total <= kTailThreads) split *= 2;
     const int slice = tid % split, groups = kTailThreads / split;
@@ -219,11 +220,17 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(Batch b, int level0, long
     RqEntry *rq = b.rq + (long long)pd * rq_share;
 
     // Rows that can still be tested at level0: degree >= level0 + 1 in the last snapshot.
-    if (tid == 0) sm.nrows = 0;
+    if (tid == 0) {
+        sm.nrows = 0;
+        sm.md0 = 0;
+    }
     __syncthreads();
+    int dmax = 0;
     for (int r0 = 0; r0 < n; r0 += kTailThreads) {
         const int r = r0 + tid;
-        const bool f = r < n && P.deg[r] >= level0 + 1;
+        const int dr = r < n ? P.deg[r] : 0;
+        const bool f = dr >= level0 + 1;
+        dmax = f && dr > dmax ? dr : dmax;
         long long tot = 0;
         const long long pre = block_exclusive_scan<kTailThreads>(f ? 1 : 0, sm.scan_a, tot);
         const int base = sm.nrows;
@@ -232,6 +239,21 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(Batch b, int level0, long
         if (tid == 0) sm.nrows = base + (int)tot;
         __syncthreads();
     }
+    for (int o = 32; o >= 1; o >>= 1) {
+        const int om = __shfl_xor(dmax, o, 64);
+        dmax = om > dmax ? om : dmax;
+    }
+    if (lane == 0) atomicMax(&sm.md0, dmax);
+    __syncthreads();
+    // Binomials of every unranking and count of the tail: degrees never exceed md0 again.
+    const int md0 = sm.md0;
+    const bool bin_lds = (md0 + 1) * kTailBinCols <= kTailBin;
+    if (bin_lds)
+        for (int e = tid; e < (md0 + 1) * kTailBinCols; e += kTailThreads)
+            sm.bin[e] = gbin(e / kTailBinCols, e % kTailBinCols);
+    __syncthreads();
+    const LdsBinom lbin{(lds_ptr<const unsigned long long>)sm.bin, kTailBinCols};
+    auto binom = [&](int a, int k) -> unsigned long long { return bin_lds ? lbin(a, k) : gbin(a, k); };
     int level = level0, stop = 0;   // stop: 1 finished, 2 left to the level kernels
     if (sm.nrows > kTailRows) stop = 2;
     while (!stop) {
@@ -252,12 +274,12 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(Batch b, int level0, long
             unsigned long long *arow = P.adj + (int64_t)r * W;
             int *out = P.nbr + (int64_t)r * n;
             int cnt = 0;
-            for (int64_t w0 = 0; w0 < W; w0 += 8) {
-                unsigned long long wd[8];
+            for (int64_t w0 = 0; w0 < W; w0 += 16) {
+                unsigned long long wd[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) wd[u] = w0 + u < W ? live_word(arow + w0 + u) : 0ull;
+                for (int u = 0; u < 16; ++u) wd[u] = w0 + u < W ? live_word(arow + w0 + u) : 0ull;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < 16; ++u) {
                     const int64_t w = w0 + u;
                     unsigned long long x = wd[u];
                     if (w == (r >> 6)) x &= ~(1ull << (r & 63));
@@ -274,7 +296,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(Batch b, int level0, long
             if (cnt >= level + 1) {
                 // tests of the row: C(d, l) sets of d - l candidates (saturating at 2^50 per thread)
                 constexpr unsigned long long kSatB = 1ull << 50;
-                const unsigned long long c = gbin(cnt, level);
+                const unsigned long long c = binom(cnt, level);
                 const unsigned long long t = c < (1ull << 30) ? c * (unsigned long long)(cnt - level) : kSatB;
                 mybound = mybound + t < kSatB ? mybound + t : kSatB;
             }
@@ -311,7 +333,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(Batch b, int level0, long
                 r = sm.rows[q];
                 dq = sm.deg[q];
                 f = dq >= level + 1;
-                ns = f ? gbin(dq, level) : 0;
+                ns = f ? binom(dq, level) : 0;
             }
             long long tot = 0, stot = 0;
             const long long pre = block_exclusive_scan<kTailThreads>(f ? 1 : 0, sm.scan_a, tot);
@@ -331,9 +353,6 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(Batch b, int level0, long
             }
             __syncthreads();
         }
-        const bool bin_lds = (md + 1) * (level + 1) <= kTailBin;
-        if (bin_lds)
-            for (int e = tid; e < (md + 1) * (level + 1); e += kTailThreads) sm.bin[e] = gbin(e / (level + 1), e % (level + 1));
         if (tid == 0) {
             sm.soff[sm.nnew] = sm.sets;
             P.items[level] = sm.sets;
