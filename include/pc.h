@@ -317,6 +317,26 @@ pc_status pc_mlp_bce(pc_ctx *ctx, const float *scores, const float *labels, int6
 pc_status pc_mlp_adam(pc_ctx *ctx, float *params, const float *grads, float *m1, float *m2, int step,
                       float lr, float beta1, float beta2, float eps);
 
+/* Orientation of a skeleton into a CPDAG: the step of the PC algorithm after the skeleton
+ * (Sec. 2.4), here on the GPU. Unshielded colliders i -> k <- j wherever k is not in SepSet(i, j),
+ * then Meek's rules R1-R3 in synchronous rounds until nothing changes. Conventions that make the
+ * result independent of the order of work: colliders are judged on the skeleton and SepSets
+ * alone, and an edge that receives arrowheads at both ends is bidirected; a round orients every
+ * undirected edge that a rule orients in the state at the start of the round, and an edge
+ * proposed both ways in the same round stays undirected.
+ *   adj     device n x ceil(n/64) u64 skeleton (symmetric, zero diagonal), not modified.
+ *   recs    device SepSet records of the level >= 1 removals (as pc_skeleton writes them), nrec of
+ *           them; a non-adjacent pair without a record has the empty SepSet (level 0). Records
+ *           with ids or levels out of range are ignored.
+ *   arrows  device n x ceil(n/64) u64, written: bit y of row x set iff the edge x - y has an
+ *           arrowhead at y (x -> y, or x <-> y when row y has bit x too).
+ *   ws      workspace of pc_orient_workspace_bytes(n) bytes, 256-byte aligned.
+ *   rounds  host (optional): propagation rounds that oriented at least one edge.
+ * Synchronises the stream once per round. */
+size_t pc_orient_workspace_bytes(int64_t n);
+pc_status pc_orient(pc_ctx *ctx, int64_t n, const uint64_t *adj, const pc_sep_rec *recs, int64_t nrec,
+                    uint64_t *arrows, void *ws, size_t ws_bytes, int32_t *rounds);
+
 /* Waits for the context's stream and reports device-detected input errors of pc_corr. */
 pc_status pc_sync_status(pc_ctx *ctx, void *ws, size_t ws_bytes);
 

@@ -167,6 +167,10 @@ def lib() -> ct.CDLL:
         L.pc_row_features.argtypes = [vp, ct.c_int, i64, i64, ct.c_double, vp, fp, fp, vp, i64, ct.POINTER(i64), vp,
                                       ct.c_size_t]
         L.pc_row_features.restype = ct.c_int
+        L.pc_orient_workspace_bytes.argtypes = [i64]
+        L.pc_orient_workspace_bytes.restype = ct.c_size_t
+        L.pc_orient.argtypes = [vp, i64, vp, vp, i64, vp, vp, ct.c_size_t, ct.POINTER(ct.c_int32)]
+        L.pc_orient.restype = ct.c_int
         L.pc_mlp_forward.argtypes = [vp, fp, fp, i64, fp, fp]
         L.pc_mlp_forward.restype = ct.c_int
         L.pc_mlp_backward.argtypes = [vp, fp, fp, i64, fp, fp, fp, fp]
@@ -189,7 +193,7 @@ EXPORTED = ["pc_create", "pc_destroy", "pc_default_options", "pc_workspace_bytes
             "pc_abi_size", "pc_status_str", "pc_batch_workspace_bytes", "pc_batch_skeleton",
             "pc_batch_capture", "pc_graph_launch", "pc_graph_results", "pc_graph_destroy",
             "pc_ordered_workspace_bytes", "pc_skeleton_ordered", "pc_features", "pc_row_features", "pc_mlp_forward",
-            "pc_mlp_backward", "pc_mlp_bce", "pc_mlp_adam"]
+            "pc_mlp_backward", "pc_mlp_bce", "pc_mlp_adam", "pc_orient_workspace_bytes", "pc_orient"]
 
 
 def _check_abi(L: ct.CDLL) -> None:
@@ -421,6 +425,28 @@ class Context:
             return -int(rows.value)
         _check(r, "pc_row_features")
         return int(rows.value)
+
+    def orient_workspace(self, n: int):
+        torch = _torch()
+        nbytes = int(lib().pc_orient_workspace_bytes(n))
+        if nbytes == 0:
+            raise PCError(PC_ERR_SHAPE, "pc_orient_workspace_bytes")
+        return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+    def pc_orient(self, n: int, adj, recs, nrec: int, arrows, ws) -> int:
+        """CPDAG arrowheads of a skeleton and its SepSet records (see include/pc.h); returns the
+        number of propagation rounds that oriented something."""
+        torch = _torch()
+        W = (n + 63) // 64
+        assert adj.is_cuda and adj.dtype == torch.int64 and adj.numel() == n * W
+        assert arrows.is_cuda and arrows.dtype == torch.int64 and arrows.numel() == n * W
+        assert nrec == 0 or (recs.is_cuda and recs.numel() * recs.element_size() >= nrec * ct.sizeof(pc_sep_rec))
+        rounds = ct.c_int32()
+        _check(lib().pc_orient(self.h, n, ct.c_void_p(adj.data_ptr()),
+                               ct.c_void_p(recs.data_ptr()) if nrec > 0 else None, nrec,
+                               ct.c_void_p(arrows.data_ptr()), ct.c_void_p(ws.data_ptr()), ws.numel(),
+                               ct.byref(rounds)), "pc_orient")
+        return int(rounds.value)
 
     @staticmethod
     def _mlp_shapes(params, X, **bufs):

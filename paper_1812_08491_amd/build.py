@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpc.so")
 # Longest compilations first: the level-kernel instances dominate the build.
 SOURCES = ["pc_level_deep.hip", "pc_level_f32.hip", "pc_level_f64.hip", "pc_recheck.hip", "pc_mlp.hip",
-           "pc_tail.hip", "pc_corr.hip", "pc_level.hip", "pc_prep.hip", "pc_api.cpp"]
+           "pc_tail.hip", "pc_orient.hip", "pc_corr.hip", "pc_level.hip", "pc_prep.hip", "pc_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I" + os.path.join(ROOT, "include"),

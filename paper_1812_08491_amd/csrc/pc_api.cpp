@@ -1127,6 +1127,50 @@ pc_status pc_mlp_adam(pc_ctx *ctx, float *params, const float *grads, float *m1,
     return PC_OK;
 }
 
+// Orientation workspace: IN, two proposal buffers (n x W words each), the SepSet index (n x n
+// int32) and the round counter.
+size_t orient_ws_bytes(int64_t n) {
+    const size_t bits = align256((size_t)n * (size_t)words_per_row(n) * sizeof(uint64_t));
+    return 3 * bits + align256((size_t)n * (size_t)n * sizeof(int)) + 256;
+}
+
+size_t pc_orient_workspace_bytes(int64_t n) {
+    if (check_shape(n, 4) != PC_OK) return 0;
+    return orient_ws_bytes(n);
+}
+
+pc_status pc_orient(pc_ctx *ctx, int64_t n, const uint64_t *adj, const pc_sep_rec *recs, int64_t nrec,
+                    uint64_t *arrows, void *ws, size_t ws_bytes, int32_t *rounds) {
+    if (!ctx || !adj || !arrows || !ws || nrec < 0 || (nrec > 0 && !recs)) return PC_ERR_INVALID_ARG;
+    pc_status st = check_shape(n, 4);
+    if (st != PC_OK) return st;
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return PC_ERR_INVALID_ARG;
+    if (ws_bytes < orient_ws_bytes(n)) return PC_ERR_WORKSPACE;
+    const size_t bits = align256((size_t)n * (size_t)words_per_row(n) * sizeof(uint64_t));
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    auto *IN = reinterpret_cast<unsigned long long *>(w);
+    auto *P0 = reinterpret_cast<unsigned long long *>(w + bits);
+    auto *P1 = reinterpret_cast<unsigned long long *>(w + 2 * bits);
+    int *sep_idx = reinterpret_cast<int *>(w + 3 * bits);
+    int *flag = reinterpret_cast<int *>(w + 3 * bits + align256((size_t)n * (size_t)n * sizeof(int)));
+    const auto *A = reinterpret_cast<const unsigned long long *>(adj);
+    auto *OUT = reinterpret_cast<unsigned long long *>(arrows);
+    hipStream_t s = ctx->stream;
+    PC_HIP(launch_orient_setup(s, n, A, recs, nrec, OUT, IN, P0, P1, sep_idx, flag));
+    // Every round that changes something orients at least one of the n(n-1)/2 possible edges.
+    int32_t done = 0;
+    for (int64_t r = 0; r <= n * (n - 1) / 2; ++r) {
+        PC_HIP(launch_orient_round(s, n, A, OUT, IN, (r & 1) ? P1 : P0, (r & 1) ? P0 : P1, flag));
+        int changed = 0;
+        PC_HIP(hipMemcpyAsync(&changed, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        PC_HIP(hipStreamSynchronize(s));
+        if (changed == 0) break;
+        ++done;
+    }
+    if (rounds) *rounds = done;
+    return PC_OK;
+}
+
 pc_status pc_comb_unrank(int32_t d, int32_t l, uint64_t t, int32_t skip, int32_t *out) {
     if (!out || d < 0 || l < 0 || l > PC_MAX_LEVEL) return PC_ERR_INVALID_ARG;
     const int pool = skip >= 0 ? d - 1 : d;

@@ -191,6 +191,17 @@ hipError_t launch_level(hipStream_t s, const Batch &b, int level, int ranks_per_
 hipError_t launch_recheck(hipStream_t s, const Batch &b, int level, int grid);
 int recheck_blocks_per_cu();                                    // resident re-check work-groups per CU
 
+// pc_orient.hip
+// Skeleton orientation: clears the state, indexes the SepSet records, marks the unshielded
+// colliders (OUT / IN: n x W arrowhead bit matrices; P0, P1: proposal buffers; sep_idx: n x n).
+hipError_t launch_orient_setup(hipStream_t s, int64_t n, const unsigned long long *A, const pc_sep_rec *recs,
+                               int64_t nrec, unsigned long long *OUT, unsigned long long *IN,
+                               unsigned long long *P0, unsigned long long *P1, int *sep_idx, int *flag);
+// One propagation round: proposals into P (cleared before), applied; Q cleared for the next round;
+// *flag = number of edges oriented.
+hipError_t launch_orient_round(hipStream_t s, int64_t n, const unsigned long long *A, unsigned long long *OUT,
+                               unsigned long long *IN, unsigned long long *P, unsigned long long *Q, int *flag);
+
 // pc_tail.hip
 // The remaining levels from `level` of every problem, one work-group per problem, as long as a
 // level has at most cap_tests CI tests (an upper bound from the degrees) and l <= kFastLevels.
