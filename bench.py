@@ -313,8 +313,33 @@ def main() -> int:
         out["batch256_graph"] = {"workload": "256 datasets, n~U[20,400], degree~U[2,8], m~U[200,5000], alpha 0.01",
                                  "ms_per_batch": bms, "status": br,
                                  "tests": int(sum(sum(s.as_dict()["tests"]) for s in bst))}
+        # -- orientation of the bench skeleton into a CPDAG (pc_orient) ----------------------------
+        nrec = int(gcount.item())
+        arrows = gctx.adjacency(n)
+        ows = gctx.orient_workspace(n)
+        rounds = gctx.pc_orient(n, gadj, grecs, nrec, arrows, ows)
+        torch.cuda.synchronize()
+        o0 = time.perf_counter()
+        oreps = 20
+        for _ in range(oreps):
+            gctx.pc_orient(n, gadj, grecs, nrec, arrows, ows)
+        torch.cuda.synchronize()
+        orient_ms = (time.perf_counter() - o0) / oreps * 1e3
+        Hg = pc.bits_to_dense(arrows.cpu().numpy(), n).astype(bool)
+        out["orientation"] = {"workload": "CPDAG of the bench skeleton (colliders + Meek R1-R3)",
+                              "ms": orient_ms, "rounds": rounds,
+                              "directed": int((Hg & ~Hg.T).sum()), "bidirected": int((Hg & Hg.T).sum()) // 2,
+                              "undirected": int(G.sum()) // 2 - int((Hg & ~Hg.T).sum()) - int((Hg & Hg.T).sum()) // 2}
 
     if not args.no_cpu_baseline:
+        if "orientation" in out:
+            # the orientation reference on the same skeleton and SepSets, timed and compared
+            from oracle import orient as orient_ref
+            seps = pc.decode_sepsets(grecs[:max(nrec, 1)].cpu().numpy(), nrec)
+            c0 = time.perf_counter()
+            H_ref, rounds_ref = orient_ref.orient(G.astype(bool), orient_ref.sepset_lookup(seps))
+            out["orientation"]["cpu_reference_s"] = time.perf_counter() - c0
+            out["orientation"]["same_as_reference"] = bool(np.array_equal(H_ref, Hg) and rounds_ref == rounds)
         ref, cpu_sec, reps = cpu_baseline(X, alpha)
         canonical = int(sum(ref.tests))
         out["value"] = canonical / sec_per_step
