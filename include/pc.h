@@ -82,8 +82,9 @@ typedef struct {
                                   stream in pc_graph_results. */
     int32_t tests_per_lane;    /* levels up to 13: rows with long neighbour lists get work items of
                                   fewer conditioning sets, so one lane runs about this many CI
-                                  tests per item (0 = automatic: 32 when the call has at most
-                                  2048 variables in all, else 128) */
+                                  tests per item (0 = automatic: 32 when the call has no more
+                                  variables in all than level-1 work-groups fit on the device,
+                                  else 128) */
     int32_t tail_tests;        /* > 0: once a level of a problem (level >= 2, <= 8) has at most this
                                   many CI tests (bounded by sum C(d_i, l)(d_i - l)), that level and
                                   the following ones run in one work-group per problem instead of

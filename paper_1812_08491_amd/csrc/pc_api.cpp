@@ -58,13 +58,12 @@ struct pc_graph {
 namespace {
 
 constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24, unit roundoff of FP32
-// Default bound on the CI tests of a lane per work item. A call with few rows has few heavy rows,
-// and a level's launch lasts as long as its heaviest item, so they are cut finer; with many rows
-// (large problems, or batches) items already outnumber work-groups, and finer items only repeat
-// the row staging.
+// Default bound on the CI tests of a lane per work item. When every row can have a work-group of
+// its own, a level's launch lasts as long as its heaviest row, so heavy rows are cut finer; when
+// rows outnumber the work-groups (large problems, batches), the queue balances them, and finer
+// items only repeat the row staging.
 constexpr int kAutoLaneTests = 128;
-constexpr int kAutoLaneTestsSmall = 32;             // when the call has at most kSmallRows rows
-constexpr int64_t kSmallRows = 2048;
+constexpr int kAutoLaneTestsSmall = 32;             // when the call has no more rows than work-groups
 
 #define PC_HIP(call)                                                       \
     do {                                                                   \
@@ -284,8 +283,9 @@ Batch make_batch(const pc_ctx *ctx, const Plan &L, unsigned char *ws) {
     b.count = L.count;
     b.prec = L.prec;
     b.force_recheck = L.prec != PC_PREC_FP64 && ctx->opt.force_recheck_all;
+    const long long groups = ctx->level_grid[1] > 0 ? ctx->level_grid[1] : 4 * ctx->num_cu;
     b.lane_tests = ctx->opt.tests_per_lane > 0 ? ctx->opt.tests_per_lane
-                                               : (L.total_rows <= kSmallRows ? kAutoLaneTestsSmall : kAutoLaneTests);
+                                               : (L.total_rows <= groups ? kAutoLaneTestsSmall : kAutoLaneTests);
     const long long *bases = reinterpret_cast<const long long *>(ws + L.table + sizeof(Prob) * L.count);
     b.row_base = bases;
     b.cs_base = bases + (L.count + 1);
