@@ -331,6 +331,31 @@ def main() -> int:
                               "directed": int((Hg & ~Hg.T).sum()), "bidirected": int((Hg & Hg.T).sum()) // 2,
                               "undirected": int(G.sum()) // 2 - int((Hg & ~Hg.T).sum()) - int((Hg & Hg.T).sum()) // 2}
 
+    if not args.no_extras:
+        # -- the paper's scalability family: n = 1000, edge probability 0.1, m = 10000, FP64 --------
+        Xs, _, alpha_s = semgen.scalability(1000, 0.1, 10000)
+        ms_s, ns_s = Xs.shape
+        sctx = pc.Context(precision="fp64")
+        sws = sctx.workspace(ns_s, ms_s)
+        sadj = sctx.adjacency(ns_s)
+        srecs, scount = sctx.sepsets(ns_s * (ns_s - 1) // 2)
+        Xsd = torch.from_numpy(np.ascontiguousarray(Xs)).cuda()
+        walls = []
+        for r in range(4):
+            sst = pc.pc_run_stats()
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            sstatus = sctx.pc_skeleton(Xsd, alpha_s, sadj, srecs, scount, sws, stats=sst)
+            torch.cuda.synchronize()
+            if r:
+                walls.append(time.perf_counter() - s0)
+        sd = sst.as_dict()
+        out["paper_scalability"] = {
+            "workload": "n=1000, edge probability 0.1, positive weights, m=10000, alpha 0.01, fp64",
+            "ms": float(np.median(walls)) * 1e3, "status": sstatus, "levels_run": sd["levels_run"],
+            "gpu_tests": int(sum(sd["tests"])), "edges": int(pc.bits_to_dense(sadj.cpu().numpy(), ns_s).sum()) // 2}
+        del Xsd, sws
+
     if not args.no_cpu_baseline:
         if "orientation" in out:
             # the orientation reference on the same skeleton and SepSets, timed and compared

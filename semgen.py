@@ -114,6 +114,15 @@ def workload(name: str, instance: int = 0):
     return X, sem, alpha
 
 
+def scalability(n: int = 1000, p: float = 0.1, m: int = 10000, instance: int = 0):
+    """The paper's own scalability family (Sec. 5, scalability): every ordered pair gets an edge with
+    probability p (a dense graph: about p (n - 1) / 2 parents per node), positive weights U[0.1, 1],
+    unit-variance Gaussian noise, m samples. Returns (X, sem, alpha = 0.01)."""
+    rng = np.random.default_rng(1000 * 6 + 10 * int(round(p * 100)) + instance)
+    sem = random_dag(n, p, rng, signed=False)
+    return sample(sem, m, rng), sem, 0.01
+
+
 def batch_problems(count: int = 256, instance: int = 0, nmin: int = 20, nmax: int = 400,
                    dmin: float = 2.0, dmax: float = 8.0, mmin: int = 200, mmax: int = 5000):
     """Uneven batch of independent datasets: n ~ U[20,400], degree ~ U[2,8], m ~ U[200,5000]."""
