@@ -16,14 +16,13 @@ __device__ inline unsigned long long live_word(unsigned long long *p) {
 }
 
 // Clears edge (lo, hi) from G. Returns true for the one caller whose atomic AND on the canonical
-// bit (row lo, column hi) found it set: that caller owns the SepSet record. The mirrored bit is
-// cleared by every caller (clearing it twice changes nothing), so that AND needs no result and
-// the caller waits on one round trip only.
+// bit (row lo, column hi) found it set: that caller owns the SepSet record.
 __device__ inline bool take_edge(unsigned long long *adj, int64_t W, int lo, int hi) {
     const unsigned long long bit = 1ull << (hi & 63);
     const unsigned long long old = atomicAnd(adj + (int64_t)lo * W + (hi >> 6), ~bit);
+    if (!(old & bit)) return false;
     atomicAnd(adj + (int64_t)hi * W + (lo >> 6), ~(1ull << (lo & 63)));
-    return (old & bit) != 0ull;
+    return true;
 }
 
 // Writes one SepSet record: (lo, hi, level) and S[0..level), the rest -1.
