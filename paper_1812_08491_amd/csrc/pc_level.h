@@ -635,10 +635,12 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
             };
             auto CS = [&](int p, int q) -> T {
                 if constexpr (K == 7) return p == q ? (T)1 : lds_blk[p * d + q];
-                else if constexpr (K == 5) return p == q ? (T)1 : C[(int64_t)lds_nb[p] * n + lds_nb[q]];
+                // From global C, the row of the set element q (C is exactly symmetric): at level 1
+                // the lanes of a wavefront share q and read ascending columns N_p of one row.
+                else if constexpr (K == 5) return p == q ? (T)1 : C[(int64_t)lds_nb[q] * n + lds_nb[p]];
                 else {
                     if (p == q) return (T)1;
-                    return (mode & 2) ? lds_blk[p * d + q] : C[(int64_t)NB(p) * n + NB(q)];
+                    return (mode & 2) ? lds_blk[p * d + q] : C[(int64_t)NB(q) * n + NB(p)];
                 }
             };
             auto LIVE = [&](int j) -> bool {
