@@ -27,13 +27,45 @@ class OracleError(RuntimeError):
     pass
 
 
+# Built with -O3 -march=native, so the library is tied to the CPU it was built on; a stamp file
+# records that CPU and the flags, and a library built elsewhere is rebuilt before it is loaded.
+_FLAGS = ["-O3", "-march=native", "-fopenmp", "-std=c11", "-fPIC", "-shared", "-Wall"]
+_STAMP = _LIB + ".host"
+
+
+def _host_stamp() -> str:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model + " | " + " ".join(_FLAGS)
+
+
+def _stale() -> bool:
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        return True
+    try:
+        with open(_STAMP) as f:
+            return f.read() != _host_stamp()
+    except OSError:
+        return True
+
+
 def build(force: bool = True) -> str:
-    """Compiles the oracle with gcc (plain -O2, single-threaded)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compiles the oracle with gcc (-O3 -march=native, OpenMP; single-threaded unless
+    set_threads says otherwise). -std=c11 keeps floating-point contraction off, so the arithmetic
+    is the plain sequence of the source."""
+    if force or _stale():
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-o", tmp,
-                               _SRC, "-lm"])
+        subprocess.check_call(["gcc"] + _FLAGS + ["-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
+        with open(_STAMP, "w") as f:
+            f.write(_host_stamp())
     return _LIB
 
 
@@ -53,7 +85,7 @@ class _Stats(ct.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale():
             build(force=True)
         L = ct.CDLL(_LIB)
         dp, ip = ct.POINTER(ct.c_double), ct.POINTER(ct.c_int)
@@ -73,6 +105,8 @@ def lib():
         L.oc_level.argtypes = [dp, ct.c_int64, ct.c_double, ct.c_double, ct.c_int, up,
                                ct.POINTER(_Sep), ct.POINTER(_Stats)]
         L.oc_max_degree.argtypes = [up, ct.c_int64]
+        L.oc_set_threads.argtypes = [ct.c_int]
+        L.oc_set_threads.restype = None
         L.oc_skeleton_corr.argtypes = [dp, ct.c_int64, ct.c_double, ct.c_double, ct.c_int, up,
                                        ct.POINTER(_Sep), ct.POINTER(_Stats), ct.c_int, up,
                                        ct.POINTER(ct.c_int)]
@@ -81,6 +115,12 @@ def lib():
                                   ct.POINTER(ct.c_int)]
         _lib = L
     return _lib
+
+
+def set_threads(k: int) -> None:
+    """Threads the level loop uses (edges of a level are decided in parallel from the snapshot G'
+    and applied in canonical order, so every result is the same for any k)."""
+    lib().oc_set_threads(int(k))
 
 
 def _dp(a):

@@ -27,6 +27,9 @@
  *   - M2 is applied through a Cholesky factor; a pivot <= 1e-12 * max diag(M2) switches to the
  *     pseudo-inverse from a symmetric (cyclic Jacobi) eigendecomposition, dropping eigenvalues
  *     <= l * eps64 * lambda_max.
+ * The edges of a level may be decided by several threads (oc_set_threads; default one): each
+ * decision reads only C and the snapshot G', and the removals and SepSets are applied afterwards
+ * in canonical order, so the results do not depend on the thread count.
  */
 #include "pc_oracle.h"
 
@@ -355,50 +358,85 @@ static int test_direction(const double *C, int64_t n, const unsigned char *Gp, i
     return 0;
 }
 
+/* Threads of oc_level (1 unless oc_set_threads says otherwise). */
+static int g_threads = 1;
+
+void oc_set_threads(int k) { g_threads = k > 0 ? k : 1; }
+
 int oc_level(const double *C, int64_t n, double m, double alpha, int l, unsigned char *G,
              oc_sepset *sep, oc_level_stats *st)
 {
     double tau = oc_tau(alpha, m, l);
     if (isnan(tau)) return OC_WARN_SAMPLE_LIMIT;
     unsigned char *Gp = (unsigned char *)malloc((size_t)(n * n));
-    int *cand = (int *)malloc(sizeof(int) * (size_t)(n + 1));
-    int *pos = (int *)malloc(sizeof(int) * (size_t)(l + 1));
-    int *S = (int *)malloc(sizeof(int) * (size_t)(l + 1));
-    int *Sbest = (int *)malloc(sizeof(int) * (size_t)(l + 1));
-    if (!Gp || !cand || !pos || !S || !Sbest) {
-        free(Gp); free(cand); free(pos); free(S); free(Sbest);
+    if (!Gp) return OC_ERR_ALLOC;
+    memcpy(Gp, G, (size_t)(n * n)); /* G' := G */
+    /* The edges of G' in canonical order (i < j, lexicographic). */
+    int64_t E = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) E += Gp[i * n + j] ? 1 : 0;
+    int *ei = (int *)malloc(sizeof(int) * (size_t)(E + 1));
+    int *ej = (int *)malloc(sizeof(int) * (size_t)(E + 1));
+    int *res = (int *)malloc(sizeof(int) * (size_t)(E + 1));
+    int *Sres = (int *)malloc(sizeof(int) * (size_t)(E + 1) * (size_t)(l + 1));
+    if (!ei || !ej || !res || !Sres) {
+        free(Gp); free(ei); free(ej); free(res); free(Sres);
         return OC_ERR_ALLOC;
     }
-    memcpy(Gp, G, (size_t)(n * n)); /* G' := G */
-    int64_t ntests = 0, nremoved = 0;
-    int status = OC_OK;
-    for (int i = 0; i < n && status >= 0; ++i)
-        for (int j = i + 1; j < n; ++j) {
-            if (!Gp[(int64_t)i * n + j]) continue;
-            int r = test_direction(C, n, Gp, i, j, l, tau, Sbest, &ntests, cand, pos, S);
-            if (r == 0) r = test_direction(C, n, Gp, j, i, l, tau, Sbest, &ntests, cand, pos, S);
-            if (r < 0) { status = r; break; }
-            if (r == 1) {
-                G[(int64_t)i * n + j] = 0;
-                G[(int64_t)j * n + i] = 0;
-                nremoved += 1;
-                if (sep) {
-                    if (sep->count < sep->cap) {
-                        int64_t k = sep->count;
-                        sep->i[k] = i;
-                        sep->j[k] = j;
-                        sep->level[k] = l;
-                        for (int e = 0; e < l; ++e) sep->S[k * sep->max_level + e] = Sbest[e];
-                    }
-                    sep->count += 1;
-                }
-            }
+    E = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            if (Gp[(int64_t)i * n + j]) { ei[E] = i; ej[E] = j; ++E; }
+    /* Every edge is decided from G' alone (Sec. 2.4): S is drawn from the snapshot, and removals
+     * go to G only. So the edges may be decided in any order, here by several threads, and the
+     * removals and SepSets are then applied in canonical order. */
+    int64_t ntests = 0;
+    int alloc_fail = 0;
+#pragma omp parallel num_threads(g_threads) reduction(+ : ntests)
+    {
+        int *cand = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+        int *pos = (int *)malloc(sizeof(int) * (size_t)(l + 1));
+        int *S = (int *)malloc(sizeof(int) * (size_t)(l + 1));
+        if (!cand || !pos || !S) {
+#pragma omp atomic write
+            alloc_fail = 1;
         }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t e = 0; e < E; ++e) {
+            if (!cand || !pos || !S) { res[e] = OC_ERR_ALLOC; continue; }
+            int *Sbest = Sres + e * (l + 1);
+            int r = test_direction(C, n, Gp, ei[e], ej[e], l, tau, Sbest, &ntests, cand, pos, S);
+            if (r == 0) r = test_direction(C, n, Gp, ej[e], ei[e], l, tau, Sbest, &ntests, cand, pos, S);
+            res[e] = r;
+        }
+        free(cand); free(pos); free(S);
+    }
+    int64_t nremoved = 0;
+    int status = alloc_fail ? OC_ERR_ALLOC : OC_OK;
+    for (int64_t e = 0; e < E && status >= 0; ++e) {
+        const int r = res[e];
+        if (r < 0) { status = r; break; }
+        if (r != 1) continue;
+        const int i = ei[e], j = ej[e];
+        G[(int64_t)i * n + j] = 0;
+        G[(int64_t)j * n + i] = 0;
+        nremoved += 1;
+        if (sep) {
+            if (sep->count < sep->cap) {
+                int64_t k = sep->count;
+                sep->i[k] = i;
+                sep->j[k] = j;
+                sep->level[k] = l;
+                for (int q = 0; q < l; ++q) sep->S[k * sep->max_level + q] = Sres[e * (l + 1) + q];
+            }
+            sep->count += 1;
+        }
+    }
     if (st) {
         st->tests = ntests;
         st->removed = nremoved;
     }
-    free(Gp); free(cand); free(pos); free(S); free(Sbest);
+    free(Gp); free(ei); free(ej); free(res); free(Sres);
     return status;
 }
 

@@ -44,6 +44,8 @@ int oc_pinv_sym(const double *A, int k, double *P);
 int oc_pcor(const double *C, int64_t n, int i, int j, const int *S, int l, double *rho_out);
 int oc_ci_test(const double *C, int64_t n, int i, int j, const int *S, int l, double tau,
                double *z_out);
+/* Threads oc_level uses (default 1); results do not depend on it. */
+void oc_set_threads(int k);
 int oc_level0(const double *C, int64_t n, double m, double alpha, unsigned char *G,
               oc_level_stats *st);
 int oc_level(const double *C, int64_t n, double m, double alpha, int l, unsigned char *G,

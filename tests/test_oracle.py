@@ -359,3 +359,20 @@ def test_max_level_cap_and_sample_limit():
     assert sk.levels_run <= 3
     if sk.status == oracle.OC_WARN_SAMPLE_LIMIT:
         assert sk.levels_run == 3
+
+
+def test_threads_give_identical_results():
+    """Edges of a level are decided from G' alone (Sec. 2.4), so deciding them on several threads
+    must leave the skeleton, the canonical SepSets and the per-level test counts unchanged."""
+    X, _, alpha = semgen.workload("n1000_d4_m500_fp32")
+    try:
+        oracle.set_threads(1)
+        a = oracle.skeleton(X, alpha, keep_levels=True)
+        oracle.set_threads(4)
+        b = oracle.skeleton(X, alpha, keep_levels=True)
+    finally:
+        oracle.set_threads(1)
+    assert np.array_equal(a.G, b.G)
+    assert a.tests == b.tests and a.removed == b.removed
+    assert a.sepsets.as_dict() == b.sepsets.as_dict()
+    assert all(np.array_equal(x, y) for x, y in zip(a.G_after, b.G_after))
