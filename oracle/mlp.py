@@ -3,6 +3,9 @@
 TEST INFRASTRUCTURE ONLY (gradient checks of the GPU kernels). The network scores a conditioning
 candidate: 8 features -> 64 -> 64 -> 1 with ReLU. Parameters are one flat vector laid out as
 W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3 (each weight row is one output unit).
+
+Pinned in tests/test_oracle_mlp.py against torch.nn layers, torch autograd, torch's weighted
+logit BCE and torch.optim.Adam (FP64, CPU), and against finite differences.
 """
 from __future__ import annotations
 
