@@ -1,24 +1,36 @@
 """Benchmark: PC-stable skeleton on one MI355X through the C ABI.
 
-One step = one whole skeleton (standardize, correlation GEMM with the level-0 test, then every
-level until the stop rule, FP64 re-checks included) of a synthetic linear-Gaussian SEM dataset that
-is already resident in HBM: n = 1000 variables, expected degree 4, m = 500 samples, alpha = 0.01,
-FP32 CI tests with FP64 re-checks of borderline tests. The skeleton is captured once as a hipGraph
-(pc_batch_capture) and each step is one replay; `ms_per_step` is the replay time. The graph records
-the levels with many tests (those above TAIL_TESTS in an untimed pc_skeleton run on the same data)
-as level kernels, and the small levels after them as the tail kernel (one work-group per problem);
-the run asserts that no replay needed the stream continuation of pc_graph_results.
+Headline workload: a linear-Gaussian SEM with n = 2000 variables, expected degree 10 and m = 1000
+samples, alpha = 0.01. CI tests run in FP32 and borderline tests are re-done in FP64. Level 1 uses
+the learned conditioning-set order: a row model trained on 2000 generated n = 200 SEMs picks each
+node's best candidates k, and their sets {k} are tested first.
 
-`value` is CI tests per second: the tests the sequential PC-stable enumeration performs on this
-input (canonical order, early stop per edge; counted by the CPU oracle in the cpu_baseline leg, on
-the same input) divided by the time per step. The tests the GPU evaluated are reported beside it.
+One step is one whole skeleton, run by pc_skeleton_ordered on the stream. It covers
+standardization, the correlation GEMM with level 0, and every level with its re-checks. The data
+is resident in HBM. `ms_per_step` is the host wall time per step.
 
-Also reported: the same skeleton through pc_skeleton on the stream (with HIP events around the
-kernels, which give the roofline of the dominant kernel), plain vs learned conditioning-set order
-on n = 2000 (expected degree 10, m = 1000, identical skeleton required), and a captured batch of
-256 uneven datasets.
+`value` is CI tests per second: the tests that the sequential PC-stable enumeration performs on this
+input (canonical order, first success ends an edge), divided by the time per step. The CPU oracle
+counts them on the same input.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--copy-calibration MiB]
+The same skeleton is also run with plain lexicographic enumeration and with candidates ranked by
+|C_ik| alone, and timed the same way. All three skeletons must equal the oracle's; if one does not,
+`value` is null.
+
+`roofline` prices the level-1 pass of a step (k_row_order + k_window + k_level<float,1>) on the
+canonical level-1 work. Each CI test reads 8 bytes (C_ij and C_jk) and each conditioning set
+{k} of a row reads 8 bytes (C_ik, C_kk). The pass is timed with HIP events inside the timed
+steps.
+
+Further legs (skipped with --no-extras):
+* the n = 1000, degree 4, m = 500 skeleton as a captured hipGraph;
+* the n = 8000, degree 6, m = 2000 skeleton with the BF16x3 GEMM, levels 1-3;
+* 256 uneven datasets in one graph;
+* orientation of the n = 1000 skeleton;
+* the paper's scalability family.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
+                    [--headline-only] [--copy-calibration MiB] [--write-traffic ...]
 """
 from __future__ import annotations
 
@@ -34,17 +46,34 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "n1000_d4_m500_fp32"
-APPLY_WORKLOAD = "n2000_d10_m1000_apply"
+HEADLINE = "n2000_d10_m1000_apply"
+C2_WORKLOAD = "n1000_d4_m500_fp32"
+C3_WORKLOAD = "n8000_d6_m2000_bf16x3"
+C3_GOLDEN = os.path.join(ROOT, "tests", "golden", "n8000_d6_m2000_levels3.npz")
 PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix
+PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_level1_n1000_d4_m500.json")
-ROW_TOP = 2   # candidates per node the learned order tests first at level 1
-TAIL_TESTS = 2048     # levels with more CI tests than this run as level kernels in the graph
+ROW_TOP = 2           # candidates per node the ordered forms test first at level 1
+TAIL_TESTS = 2048     # c2 graph: levels with more CI tests than this run as level kernels
 TAIL_MAX_LEVEL = 8    # deepest level the tail kernel runs
+TRAFFIC = {
+    "headline": os.path.join(ROOT, "profiles", "traffic_level1_n2000_d10_m1000.json"),
+    "c2": os.path.join(ROOT, "profiles", "traffic_k_level1_n1000_d4_m500.json"),
+}
+LEVEL1_KERNELS = {"headline": ["k_row_order<float>", "k_window", "k_level<float, 1>"],
+                  "c2": ["k_level<float, 1>"]}
 LEVEL_SOURCES = ["paper_1812_08491_amd/csrc/pc_level.h", "paper_1812_08491_amd/csrc/pc_level_f32.hip",
-                 "paper_1812_08491_amd/csrc/pc_citest.h", "paper_1812_08491_amd/csrc/pc_dev.h",
-                 "paper_1812_08491_amd/csrc/pc_comb.h"]
+                 "paper_1812_08491_amd/csrc/pc_level.hip", "paper_1812_08491_amd/csrc/pc_citest.h",
+                 "paper_1812_08491_amd/csrc/pc_dev.h", "paper_1812_08491_amd/csrc/pc_comb.h",
+                 "paper_1812_08491_amd/csrc/pc_mlp.hip"]
+
+
+_T0 = time.perf_counter()
+
+
+def progress(msg: str) -> None:
+    """A progress line on stderr (the JSON result is the only line on stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def level_source_hash() -> str:
@@ -55,31 +84,25 @@ def level_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of k_level<float,1> from the committed PMC summary, or None when the
-    level kernel's sources changed after the counters were taken."""
+def measured_traffic(leg: str):
+    """HBM bytes per level-1 pass from the committed PMC summary, or None when a level-1 source
+    changed after the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC[leg]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("source_hash") != level_source_hash():
         return None
-    return float(t["bytes_per_launch"])
+    return float(t["bytes_per_pass"])
 
 
-def cpu_baseline(X: np.ndarray, alpha: float, min_seconds: float = 10.0, max_reps: int = 30):
-    """The FP64 oracle (single-threaded C, as it stands) on the same input, repeated until about
-    min_seconds of CPU time; returns (oracle result, seconds per skeleton, runs)."""
-    import oracle
-    t0 = time.perf_counter()
-    ref = oracle.skeleton(X, alpha)
-    times = [time.perf_counter() - t0]
-    while sum(times) < min_seconds and len(times) < max_reps:
-        t0 = time.perf_counter()
-        oracle.skeleton(X, alpha)
-        times.append(time.perf_counter() - t0)
-    return ref, float(np.mean(times)), len(times)
+def level1_bytes(ref, n: int) -> float:
+    """Canonical level-1 bytes: 8 B per CI test the sequential enumeration performs (C_ij and C_jk)
+    and 8 B per conditioning set {k} of a row of G' (C_ik, C_kk), i.e. two per edge of G after
+    level 0."""
+    edges_after_0 = n * (n - 1) // 2 - int(ref.removed[0])
+    return 8.0 * (int(ref.tests[1]) + 2 * edges_after_0)
 
 
 def copy_calibration(mib: int, reps: int = 5) -> None:
@@ -93,44 +116,420 @@ def copy_calibration(mib: int, reps: int = 5) -> None:
     print(json.dumps({"copy_calibration_bytes": mib << 20, "reps": reps}))
 
 
-def write_traffic(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str,
+def write_traffic(leg: str, fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str,
                   copy_bytes: int) -> None:
-    """Per-launch HBM bytes of k_level<float,1> from two rocprofv3 --pmc runs (FETCH_SIZE, then
-    WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for a device copy of
-    copy_bytes; written to the traffic summary with the hash of the level kernel's sources."""
+    """Per-dispatch HBM bytes of the level-1 kernels of a leg from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for
+    a device copy of copy_bytes; written with the hash of the level-1 sources."""
     import csv
 
     def per_dispatch(path, kernel):
-        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if r["Kernel_Name"].startswith(kernel)]
-        return float(np.mean(vals)), len(vals)
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                if r["Kernel_Name"].startswith("void pcg::" + kernel) or r["Kernel_Name"].startswith("pcg::" + kernel)
+                or r["Kernel_Name"].startswith(kernel)]
+        return (float(np.mean(vals)) if vals else 0.0), len(vals)
 
-    fetch, nf = per_dispatch(fetch_csv, "void pcg::k_level<float, 1>")
-    write, nw = per_dispatch(write_csv, "void pcg::k_level<float, 1>")
     cf, _ = per_dispatch(copy_fetch_csv, "__amd_rocclr_copyBuffer")
     cw, _ = per_dispatch(copy_write_csv, "__amd_rocclr_copyBuffer")
     f_fetch, f_write = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
-    out = {"kernel": "k_level<float,1>", "workload": "n=1000, degree 4, m=500, alpha 0.01, fp32",
-           "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
-           "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
-           "fetch_scale": f_fetch, "write_scale": f_write,
-           "bytes_per_launch": (fetch * f_fetch + write * f_write) * 1024.0,
+    kernels, total = {}, 0.0
+    for k in LEVEL1_KERNELS[leg]:
+        fetch, nf = per_dispatch(fetch_csv, k)
+        write, nw = per_dispatch(write_csv, k)
+        b = (fetch * f_fetch + write * f_write) * 1024.0
+        kernels[k] = {"fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
+                      "bytes_per_launch": b}
+        total += b
+    out = {"leg": leg, "kernels": kernels, "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": f_fetch, "write_scale": f_write, "bytes_per_pass": total,
            "source_hash": level_source_hash()}
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(TRAFFIC[leg], "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
+
+
+def oracle_timed(X, alpha, threads: int, max_level: int = -1):
+    """The FP64 oracle as it stands on `threads` threads: (result, seconds)."""
+    import oracle
+    oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        ref = oracle.skeleton(X, alpha, max_level=max_level)
+        return ref, time.perf_counter() - t0
+    finally:
+        oracle.set_threads(1)
+
+
+def host_threads() -> int:
+    """Threads for the multi-threaded oracle run: this process's CPU share (OMP_NUM_THREADS when
+    the host sets it), at most the CPUs present."""
+    cpus = os.cpu_count() or 1
+    try:
+        cpus = min(cpus, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        pass
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(cpus, int(env))) if env.isdigit() and int(env) > 0 else cpus
+
+
+# ---------------------------------------------------------------------------------------------
+# Headline: learned order vs |C_ik| vs plain, n = 2000, degree 10, m = 1000
+# ---------------------------------------------------------------------------------------------
+def headline(args, torch, pc, semgen, out):
+    from paper_1812_08491_amd import learn
+    progress("headline: n=2000 learned / |C_ik| / plain")
+    X, _, alpha = semgen.workload(HEADLINE)
+    m, n = X.shape
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    row_w = learn.load_weights(learn.ROW_WEIGHTS)
+    modes = {}
+    for mode in ("learned", "abs", "plain"):
+        # Level kernels timed with HIP events inside every step (bit 2).
+        ctx = pc.Context(precision="fp32", timing=2)
+        order = None
+        if mode == "learned":
+            order = ctx.order(None, row_params=row_w, row_top=ROW_TOP)
+        elif mode == "abs":
+            order = ctx.order(None, row_top=ROW_TOP, row_rank="abs")
+        ws = ctx.ordered_workspace(n, m, order) if order is not None else ctx.workspace(n, m)
+        recs, count = ctx.sepsets(n * (n - 1) // 2)
+        modes[mode] = dict(ctx=ctx, order=order, ws=ws, adj=ctx.adjacency(n), recs=recs, count=count)
+
+    def step(mode):
+        r = modes[mode]
+        st = pc.pc_run_stats()
+        if r["order"] is None:
+            s = r["ctx"].pc_skeleton(Xd, alpha, r["adj"], r["recs"], r["count"], r["ws"], stats=st)
+        else:
+            s = r["ctx"].pc_skeleton_ordered(Xd, alpha, r["adj"], r["recs"], r["count"], r["ws"], r["order"],
+                                             stats=st)
+        assert s == 0, pc.status_str(s)
+        return st
+
+    names = ("learned",) if args.headline_only else ("learned", "abs", "plain")
+    for mode in names:
+        for _ in range(args.warmup):
+            step(mode)
+    res = {}
+    for mode in names:
+        torch.cuda.synchronize()
+        sts = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sts.append(step(mode).as_dict())
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        last = sts[-1]
+        res[mode] = {"ms_per_step": sec * 1e3, "tests": last["tests"], "probe_tests": last["probe_tests"],
+                     "levels_run": last["levels_run"],
+                     "level1_pass_ms": float(np.mean([s["level_ms"][1] for s in sts])),
+                     "adj": modes[mode]["adj"].cpu().numpy()}
+    G = {mode: pc.bits_to_dense(res[mode].pop("adj"), n) for mode in names}
+    sec = res["learned"]["ms_per_step"] * 1e-3
+    out.update({
+        "ms_per_step": res["learned"]["ms_per_step"],
+        "config": {"workload": "pc_stable_skeleton_n2000_deg10_m1000_alpha0.01_fp32_recheck_learned_order",
+                   "n": n, "m": m, "expected_degree": 10, "alpha": alpha,
+                   "precision": "fp32 CI tests + fp64 re-check of borderline tests",
+                   "order": {"form": "shared-set (row) model at level 1", "row_top": ROW_TOP,
+                             "weights": "paper_1812_08491_amd/weights/order_row_mlp_n200.npy",
+                             "trained_on": "2000 generated SEMs, n=200, degree~U[2,10], m=1000"},
+                   "step": "one pc_skeleton_ordered call: the whole skeleton on the stream"},
+        "gpu_tests_per_step": int(sum(res["learned"]["tests"])),
+        "orders": {mode: {k: v for k, v in r.items()} for mode, r in res.items()},
+    })
+    if "plain" in G:
+        out["orders_same_skeleton"] = bool(np.array_equal(G["learned"], G["plain"]) and
+                                           np.array_equal(G["abs"], G["plain"]))
+        out["learned_vs_plain_speedup"] = res["plain"]["ms_per_step"] / res["learned"]["ms_per_step"]
+        out["learned_vs_abs_speedup"] = res["abs"]["ms_per_step"] / res["learned"]["ms_per_step"]
+    if args.no_cpu_baseline:
+        out["value"] = None
+        out["note"] = "no oracle run: value needs the oracle's canonical test count"
+        return
+    progress("headline: GPU steps done; oracle at 1 thread")
+    ref1, t1 = oracle_timed(X, alpha, 1)
+    threads = host_threads()
+    progress(f"headline: oracle at {threads} threads")
+    refN, tN = oracle_timed(X, alpha, threads)
+    assert np.array_equal(ref1.G, refN.G) and ref1.tests == refN.tests
+    canonical = int(sum(ref1.tests))
+    equal = {mode: bool(np.array_equal(G[mode], ref1.G)) for mode in names}
+    out["canonical_tests_per_step"] = canonical
+    out["canonical_tests_per_level"] = list(ref1.tests)
+    out["skeleton_equal_to_oracle"] = equal
+    ok = all(equal.values()) and out.get("orders_same_skeleton", True)
+    out["value"] = canonical / sec if ok else None
+    for mode in names:
+        out["orders"][mode]["canonical_tests_per_s"] = canonical / (res[mode]["ms_per_step"] * 1e-3)
+    lb = level1_bytes(ref1, n)
+    l1_ms = res["learned"]["level1_pass_ms"]
+    ach = lb / (l1_ms * 1e-3) / 1e9
+    out["roofline"] = {"kernel": "level-1 pass: k_row_order + k_window + k_level<float,1>", "bound": "hbm",
+                       "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                       "traffic": measured_traffic("headline"), "algorithmic_bytes": lb,
+                       "algorithmic_units": {"canonical_level1_tests": int(ref1.tests[1]),
+                                             "level1_sets": 2 * (n * (n - 1) // 2 - int(ref1.removed[0]))},
+                       "launch_ms": l1_ms}
+    if "plain" in res:
+        pl = res["plain"]["level1_pass_ms"]
+        out["roofline_plain_level1"] = {"kernel": "k_level<float,1> (plain order)", "achieved": lb / (pl * 1e-3) / 1e9,
+                                        "frac": lb / (pl * 1e-3) / 1e9 / PEAK_HBM_GBS, "launch_ms": pl,
+                                        "executed_over_canonical": res["plain"]["tests"][1] / ref1.tests[1]}
+    out["cpu_baseline"] = {"value": canonical / t1, "unit": "CI tests/s", "cores": 1, "kind": "oracle",
+                           "sample": f"whole workload (same input), one run, {t1:.2f} s",
+                           "wall_s_per_skeleton": t1,
+                           "threaded": {"value": canonical / tN, "cores": threads, "wall_s_per_skeleton": tN},
+                           "build": "gcc -O3 -march=native -fopenmp (edges of a level in parallel)"}
+
+
+# ---------------------------------------------------------------------------------------------
+# n = 1000, degree 4, m = 500: the whole skeleton as one captured graph
+# ---------------------------------------------------------------------------------------------
+def leg_c2_graph(args, torch, pc, semgen, out):
+    progress("c2: n=1000 graph")
+    X, sem, alpha = semgen.workload(C2_WORKLOAD)
+    m, n = X.shape
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    ctx = pc.Context(precision="fp32", timing=1 | 2)
+    ws = ctx.workspace(n, m)
+    adj = ctx.adjacency(n)
+    recs, count = ctx.sepsets(n * (n - 1) // 2)
+    sts = []
+    for _ in range(max(3, args.warmup)):
+        st = pc.pc_run_stats()
+        assert ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st) == 0
+        sts.append(st.as_dict())
+    last = sts[-1]
+    L = last["levels_run"]
+    big = [l for l in range(1, L) if last["tests"][l] > TAIL_TESTS]
+    graph_levels = max([1] + big)
+    if L - 1 > TAIL_MAX_LEVEL:
+        graph_levels = max(graph_levels, L - 1)
+    gstream = torch.cuda.Stream()
+    with torch.cuda.stream(gstream):
+        gctx = pc.Context(stream=gstream, precision="fp32", graph_levels=graph_levels, tail_tests=1 << 30)
+        gadj = gctx.adjacency(n)
+        grecs, gcount = gctx.sepsets(n * (n - 1) // 2)
+        probs = gctx.problems([(Xd, alpha, -1, gadj, grecs, gcount)])
+        gws = gctx.batch_workspace(probs)
+        graph = gctx.pc_batch_capture(probs, gws)
+        for _ in range(args.warmup):
+            graph.pc_graph_launch()
+        torch.cuda.synchronize()
+        reps = max(20, args.steps)
+        g0 = time.perf_counter()
+        for _ in range(reps):
+            graph.pc_graph_launch()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - g0) / reps
+        gst = (pc.pc_run_stats * 1)()
+        r, gstatus = graph.pc_graph_results(gst)
+        graph.close()
+    assert r == 0 and gstatus[0] == 0, (r, gstatus)
+    gd = gst[0].as_dict()
+    assert gd["levels_run"] - 1 <= max(graph_levels, TAIL_MAX_LEVEL), "the graph did not cover every level"
+    G = pc.bits_to_dense(gadj.cpu().numpy(), n)
+    leg = {"workload": "n=1000, degree 4, m=500, alpha 0.01, fp32 + fp64 re-check; one hipGraph replay",
+           "ms_per_skeleton": sec * 1e3, "graph_levels": graph_levels, "levels_run": gd["levels_run"],
+           "gpu_tests": int(sum(gd["tests"])), "edges": int(G.sum()) // 2,
+           "level1_ms_events": float(np.mean([s["level_ms"][1] for s in sts[1:]])),
+           "corr_ms_events": float(np.mean([s["corr_ms"] for s in sts[1:]]))}
+    fl = float(m) * n * (n - 1) / (leg["corr_ms_events"] * 1e-3) / 1e12
+    leg["roofline_corr"] = {"kernel": "k_corr<fp32> (SYRK + level-0 test)", "bound": "mfma", "achieved": fl,
+                            "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": fl / PEAK_FP32_MFMA_TFLOPS}
+    if not args.no_cpu_baseline:
+        ref, t1 = oracle_timed(X, alpha, 1)
+        canonical = int(sum(ref.tests))
+        leg["skeleton_equal_to_oracle"] = bool(np.array_equal(G, ref.G))
+        leg["canonical_tests"] = canonical
+        leg["canonical_tests_per_s"] = canonical / sec if leg["skeleton_equal_to_oracle"] else None
+        lb = level1_bytes(ref, n)
+        ach = lb / (leg["level1_ms_events"] * 1e-3) / 1e9
+        leg["roofline_level1"] = {"kernel": "k_level<float,1>", "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
+                                  "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic("c2"),
+                                  "algorithmic_bytes": lb,
+                                  "executed_over_canonical": last["tests"][1] / max(1, ref.tests[1])}
+        leg["cpu_oracle_s"] = t1
+    out["c2_graph"] = leg
+    return gctx, gadj, grecs, gcount, G, n
+
+
+# ---------------------------------------------------------------------------------------------
+# n = 8000, degree 6, m = 2000: BF16x3 correlation GEMM, levels 1-3
+# ---------------------------------------------------------------------------------------------
+def leg_c3(args, torch, pc, semgen, out):
+    progress("c3: n=8000 levels 0-3")
+    X, sem, alpha = semgen.workload(C3_WORKLOAD)
+    m, n = X.shape
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    leg = {"workload": "n=8000, degree 6, m=2000, alpha 0.05, bf16x3 GEMM + fp32 tests + fp64 re-check, levels 0-3"}
+    for prec in ("bf16x3", "fp32"):
+        progress(f"c3: {prec}")
+        ctx = pc.Context(precision=prec, timing=1 | 2 | 8)
+        ws = ctx.workspace(n, m)
+        adj = ctx.adjacency(n)
+        recs, count = ctx.sepsets(4 * n * n // 8)
+        walls, sts = [], []
+        for r in range(3):
+            st = pc.pc_run_stats()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            assert ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, max_level=3, stats=st) == 0
+            torch.cuda.synchronize()
+            if r:
+                walls.append(time.perf_counter() - t0)
+                sts.append(st.as_dict())
+        G = pc.bits_to_dense(adj.cpu().numpy(), n)
+        d = sts[-1]
+        corr_ms = float(np.mean([s["corr_ms"] for s in sts]))
+        e = {"ms_per_skeleton": float(np.median(walls)) * 1e3, "corr_ms": corr_ms,
+             "level_ms": [float(np.mean([s["level_ms"][l] for s in sts])) for l in range(4)],
+             "recheck_ms": [float(np.mean([s["recheck_ms"][l] for s in sts])) for l in range(4)],
+             "gpu_tests": d["tests"], "rechecks": d["rechecks"], "edges": int(G.sum()) // 2}
+        flops = float(m) * n * (n - 1)
+        if prec == "bf16x3":
+            ach = 3 * flops / (corr_ms * 1e-3) / 1e12
+            e["roofline_corr"] = {"kernel": "k_corr<bf16x3>", "bound": "mfma", "achieved": ach,
+                                  "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s (3 BF16 products)",
+                                  "frac": ach / PEAK_BF16_MFMA_TFLOPS}
+        else:
+            ach = flops / (corr_ms * 1e-3) / 1e12
+            e["roofline_corr"] = {"kernel": "k_corr<fp32>", "bound": "mfma", "achieved": ach,
+                                  "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA_TFLOPS}
+        if os.path.exists(C3_GOLDEN):
+            # the oracle's stored result for this input (tests/golden/make_oracle_skeletons.py)
+            g = np.load(C3_GOLDEN, allow_pickle=False)
+            digest = hashlib.sha256(np.ascontiguousarray(X, dtype=np.float64).tobytes()).hexdigest()
+            if str(g["digest"]) == digest:
+                ref_edges = g["edges_after_3"]
+                Gr = np.zeros((n, n), bool)
+                Gr[ref_edges[:, 0], ref_edges[:, 1]] = True
+                Gr |= Gr.T
+                e["skeleton_equal_to_oracle"] = bool(np.array_equal(G.astype(bool), Gr))
+                canonical = int(g["tests"].sum())
+                e["canonical_tests"] = canonical
+                e["canonical_tests_per_s"] = canonical / (e["ms_per_skeleton"] * 1e-3)
+                lb = 8.0 * (int(g["tests"][1]) + 2 * (n * (n - 1) // 2 - int(g["removed"][0])))
+                a1 = lb / (e["level_ms"][1] * 1e-3) / 1e9
+                e["roofline_level1"] = {"kernel": "k_level<float,1>", "bound": "hbm", "achieved": a1,
+                                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": a1 / PEAK_HBM_GBS,
+                                        "algorithmic_bytes": lb,
+                                        "executed_over_canonical": d["tests"][1] / int(g["tests"][1])}
+        leg[prec] = e
+        del ws
+    out["c3_n8000"] = leg
+
+
+def leg_batch(args, torch, pc, semgen, out):
+    progress("batch: 256 datasets")
+    batch = semgen.batch_problems(256)
+    bstream = torch.cuda.Stream()
+    with torch.cuda.stream(bstream):
+        bctx = pc.Context(stream=bstream, precision="fp32")
+        items = []
+        for Xb, _, ab in batch:
+            mb, nb = Xb.shape
+            rb, cb = bctx.sepsets(nb * (nb - 1) // 2)
+            items.append((torch.from_numpy(np.ascontiguousarray(Xb)).cuda(), ab, -1, bctx.adjacency(nb), rb, cb))
+        bprobs = bctx.problems(items)
+        bws = bctx.batch_workspace(bprobs)
+        bgraph = bctx.pc_batch_capture(bprobs, bws)
+        bst = (pc.pc_run_stats * len(items))()
+        for _ in range(2):
+            bgraph.pc_graph_launch()
+            bgraph.pc_graph_results(bst)
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 5)
+        b0 = time.perf_counter()
+        for _ in range(reps):
+            # a replay and its results: levels some datasets need beyond the recorded ones run
+            # inside pc_graph_results, so both are timed
+            bgraph.pc_graph_launch()
+            br, bstatus = bgraph.pc_graph_results(bst)
+        torch.cuda.synchronize()
+        bms = (time.perf_counter() - b0) / reps * 1e3
+        bgraph.close()
+    assert br == 0 and all(s == 0 for s in bstatus), (br, bstatus)
+    tests = int(sum(sum(s.as_dict()["tests"]) for s in bst))
+    out["batch256_graph"] = {"workload": "256 datasets, n~U[20,400], degree~U[2,8], m~U[200,5000], alpha 0.01, fp32",
+                             "ms_per_batch": bms, "status": br, "gpu_tests": tests,
+                             "gpu_tests_per_s": tests / (bms * 1e-3)}
+
+
+def leg_orient(args, torch, pc, out, c2):
+    progress("orientation")
+    gctx, gadj, grecs, gcount, G, n = c2
+    nrec = int(gcount.item())
+    arrows = gctx.adjacency(n)
+    ows = gctx.orient_workspace(n)
+    rounds = gctx.pc_orient(n, gadj, grecs, nrec, arrows, ows)
+    torch.cuda.synchronize()
+    o0 = time.perf_counter()
+    oreps = 20
+    for _ in range(oreps):
+        gctx.pc_orient(n, gadj, grecs, nrec, arrows, ows)
+    torch.cuda.synchronize()
+    orient_ms = (time.perf_counter() - o0) / oreps * 1e3
+    Hg = pc.bits_to_dense(arrows.cpu().numpy(), n).astype(bool)
+    leg = {"workload": "CPDAG of the n=1000 skeleton (colliders + Meek R1-R3)", "ms": orient_ms, "rounds": rounds,
+           "directed": int((Hg & ~Hg.T).sum()), "bidirected": int((Hg & Hg.T).sum()) // 2,
+           "undirected": int(G.sum()) // 2 - int((Hg & ~Hg.T).sum()) - int((Hg & Hg.T).sum()) // 2}
+    if not args.no_cpu_baseline:
+        from oracle import orient as orient_ref
+        seps = pc.decode_sepsets(grecs[:max(nrec, 1)].cpu().numpy(), nrec)
+        c0 = time.perf_counter()
+        H_ref, rounds_ref = orient_ref.orient(G.astype(bool), orient_ref.sepset_lookup(seps))
+        leg["cpu_reference_s"] = time.perf_counter() - c0
+        leg["same_as_reference"] = bool(np.array_equal(H_ref, Hg) and rounds_ref == rounds)
+    out["orientation"] = leg
+
+
+def leg_scalability(args, torch, pc, semgen, out):
+    progress("paper scalability family")
+    Xs, _, alpha_s = semgen.scalability(1000, 0.1, 10000)
+    ms_s, ns_s = Xs.shape
+    Xsd = torch.from_numpy(np.ascontiguousarray(Xs)).cuda()
+    leg = {"workload": "n=1000, edge probability 0.1, positive weights, m=10000, alpha 0.01"}
+    # FP64 only: on this family nearly every FP32 test falls inside its error band (near-collinear
+    # variables), so the FP32 path would re-check almost everything in FP64 anyway.
+    for prec in ("fp64",):
+        progress(f"paper scalability: {prec}")
+        sctx = pc.Context(precision=prec)
+        sws = sctx.workspace(ns_s, ms_s)
+        sadj = sctx.adjacency(ns_s)
+        srecs, scount = sctx.sepsets(ns_s * (ns_s - 1) // 2)
+        walls = []
+        for r in range(3):
+            sst = pc.pc_run_stats()
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            try:
+                sstatus = sctx.pc_skeleton(Xsd, alpha_s, sadj, srecs, scount, sws, stats=sst)
+            except pc.PCError as e:
+                sstatus = e.status
+            torch.cuda.synchronize()
+            if r:
+                walls.append(time.perf_counter() - s0)
+        sd = sst.as_dict()
+        leg[prec] = {"ms": float(np.median(walls)) * 1e3, "status": sstatus, "levels_run": sd["levels_run"],
+                     "gpu_tests": int(sum(sd["tests"])), "rechecks": int(sum(sd["rechecks"])),
+                     "edges": int(pc.bits_to_dense(sadj.cpu().numpy(), ns_s).sum()) // 2}
+        del sws
+    out["paper_scalability"] = leg
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the learned-order and batch legs")
-    ap.add_argument("--graph-levels", type=int, default=0,
-                    help="levels recorded as level kernels before the tail kernel (0: from TAIL_TESTS)")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline leg")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the learned-order steps of the headline (for profiling; no value)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
-    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+    ap.add_argument("--write-traffic", nargs=5, metavar=("LEG", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                          "COPY_WRITE_CSV"))
     args = ap.parse_args()
     if args.write_traffic:
@@ -143,240 +542,30 @@ def main() -> int:
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return 0
+    if args.headline_only:
+        args.no_extras = True
+        args.no_cpu_baseline = True
 
     import torch
 
     import paper_1812_08491_amd as pc
     import semgen
 
-    X, sem, alpha = semgen.workload(WORKLOAD)
-    m, n = X.shape
+    progress("torch imported")
     torch.cuda.set_device(0)
-    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
-
-    # -- the skeleton through pc_skeleton on the stream, HIP events around every kernel phase -------
-    stream = torch.cuda.current_stream()
-    ctx = pc.Context(stream=stream, precision="fp32", timing=1 | 2 | 4 | 8 | 16)
-    ws = ctx.workspace(n, m)
-    adj = ctx.adjacency(n)
-    recs, count = ctx.sepsets(n * (n - 1) // 2)
-    st = pc.pc_run_stats()
-    for _ in range(args.warmup):
-        ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st)
-    torch.cuda.synchronize()
-    runs = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        status = ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, stats=st)
-        runs.append(st.as_dict())
-    torch.cuda.synchronize()
-    stream_sec = (time.perf_counter() - t0) / args.steps
-    assert status == 0, pc.status_str(status)
-    L = runs[-1]["levels_run"]
-    # Levels with many tests go to the level kernels, the rest to the tail kernel (levels <= 8).
-    big = [l for l in range(1, L) if runs[-1]["tests"][l] > TAIL_TESTS]
-    graph_levels = args.graph_levels or max([1] + big)
-    if L - 1 > TAIL_MAX_LEVEL:
-        graph_levels = max(graph_levels, L - 1)
-
-    # -- timed region: graph replays of the whole skeleton ----------------------------------------
-    gstream = torch.cuda.Stream()
-    with torch.cuda.stream(gstream):
-        # Levels 1 .. graph_levels as level kernels, then the tail kernel (with a budget that
-        # covers any level here) up to level 8; a replay needing more would be continued by
-        # pc_graph_results, which the check below rules out for the timed replays.
-        gctx = pc.Context(stream=gstream, precision="fp32", graph_levels=graph_levels, tail_tests=1 << 30)
-        gadj = gctx.adjacency(n)
-        grecs, gcount = gctx.sepsets(n * (n - 1) // 2)
-        probs = gctx.problems([(Xd, alpha, -1, gadj, grecs, gcount)])
-        gws = gctx.batch_workspace(probs)
-        graph = gctx.pc_batch_capture(probs, gws)
-        for _ in range(args.warmup):
-            graph.pc_graph_launch()
-        torch.cuda.synchronize()
-        g0 = time.perf_counter()
-        for _ in range(args.steps):
-            graph.pc_graph_launch()
-        torch.cuda.synchronize()
-        sec_per_step = (time.perf_counter() - g0) / args.steps
-        gst = (pc.pc_run_stats * 1)()
-        r, gstatus = graph.pc_graph_results(gst)
-        graph.close()
-    assert r == 0 and gstatus[0] == 0, (r, gstatus)
-    G = pc.bits_to_dense(gadj.cpu().numpy(), n)
-    gstats = gst[0].as_dict()
-    assert gstats["levels_run"] - 1 <= max(graph_levels, TAIL_MAX_LEVEL), "the recorded graph did not cover every level"
-
-    gpu_tests = int(sum(gstats["tests"]))
-
-    same_as_graph = bool(np.array_equal(pc.bits_to_dense(adj.cpu().numpy(), n), G))
-
-    def mean_of(key, lvl=None):
-        v = [d[key] if lvl is None else d[key][lvl] for d in runs]
-        return float(np.mean(v))
-
-    level_ms = [mean_of("level_ms", l) for l in range(L)]
-    kernel_ms = {"prep": mean_of("prep_ms"), "corr_gemm_level0": mean_of("corr_ms"),
-                 "compact_plan": [mean_of("compact_ms", l) for l in range(L)],
-                 "level": level_ms, "recheck": [mean_of("recheck_ms", l) for l in range(L)]}
-
     out = {
-        "metric": "CI tests/sec and skeleton wall time (PC-stable skeleton, identical to the FP64 oracle)",
-        "value": None,
-        "unit": "CI tests/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": sec_per_step * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
+        "metric": "CI tests/sec and skeleton wall time (learned-order vs plain, identical skeleton)",
+        "value": None, "unit": "CI tests/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic linear-Gaussian SEM (seeded), resident in HBM",
-        "config": {"workload": "pc_stable_skeleton_n1000_deg4_m500_alpha0.01_fp32_recheck",
-                   "n": n, "m": m, "expected_degree": 4, "alpha": alpha, "precision": "fp32+fp64 recheck",
-                   "step": "one hipGraph replay of the whole skeleton",
-                   "graph_levels": graph_levels, "tail_from_level": graph_levels + 1,
-                   "levels_run": gstats["levels_run"], "edges": int(G.sum()) // 2},
-        "gpu_tests_per_step": gpu_tests,
-        "gpu_executed_tests_per_s": gpu_tests / sec_per_step,
-        "per_level_tests": gstats["tests"][:gstats["levels_run"]],
-        "rechecks": gstats["rechecks"][:gstats["levels_run"]],
-        "stream_ms_per_step": stream_sec * 1e3,
-        "stream_same_skeleton": same_as_graph,
-        "kernel_ms": kernel_ms,
     }
-
-    # -- roofline of the dominant kernel: the level-1 CI tests (gather bound: per test C_ij and the
-    #    entry C[j,S], 4 (l + 1) = 8 bytes at l = 1) --------------------------------------------------
-    t1 = runs[-1]["tests"][1]
-    l1_s = level_ms[1] * 1e-3
-    ach = t1 * 8.0 / l1_s / 1e9
-    traffic = measured_traffic()
-    out["roofline"] = {"kernel": "k_level<float,1> (level-1 CI tests)", "bound": "hbm",
-                       "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                       "traffic": traffic, "algorithmic_bytes": t1 * 8.0, "launch_ms": level_ms[1]}
-    corr_s = kernel_ms["corr_gemm_level0"] * 1e-3
-    fl = float(m) * n * (n - 1) / corr_s / 1e12
-    out["roofline_corr"] = {"kernel": "k_corr<fp32> (SYRK + level-0 test)", "bound": "mfma", "achieved": fl,
-                            "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": fl / PEAK_FP32_MFMA_TFLOPS,
-                            "launch_ms": kernel_ms["corr_gemm_level0"]}
-
+    headline(args, torch, pc, semgen, out)
     if not args.no_extras:
-        # -- plain vs learned conditioning-set order (same data, identical skeleton required) ------
-        from paper_1812_08491_amd import learn
-        Xa, _, alpha_a = semgen.workload(APPLY_WORKLOAD)
-        # The shared-set (row) model orders level 1, where this workload's tests are: each node's
-        # ROW_TOP best-scored candidates are tested first as sets {k}, then the rest.
-        cmp = learn.compare_orders(Xa, alpha_a, None, row_params=learn.load_weights(learn.ROW_WEIGHTS),
-                                   row_top=ROW_TOP, repeats=9)
-        tp, tl = sum(cmp["plain"]["tests"]), sum(cmp["learned"]["tests"])
-        out["learned_vs_plain"] = {
-            "workload": "n2000_deg10_m1000_alpha0.01_fp32", "same_skeleton": cmp["same_skeleton"],
-            "plain_ms": cmp["plain"]["wall_ms"], "learned_ms": cmp["learned"]["wall_ms"],
-            "plain_tests": tp, "learned_tests": tl,
-            "plain_tests_per_s": tp / (cmp["plain"]["wall_ms"] * 1e-3),
-            "learned_tests_per_s": tl / (cmp["learned"]["wall_ms"] * 1e-3),
-            "probe_tests": sum(cmp["learned"]["probe_tests"]),
-            "probe_removed": sum(cmp["learned"]["probe_removed"]),
-            "level1_tests": [cmp["plain"]["tests"][1], cmp["learned"]["tests"][1]],
-            "order": {"form": "shared-set (row) model at level 1", "row_top": ROW_TOP,
-                      "weights": "weights/order_row_mlp_n200.npy"}}
-        # -- 256 uneven datasets in one captured graph --------------------------------------------
-        batch = semgen.batch_problems(256)
-        bstream = torch.cuda.Stream()
-        with torch.cuda.stream(bstream):
-            bctx = pc.Context(stream=bstream, precision="fp32")
-            items = []
-            for Xb, _, ab in batch:
-                mb, nb = Xb.shape
-                rb, cb = bctx.sepsets(nb * (nb - 1) // 2)
-                items.append((torch.from_numpy(np.ascontiguousarray(Xb)).cuda(), ab, -1, bctx.adjacency(nb), rb, cb))
-            bprobs = bctx.problems(items)
-            bws = bctx.batch_workspace(bprobs)
-            bgraph = bctx.pc_batch_capture(bprobs, bws)
-            bst = (pc.pc_run_stats * len(items))()
-            for _ in range(2):
-                bgraph.pc_graph_launch()
-                bgraph.pc_graph_results(bst)
-            torch.cuda.synchronize()
-            reps = max(3, args.steps // 5)
-            b0 = time.perf_counter()
-            for _ in range(reps):
-                # a replay and its results: levels some datasets need beyond the recorded ones
-                # run inside pc_graph_results, so both are timed
-                bgraph.pc_graph_launch()
-                br, bstatus = bgraph.pc_graph_results(bst)
-            torch.cuda.synchronize()
-            bms = (time.perf_counter() - b0) / reps * 1e3
-            bgraph.close()
-        out["batch256_graph"] = {"workload": "256 datasets, n~U[20,400], degree~U[2,8], m~U[200,5000], alpha 0.01",
-                                 "ms_per_batch": bms, "status": br,
-                                 "tests": int(sum(sum(s.as_dict()["tests"]) for s in bst))}
-        # -- orientation of the bench skeleton into a CPDAG (pc_orient) ----------------------------
-        nrec = int(gcount.item())
-        arrows = gctx.adjacency(n)
-        ows = gctx.orient_workspace(n)
-        rounds = gctx.pc_orient(n, gadj, grecs, nrec, arrows, ows)
-        torch.cuda.synchronize()
-        o0 = time.perf_counter()
-        oreps = 20
-        for _ in range(oreps):
-            gctx.pc_orient(n, gadj, grecs, nrec, arrows, ows)
-        torch.cuda.synchronize()
-        orient_ms = (time.perf_counter() - o0) / oreps * 1e3
-        Hg = pc.bits_to_dense(arrows.cpu().numpy(), n).astype(bool)
-        out["orientation"] = {"workload": "CPDAG of the bench skeleton (colliders + Meek R1-R3)",
-                              "ms": orient_ms, "rounds": rounds,
-                              "directed": int((Hg & ~Hg.T).sum()), "bidirected": int((Hg & Hg.T).sum()) // 2,
-                              "undirected": int(G.sum()) // 2 - int((Hg & ~Hg.T).sum()) - int((Hg & Hg.T).sum()) // 2}
-
-    if not args.no_extras:
-        # -- the paper's scalability family: n = 1000, edge probability 0.1, m = 10000, FP64 --------
-        Xs, _, alpha_s = semgen.scalability(1000, 0.1, 10000)
-        ms_s, ns_s = Xs.shape
-        sctx = pc.Context(precision="fp64")
-        sws = sctx.workspace(ns_s, ms_s)
-        sadj = sctx.adjacency(ns_s)
-        srecs, scount = sctx.sepsets(ns_s * (ns_s - 1) // 2)
-        Xsd = torch.from_numpy(np.ascontiguousarray(Xs)).cuda()
-        walls = []
-        for r in range(4):
-            sst = pc.pc_run_stats()
-            torch.cuda.synchronize()
-            s0 = time.perf_counter()
-            sstatus = sctx.pc_skeleton(Xsd, alpha_s, sadj, srecs, scount, sws, stats=sst)
-            torch.cuda.synchronize()
-            if r:
-                walls.append(time.perf_counter() - s0)
-        sd = sst.as_dict()
-        out["paper_scalability"] = {
-            "workload": "n=1000, edge probability 0.1, positive weights, m=10000, alpha 0.01, fp64",
-            "ms": float(np.median(walls)) * 1e3, "status": sstatus, "levels_run": sd["levels_run"],
-            "gpu_tests": int(sum(sd["tests"])), "edges": int(pc.bits_to_dense(sadj.cpu().numpy(), ns_s).sum()) // 2}
-        del Xsd, sws
-
-    if not args.no_cpu_baseline:
-        if "orientation" in out:
-            # the orientation reference on the same skeleton and SepSets, timed and compared
-            from oracle import orient as orient_ref
-            seps = pc.decode_sepsets(grecs[:max(nrec, 1)].cpu().numpy(), nrec)
-            c0 = time.perf_counter()
-            H_ref, rounds_ref = orient_ref.orient(G.astype(bool), orient_ref.sepset_lookup(seps))
-            out["orientation"]["cpu_reference_s"] = time.perf_counter() - c0
-            out["orientation"]["same_as_reference"] = bool(np.array_equal(H_ref, Hg) and rounds_ref == rounds)
-        ref, cpu_sec, reps = cpu_baseline(X, alpha)
-        canonical = int(sum(ref.tests))
-        out["value"] = canonical / sec_per_step
-        out["canonical_tests_per_step"] = canonical
-        out["skeleton_equal_to_oracle"] = bool(np.array_equal(G, ref.G))
-        out["cpu_baseline"] = {"value": canonical / cpu_sec, "unit": "CI tests/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"whole workload (same input), {reps} runs, {cpu_sec:.3f} s each",
-                               "wall_s_per_skeleton": cpu_sec}
-    else:
-        out["value"] = gpu_tests / sec_per_step
-        out["note"] = "value counts GPU-executed tests (cpu baseline skipped)"
+        c2 = leg_c2_graph(args, torch, pc, semgen, out)
+        leg_orient(args, torch, pc, out, c2)
+        leg_c3(args, torch, pc, semgen, out)
+        leg_batch(args, torch, pc, semgen, out)
+        leg_scalability(args, torch, pc, semgen, out)
     print(json.dumps(out))
     return 0
 

@@ -174,6 +174,27 @@ pc_status pc_corr(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alp
 pc_status pc_level(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, uint64_t *adj,
                    const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes);
 
+/* Levels on a correlation matrix the caller supplies instead of data. The CI test of Sec. 4.3
+ * (Eq. 3-6) needs only C and the sample size, so these calls take C and a sample size m given as a
+ * double: a population correlation matrix with a nominal m such as 1e20 runs the tests in the
+ * large-sample limit, where PC-stable returns the skeleton of the true DAG and every SepSet
+ * d-separates its pair (Sec. 2.4). FP64 only: the context's precision must be PC_PREC_FP64
+ * (PC_ERR_UNSUPPORTED otherwise), since there are no data to re-check FP32 decisions against.
+ *   C        device n x n FP64 row-major, symmetric, finite, C_aa = 1; read only (copied into the
+ *            workspace). Pair (i,j) is decided on C[min(i,j), max(i,j)].
+ *   m        sample size in tau_l = z / sqrt(m - l - 3) (Eq. 6); must be > 0 and finite. A level with
+ *            m - l - 3 <= 0 is not run (PC_WARN_SAMPLE_LIMIT), as in pc_level.
+ *   ws       device workspace of at least pc_corr_workspace_bytes(n, opt) bytes, 256-byte aligned.
+ * pc_level_corr runs one level l >= 1 on the caller's G (in/out, as pc_level); pc_skeleton_corr runs
+ * level 0 on C and then the level loop of pc_skeleton (adj_out, sep, st, max_level as there). Both
+ * synchronise the stream. */
+size_t pc_corr_workspace_bytes(int64_t n, const pc_options *opt);
+pc_status pc_level_corr(pc_ctx *ctx, int level, const double *C, int64_t n, double m, double alpha,
+                        uint64_t *adj, const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes);
+pc_status pc_skeleton_corr(pc_ctx *ctx, const double *C, int64_t n, double m, double alpha, int max_level,
+                           uint64_t *adj_out, const pc_sepset *sep, pc_run_stats *st, void *ws,
+                           size_t ws_bytes);
+
 /* The whole skeleton step (Algorithm 1 / Algorithm 2): pc_corr, then levels 1, 2, ... while the
  * maximum degree of G minus 1 is >= l (and l <= max_level if max_level >= 0). The stop rule is
  * evaluated on the device; the host reads the maximum degree once, after planning level 2, to
@@ -261,6 +282,11 @@ typedef struct {
     int32_t row_top;      /* level 1, shared-set order: the row_top best-scored candidates k of
                              every node are tested first, as sets {k} against all its edges, then
                              the remaining ones (1..16; 0 = off) */
+    int32_t row_rank;     /* what ranks the candidates of the shared-set order: 0 = the row model
+                             (row_params), 1 = |C_ik| alone (row_params unused, may be NULL) */
+    int32_t row_short;    /* row model only: 0 = it scores every candidate of a node; K in
+                             row_top..64 = it scores only the K candidates of largest |C_ik| (ties:
+                             lower position first), and the row_top chosen come from those */
 } pc_order;
 
 /* Workspace of pc_skeleton_ordered (the probe keeps its features and scores on chip, so this is
@@ -300,6 +326,19 @@ pc_status pc_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha
 pc_status pc_row_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, const uint64_t *adj,
                           float *feats, float *labels, int32_t *meta, int64_t cap, int64_t *rows_out,
                           void *ws, size_t ws_bytes);
+
+/* The ranking step of the shared-set order alone, for checking the scoring kernel: for the
+ * level-1 snapshot adj (device bit matrix, not modified) it scores the candidates of every node as
+ * pc_skeleton_ordered does (order: row_params / row_rank / row_short / row_top) and runs no test.
+ *   scores  device n x n FP32: scores[i*n + k] = score of candidate k of node i (the model's BF16
+ *           MLP output, or |C_ik| for row_rank 1; -inf outside the short list). Entries of
+ *           non-neighbours, and rows that are not ranked (degree < 2 or > 1024), are not written.
+ *   top     device n x row_top int32: the chosen candidates of node i, best first (ties: lower
+ *           position in the ascending neighbour list); -1 past the node's degree. Rows of degree
+ *           < 2 are not written.
+ *   ws      workspace of a preceding pc_corr on the same data. Synchronises the stream. */
+pc_status pc_row_scores(pc_ctx *ctx, int64_t n, int64_t m, double alpha, const uint64_t *adj, const pc_order *order,
+                        float *scores, int32_t *top, void *ws, size_t ws_bytes);
 
 /* MLP kernels (stream ordered, asynchronous), exported for training and gradient checks.
  *   forward : scores[r] = MLP(X[r]) for rows x 8 inputs; act (optional, rows x 128) keeps the

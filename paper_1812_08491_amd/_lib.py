@@ -58,7 +58,8 @@ PC_MLP_PARAMS = 4801
 
 class pc_order(ct.Structure):
     _fields_ = [("params", ct.c_void_p), ("row_params", ct.c_void_p), ("min_level", ct.c_int32),
-                ("max_level", ct.c_int32), ("top", ct.c_int32), ("row_top", ct.c_int32)]
+                ("max_level", ct.c_int32), ("top", ct.c_int32), ("row_top", ct.c_int32),
+                ("row_rank", ct.c_int32), ("row_short", ct.c_int32)]
 
 
 class pc_problem(ct.Structure):
@@ -134,6 +135,14 @@ def lib() -> ct.CDLL:
         L.pc_skeleton.argtypes = [vp, vp, i64, i64, ct.c_double, ct.c_int, vp, ct.POINTER(pc_sepset),
                                   ct.POINTER(pc_run_stats), vp, ct.c_size_t]
         L.pc_skeleton.restype = ct.c_int
+        L.pc_corr_workspace_bytes.argtypes = [i64, ct.POINTER(pc_options)]
+        L.pc_corr_workspace_bytes.restype = ct.c_size_t
+        L.pc_level_corr.argtypes = [vp, ct.c_int, vp, i64, ct.c_double, ct.c_double, vp, ct.POINTER(pc_sepset),
+                                    ct.POINTER(pc_run_stats), vp, ct.c_size_t]
+        L.pc_level_corr.restype = ct.c_int
+        L.pc_skeleton_corr.argtypes = [vp, vp, i64, ct.c_double, ct.c_double, ct.c_int, vp, ct.POINTER(pc_sepset),
+                                       ct.POINTER(pc_run_stats), vp, ct.c_size_t]
+        L.pc_skeleton_corr.restype = ct.c_int
         L.pc_sync_status.argtypes = [vp, vp, ct.c_size_t]
         L.pc_sync_status.restype = ct.c_int
         L.pc_comb_unrank.argtypes = [ct.c_int32, ct.c_int32, ct.c_uint64, ct.c_int32,
@@ -167,6 +176,8 @@ def lib() -> ct.CDLL:
         L.pc_row_features.argtypes = [vp, ct.c_int, i64, i64, ct.c_double, vp, fp, fp, vp, i64, ct.POINTER(i64), vp,
                                       ct.c_size_t]
         L.pc_row_features.restype = ct.c_int
+        L.pc_row_scores.argtypes = [vp, i64, i64, ct.c_double, vp, ct.POINTER(pc_order), fp, vp, vp, ct.c_size_t]
+        L.pc_row_scores.restype = ct.c_int
         L.pc_orient_workspace_bytes.argtypes = [i64]
         L.pc_orient_workspace_bytes.restype = ct.c_size_t
         L.pc_orient.argtypes = [vp, i64, vp, vp, i64, vp, vp, ct.c_size_t, ct.POINTER(ct.c_int32)]
@@ -193,7 +204,8 @@ EXPORTED = ["pc_create", "pc_destroy", "pc_default_options", "pc_workspace_bytes
             "pc_abi_size", "pc_status_str", "pc_batch_workspace_bytes", "pc_batch_skeleton",
             "pc_batch_capture", "pc_graph_launch", "pc_graph_results", "pc_graph_destroy",
             "pc_ordered_workspace_bytes", "pc_skeleton_ordered", "pc_features", "pc_row_features", "pc_mlp_forward",
-            "pc_mlp_backward", "pc_mlp_bce", "pc_mlp_adam", "pc_orient_workspace_bytes", "pc_orient"]
+            "pc_mlp_backward", "pc_mlp_bce", "pc_mlp_adam", "pc_orient_workspace_bytes", "pc_orient",
+            "pc_corr_workspace_bytes", "pc_level_corr", "pc_skeleton_corr", "pc_row_scores"]
 
 
 def _check_abi(L: ct.CDLL) -> None:
@@ -332,6 +344,32 @@ class Context:
                                         ct.byref(stats) if stats is not None else None,
                                         ct.c_void_p(ws.data_ptr()), ws.numel()), "pc_skeleton")
 
+    # -- a caller's correlation matrix (FP64 contexts) ----------------------------------------
+    def corr_workspace(self, n: int):
+        torch = _torch()
+        nbytes = int(lib().pc_corr_workspace_bytes(n, ct.byref(self.opt)))
+        return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+    def pc_level_corr(self, level: int, C, m: float, alpha: float, adj, recs, count, ws,
+                      stats: pc_run_stats | None = None) -> int:
+        n = C.shape[0]
+        assert C.is_cuda and C.dtype == _torch().float64 and C.is_contiguous() and C.shape == (n, n)
+        sep = pc_sepset(recs.data_ptr(), recs.shape[0], count.data_ptr())
+        return _check(lib().pc_level_corr(self.h, level, ct.c_void_p(C.data_ptr()), n, float(m), alpha,
+                                          ct.c_void_p(adj.data_ptr()), ct.byref(sep),
+                                          ct.byref(stats) if stats is not None else None,
+                                          ct.c_void_p(ws.data_ptr()), ws.numel()), "pc_level_corr")
+
+    def pc_skeleton_corr(self, C, m: float, alpha: float, adj, recs, count, ws, max_level: int = -1,
+                         stats: pc_run_stats | None = None) -> int:
+        n = C.shape[0]
+        assert C.is_cuda and C.dtype == _torch().float64 and C.is_contiguous() and C.shape == (n, n)
+        sep = pc_sepset(recs.data_ptr(), recs.shape[0], count.data_ptr())
+        return _check(lib().pc_skeleton_corr(self.h, ct.c_void_p(C.data_ptr()), n, float(m), alpha, max_level,
+                                             ct.c_void_p(adj.data_ptr()), ct.byref(sep),
+                                             ct.byref(stats) if stats is not None else None,
+                                             ct.c_void_p(ws.data_ptr()), ws.numel()), "pc_skeleton_corr")
+
     # -- batches ---------------------------------------------------------------------------------
     @staticmethod
     def problems(items) -> "ct.Array":
@@ -368,16 +406,21 @@ class Context:
     # -- learned ordering ----------------------------------------------------------------------
     @staticmethod
     def order(params=None, min_level: int = 2, top: int = 4, max_level: int = 0, row_params=None,
-              row_top: int = 0) -> pc_order:
+              row_top: int = 0, row_rank: str = "model", row_short: int = 0) -> pc_order:
         """Learned order: the probe pass of the edge model `params` at levels min_level .. max_level
-        (0 = 8) that are <= top, and/or the shared-set order of the row model `row_params` at level 1
-        (its row_top best candidates per node first)."""
+        (0 = 8) that are <= top, and/or the shared-set order at level 1 (the row_top best candidates
+        per node first), ranked by the row model `row_params` (row_rank "model"; with row_short > 0
+        it scores only the row_short candidates of largest |C_ik|) or by |C_ik| alone
+        (row_rank "abs")."""
         torch = _torch()
         for p in (params, row_params):
             assert p is None or (p.is_cuda and p.dtype == torch.float32 and p.numel() == PC_MLP_PARAMS)
-        return pc_order(params.data_ptr() if params is not None else None,
-                        row_params.data_ptr() if row_params is not None else None,
-                        min_level, max_level, top, row_top)
+        rank = {"model": 0, "abs": 1}[row_rank]
+        o = pc_order(params.data_ptr() if params is not None else None,
+                     row_params.data_ptr() if row_params is not None else None,
+                     min_level, max_level, top, row_top, rank, row_short)
+        o._keep = (params, row_params)    # the struct holds raw pointers: keep the tensors alive
+        return o
 
     def ordered_workspace(self, n: int, m: int, order: pc_order):
         torch = _torch()
@@ -425,6 +468,14 @@ class Context:
             return -int(rows.value)
         _check(r, "pc_row_features")
         return int(rows.value)
+
+    def pc_row_scores(self, n: int, m: int, alpha: float, adj, order: pc_order, scores, top, ws) -> int:
+        torch = _torch()
+        assert scores.is_cuda and scores.dtype == torch.float32 and scores.shape == (n, n)
+        assert top.is_cuda and top.dtype == torch.int32 and top.shape == (n, order.row_top)
+        return _check(lib().pc_row_scores(self.h, n, m, alpha, ct.c_void_p(adj.data_ptr()), ct.byref(order),
+                                          ct.c_void_p(scores.data_ptr()), ct.c_void_p(top.data_ptr()),
+                                          ct.c_void_p(ws.data_ptr()), ws.numel()), "pc_row_scores")
 
     def orient_workspace(self, n: int):
         torch = _torch()

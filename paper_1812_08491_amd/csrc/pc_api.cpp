@@ -236,8 +236,10 @@ Plan make_plan(const int64_t *ns, const int64_t *ms, int count, const pc_options
 }
 
 // Host image of the problem table for the given workspace base.
+// m_nominal > 0 replaces the sample size in the thresholds tau_l (a correlation matrix given by the
+// caller: there is no data, and m may be a nominal large-sample value).
 void fill_probs(const pc_ctx *ctx, const Plan &L, unsigned char *ws, const pc_problem *pp,
-                std::vector<Prob> &out) {
+                std::vector<Prob> &out, double m_nominal = -1.0) {
     out.assign(L.count, Prob{});
     for (int d = 0; d < L.count; ++d) {
         Prob &P = out[d];
@@ -263,8 +265,9 @@ void fill_probs(const pc_ctx *ctx, const Plan &L, unsigned char *ws, const pc_pr
         P.rec_count = reinterpret_cast<long long *>(pp[d].sep.count);
         P.max_level = pp[d].max_level >= 0 ? std::min(pp[d].max_level, PC_MAX_LEVEL + 1) : PC_MAX_LEVEL + 1;
         const double z = z_of_alpha(pp[d].alpha);
+        const double m_tau = m_nominal > 0.0 ? m_nominal : (double)P.m;
         for (int l = 0; l < kLevels; ++l) {
-            P.tau[l] = tau_of(z, (double)P.m, l);
+            P.tau[l] = tau_of(z, m_tau, l);
             P.t[l] = std::isnan(P.tau[l]) ? 0.0f : (float)std::tanh(P.tau[l]);
             const double eps = eps_c_of(L.prec, P.mp) + (4.0 * l + 16.0) * kU32;
             P.band[l] = (float)((double)ctx->opt.margin_scale * eps);
@@ -391,6 +394,9 @@ struct OrderRun {
 
 constexpr int kProbeMaxLevel = 8;
 
+// Whether the shared-set order runs at level 1: a row model, or the |C_ik| ranking.
+bool row_order_on(const pc_order *o) { return o->row_params || (o->row_rank == 1 && o->row_top > 0); }
+
 // Whether level l runs the probe pass of the ordering.
 bool probe_level(const pc_order *o, int level) {
     if (!o->params) return false;
@@ -424,15 +430,17 @@ pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, co
     const int R = ranks_per_item(ctx, level);
     // Probe pass of the learned ordering: the best-scored subsets of every edge, before the plain
     // enumeration of the same level.
-    if (ord && probe_level(ord->order, level) && !(ord->order->row_params && level == 1))
+    const bool row_order = ord && level == 1 && row_order_on(ord->order);
+    if (ord && probe_level(ord->order, level) && !row_order)
         PC_HIP(launch_probe(s, b, level, ord->order->params, ord->order->top, ctx->num_cu));
     if (timed(ctx, 2, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][0], s));
-    if (ord && ord->order->row_params && level == 1) {
+    if (row_order) {
         // Shared-set order: each row's best-scored candidates move to the front of its neighbour
         // list and their sets are tested first (in the ordering kernel), then the level kernel runs
         // the remaining ranks; together they cover every set of the level once, on the same G'.
         const int T = ord->order->row_top;
-        PC_HIP(launch_row_order(s, b, level, ord->order->row_params, T, ctx->num_cu));
+        PC_HIP(launch_row_order(s, b, level, ord->order->row_params, T, ord->order->row_rank,
+                                ord->order->row_short, ctx->num_cu));
         Batch bm = b;
         bm.rank_lo = (unsigned long long)T;
         PC_HIP(launch_window(s, bm, level, R));
@@ -620,10 +628,19 @@ Plan plan_of(const pc_problem *pp, int count, const pc_options &o) {
 
 // Every launch of the batched skeletons (the table must already be uploaded).
 pc_status enqueue_skeletons(pc_ctx *ctx, const pc_problem *pp, int count, const Plan &L,
-                            unsigned char *ws, bool capturing, const pc_order *order = nullptr) {
+                            unsigned char *ws, bool capturing, const pc_order *order = nullptr,
+                            bool given_c = false) {
     const Batch b = make_batch(ctx, L, ws);
-    pc_status s = enqueue_corr(ctx, b, L, capturing);
-    if (s != PC_OK) return s;
+    pc_status s = PC_OK;
+    if (given_c) {
+        // C is already in the workspace: level 0 reads it directly.
+        PC_HIP(launch_init(ctx->stream, b));
+        if (timed(ctx, 1, capturing)) PC_HIP(hipEventRecord(ctx->ev_corr[0], ctx->stream));
+        PC_HIP(launch_level0_given(ctx->stream, b));
+        if (timed(ctx, 1, capturing)) PC_HIP(hipEventRecord(ctx->ev_corr[1], ctx->stream));
+    } else if ((s = enqueue_corr(ctx, b, L, capturing)) != PC_OK) {
+        return s;
+    }
     const OrderRun ord{order, &L, ws};
     const OrderRun *po = order ? &ord : nullptr;
     const int top = levels_to_enqueue(pp, count);
@@ -654,11 +671,15 @@ pc_status enqueue_skeletons(pc_ctx *ctx, const pc_problem *pp, int count, const 
 }
 
 bool valid_order(const pc_order *o) {
-    if (!o || (!o->params && !o->row_params)) return false;
+    if (!o || (!o->params && !row_order_on(o))) return false;
     if (o->params && !(o->min_level >= 1 && o->min_level <= kProbeMaxLevel && o->top >= 1 && o->top <= 8 &&
                        (o->max_level == 0 || (o->max_level >= o->min_level && o->max_level <= kProbeMaxLevel))))
         return false;
-    if (o->row_params && !(o->row_top >= 1 && o->row_top <= 16)) return false;
+    if (o->row_rank != 0 && o->row_rank != 1) return false;
+    if (row_order_on(o)) {
+        if (!(o->row_top >= 1 && o->row_top <= 16)) return false;
+        if (o->row_short != 0 && (o->row_rank != 0 || o->row_short < o->row_top || o->row_short > 64)) return false;
+    }
     return true;
 }
 
@@ -740,6 +761,11 @@ pc_status pc_create(pc_ctx **out, void *stream, const pc_options *opt) {
         c->recheck_grid = (nb > 0 ? std::min(nb, 4) : 4) * c->num_cu;
     }
     if (ok && ensure_binom(c, 8191) != PC_OK) ok = false;
+    // Pinned staging for problem tables, so that single-problem calls need no allocation later.
+    if (ok) {
+        if (hipHostMalloc(&c->staging, (size_t)1 << 16, hipHostMallocDefault) == hipSuccess) c->staging_bytes = (size_t)1 << 16;
+        else ok = false;
+    }
     if (ok && hipStreamSynchronize(c->stream) != hipSuccess) ok = false;
     if (!ok) {
         pc_destroy(c);
@@ -804,8 +830,15 @@ pc_status pc_sync_status(pc_ctx *ctx, void *ws, size_t ws_bytes) {
     return (pc_status)err;
 }
 
-pc_status pc_level(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, uint64_t *adj,
-                   const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes) {
+}  // extern "C"
+
+namespace {
+
+// One caller-driven level (pc_level, pc_level_corr). C_given: a caller's FP64 correlation matrix,
+// copied into the workspace first (then m_nominal sets the thresholds).
+pc_status level_common(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, uint64_t *adj,
+                       const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes,
+                       const double *C_given, double m_nominal) {
     if (!ctx || !adj || !sep || !sep->count || (!sep->recs && sep->cap > 0)) return PC_ERR_INVALID_ARG;
     if (level < 1 || level > PC_MAX_LEVEL) return PC_ERR_INVALID_ARG;
     if (!(alpha > 0.0 && alpha < 1.0)) return PC_ERR_INVALID_ARG;
@@ -824,8 +857,11 @@ pc_status pc_level(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, u
     p.adj_out = adj;
     p.sep = *sep;
     std::vector<Prob> probs;
-    fill_probs(ctx, L, w, &p, probs);
+    fill_probs(ctx, L, w, &p, probs, m_nominal);
     if ((s = upload_table(ctx, L, w, probs)) != PC_OK) return s;
+    if (C_given)
+        PC_HIP(hipMemcpyAsync(w + L.reg[0].c, C_given, sizeof(double) * (size_t)n * (size_t)n,
+                              hipMemcpyDeviceToDevice, ctx->stream));
     const Batch b = make_batch(ctx, L, w);
     PC_HIP(launch_rearm(ctx->stream, b));
     if ((s = enqueue_level(ctx, b, level, false)) != PC_OK) return s;
@@ -850,6 +886,71 @@ pc_status pc_level(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, u
     if (r == PC_ERR_SEPSET_CAPACITY) return r;
     if (std::isnan(P.tau[level]) && P.maxdeg[level] >= level + 1) return PC_WARN_SAMPLE_LIMIT;
     return PC_OK;
+}
+
+// Sample count of the workspace plan of a given-C call (no data is stored).
+constexpr int64_t kGivenPlanM = 4;
+
+pc_status check_given(const pc_ctx *ctx, const double *C, double m) {
+    if (!ctx || !C) return PC_ERR_INVALID_ARG;
+    if (!(m > 0.0) || !std::isfinite(m)) return PC_ERR_INVALID_ARG;
+    if (ctx->opt.precision != PC_PREC_FP64) return PC_ERR_UNSUPPORTED;
+    return PC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pc_status pc_level(pc_ctx *ctx, int level, int64_t n, int64_t m, double alpha, uint64_t *adj,
+                   const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes) {
+    return level_common(ctx, level, n, m, alpha, adj, sep, st, ws, ws_bytes, nullptr, -1.0);
+}
+
+size_t pc_corr_workspace_bytes(int64_t n, const pc_options *opt) { return pc_workspace_bytes(n, kGivenPlanM, opt); }
+
+pc_status pc_level_corr(pc_ctx *ctx, int level, const double *C, int64_t n, double m, double alpha,
+                        uint64_t *adj, const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes) {
+    pc_status s = check_given(ctx, C, m);
+    if (s != PC_OK) return s;
+    return level_common(ctx, level, n, kGivenPlanM, alpha, adj, sep, st, ws, ws_bytes, C, m);
+}
+
+pc_status pc_skeleton_corr(pc_ctx *ctx, const double *C, int64_t n, double m, double alpha, int max_level,
+                           uint64_t *adj_out, const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes) {
+    pc_status s = check_given(ctx, C, m);
+    if (s != PC_OK) return s;
+    if (!adj_out || !sep || !sep->count || (!sep->recs && sep->cap > 0)) return PC_ERR_INVALID_ARG;
+    if (!(alpha > 0.0 && alpha < 1.0)) return PC_ERR_INVALID_ARG;
+    if ((s = check_shape(n, kGivenPlanM)) != PC_OK) return s;
+    const auto t0 = std::chrono::steady_clock::now();
+    int64_t mp = kGivenPlanM;
+    const Plan L = make_plan(&n, &mp, 1, ctx->opt);
+    if ((s = check_ws(ws, ws_bytes, L)) != PC_OK) return s;
+    if ((s = ensure_binom(ctx, n)) != PC_OK) return s;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    pc_problem p{};
+    p.m = kGivenPlanM;
+    p.n = n;
+    p.alpha = alpha;
+    p.max_level = max_level;
+    p.adj_out = adj_out;
+    p.sep = *sep;
+    std::vector<Prob> table;
+    fill_probs(ctx, L, w, &p, table, m);
+    if ((s = upload_table(ctx, L, w, table)) != PC_OK) return s;
+    PC_HIP(hipMemcpyAsync(w + L.reg[0].c, C, sizeof(double) * (size_t)n * (size_t)n, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    if ((s = enqueue_skeletons(ctx, &p, 1, L, w, false, nullptr, true)) != PC_OK) return s;
+    std::vector<Prob> host;
+    pc_status status = PC_OK;
+    const pc_status r = collect(ctx, L.table, L.st, 1, w, st, &status, host);
+    if (r == PC_ERR_HIP) return r;
+    if (st) {
+        fill_times(ctx, st, ctx->top_run);
+        st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
 }
 
 pc_status pc_skeleton(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alpha,
@@ -1094,6 +1195,20 @@ pc_status pc_row_features(pc_ctx *ctx, int level, int64_t n, int64_t m, double a
     int *skip = reinterpret_cast<int *>(w + L.nitems);
     PC_HIP(launch_row_features(ctx->stream, b, level, foff, cap, skip, feats, labels, meta));
     return feature_rows(ctx, foff, L.total_rows, cap, rows_out);
+}
+
+pc_status pc_row_scores(pc_ctx *ctx, int64_t n, int64_t m, double alpha, const uint64_t *adj, const pc_order *order,
+                        float *scores, int32_t *top, void *ws, size_t ws_bytes) {
+    if (!ctx || !adj || !scores || !top || !order) return PC_ERR_INVALID_ARG;
+    if (!row_order_on(order) || !valid_order(order)) return PC_ERR_INVALID_ARG;
+    Plan L;
+    Batch b;
+    pc_status s = features_setup(ctx, 1, n, m, alpha, adj, ws, ws_bytes, L, b);
+    if (s != PC_OK) return s;
+    PC_HIP(launch_row_order(ctx->stream, b, 1, order->row_params, order->row_top, order->row_rank, order->row_short,
+                            ctx->num_cu, scores, top));
+    PC_HIP(hipStreamSynchronize(ctx->stream));
+    return PC_OK;
 }
 
 pc_status pc_mlp_forward(pc_ctx *ctx, const float *params, const float *X, int64_t rows, float *scores,

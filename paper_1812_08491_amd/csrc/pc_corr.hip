@@ -410,6 +410,39 @@ __global__ __launch_bounds__(256) void k_corr(Batch bt) {
     }
 }
 
+// Level 0 on a correlation matrix the caller supplied (FP64, no data): one work-group per row, a
+// wavefront per 64-column word. Pair (i, j) is decided on C[min(i,j), max(i,j)], so both bits of a
+// pair always agree; |atanh c| <= tau_0 removes it (Sec. 3.2, Eq. 5-6), as on the FP64 data path.
+__global__ __launch_bounds__(256) void k_level0_given(Batch b) {
+    const long long grow = blockIdx.x;
+    const int d = find_base(b.row_base, b.count, grow);
+    Prob &P = b.probs[d];
+    const int64_t n = P.n, W = P.W, row = grow - b.row_base[d];
+    const double *C = static_cast<const double *>(P.C);
+    const double tau0 = P.tau[0];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int removed = 0;
+    for (int64_t w = wave; w < W; w += 4) {
+        const int64_t j = 64 * w + lane;
+        bool keep = false;
+        if (j < n && j != row) {
+            const int64_t lo = row < j ? row : j, hi = row < j ? j : row;
+            keep = !(fisher_z(C[lo * n + hi]) <= tau0);
+            removed += (!keep && row < j) ? 1 : 0;
+        }
+        const unsigned long long bits = __ballot(keep);
+        if (lane == 0) P.adj[row * W + w] = bits;
+    }
+    for (int o = 32; o >= 1; o >>= 1) removed += __shfl_xor(removed, o, 64);
+    if (lane == 0 && removed) add_ll(&P.removed[0], (long long)removed);
+    if (row == 0 && threadIdx.x == 0) P.tests[0] = (long long)(n * (n - 1) / 2);
+}
+
+hipError_t launch_level0_given(hipStream_t s, const Batch &b) {
+    hipLaunchKernelGGL(k_level0_given, dim3((unsigned)b.total_rows), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
 // Deep staging (64 samples per barrier) when the tiles do not fill the CUs, or on BF16x3, whose
 // three products per block keep a CU busy long enough to cover the loads of the next group.
 hipError_t launch_corr(hipStream_t s, const Batch &b, long long tiles, int num_cu) {

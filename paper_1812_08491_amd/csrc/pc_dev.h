@@ -179,6 +179,7 @@ hipError_t launch_standardize(hipStream_t s, const Batch &b, long long blocks);
 
 // pc_corr.hip
 hipError_t launch_corr(hipStream_t s, const Batch &b, long long tiles, int num_cu);
+hipError_t launch_level0_given(hipStream_t s, const Batch &b);
 
 // pc_level.hip
 hipError_t launch_compact(hipStream_t s, const Batch &b, int level, int ranks_per_item);
@@ -224,7 +225,8 @@ hipError_t launch_features(hipStream_t s, const Batch &b, int level, const long 
                            int *meta, const int *skip);
 // Shared-set order: reorders each row's neighbour list, the `top` best-scored candidates first, and
 // tests their sets. grid: compute units (the launch fills them).
-hipError_t launch_row_order(hipStream_t s, const Batch &b, int level, const float *params, int top, int grid);
+hipError_t launch_row_order(hipStream_t s, const Batch &b, int level, const float *params, int top, int by_abs,
+                            int short_k, int grid, float *scores_out = nullptr, int *top_out = nullptr);
 // Training rows of the shared-set order (features, labels, meta (i, k)) after a compaction.
 hipError_t launch_row_features(hipStream_t s, const Batch &b, int level, long long *foff, long long cap, int *skip,
                                float *feats, float *labels, int *meta);

@@ -729,6 +729,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe(Batch b, const float *p
 constexpr int kRowCap = 1024;     // rows up to this degree are ranked (neighbour list in LDS)
 constexpr int kRowWords = 256;    // adjacency words of a row staged in LDS (n <= 16384)
 constexpr int kRowTopMax = 16;
+constexpr int kRowShortMax = 64;   // longest short list the model scores (one tile per wavefront)
 
 template <typename T>
 struct __align__(16) RowSmem {
@@ -750,6 +751,8 @@ struct __align__(16) RowSmem {
     float red[4], redmax[4];
     float b3;
     int taken[kRowCap];    // candidate already among the top (argmax rounds)
+    int slist[kRowShortMax];     // short list: positions of the largest |C_ik|, in that order
+    float sshort[kRowShortMax];  // model scores of the short list
     float bestv[4];
     int besti[4];
 };
@@ -891,11 +894,15 @@ __device__ inline void row_features(const Smem &sm, const Prob &P, int d, int p,
 //     settled together (one winner per edge, one SepSet slot reservation per row).
 // The rest of the level then runs over the ranks top .. d - 1 of the rewritten lists.
 template <typename T>
-__global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const float *params, int top) {
+// With scores_out (n x n, problem 0 only) the kernel only ranks: it writes each scored candidate's
+// score at [i][k] (-inf for candidates outside the short list) and the chosen candidates at
+// top_out[i][0 .. top) (best first, -1 past the row's choices), and runs no test.
+__global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const float *params, int top, int by_abs,
+                                                    int short_k, float *scores_out, int *top_out) {
     __shared__ RowSmem<T> sm;
     if (b.st->done) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    load_mlp_bf16(sm, params, tid, 256);
+    if (!by_abs) load_mlp_bf16(sm, params, tid, 256);
     if (tid == 0) {
         sm.tests = 0;
         sm.removed = 0;
@@ -931,14 +938,44 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
         if (scored) {
             float rowmax = 0.0f;
             const float rowmean = stage_row<T>(sm, P, row, d, tid, 256, rowmax);
-            for (int r0 = 64 * wave; r0 < d; r0 += 256) {
-                float x[kIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                if (r0 + lane < d) row_features(sm, P, d, r0 + lane, level, rowmean, rowmax, x);
+            if (by_abs) {
+                // |C_ik| alone ranks the candidates (no model).
+                for (int p = tid; p < d; p += 256) sm.sc[p] = sm.ac[p];
+            } else if (short_k > 0 && d > short_k) {
+                // Only the short_k candidates of largest |C_ik| are scored by the model; the others
+                // cannot be chosen. A candidate's place in that order is the number of candidates
+                // before it (larger |C_ik|, or equal at a lower position).
+                for (int p = tid; p < d; p += 256) {
+                    const float a = sm.ac[p];
+                    int r = 0;
+                    for (int q = 0; q < d; ++q) {
+                        const float c = sm.ac[q];
+                        r += (c > a || (c == a && q < p)) ? 1 : 0;
+                    }
+                    sm.sc[p] = -INFINITY;
+                    if (r < short_k) sm.slist[r] = p;
+                }
+                __syncthreads();
+                for (int r0 = 64 * wave; r0 < short_k; r0 += 256) {
+                    float x[kIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    if (r0 + lane < short_k) row_features(sm, P, d, sm.slist[r0 + lane], level, rowmean, rowmax, x);
 #pragma unroll
-                for (int u = 0; u < kIn; ++u) sm.X[wave][lane][u] = bf16_rne(x[u]);
-                wave_sync_lds();
-                mlp_score64(sm, wave, lane, r0, d, sm.sc + r0);
-                wave_sync_lds();
+                    for (int u = 0; u < kIn; ++u) sm.X[wave][lane][u] = bf16_rne(x[u]);
+                    wave_sync_lds();
+                    mlp_score64(sm, wave, lane, r0, short_k, sm.sshort + r0);
+                    wave_sync_lds();
+                    if (r0 + lane < short_k) sm.sc[sm.slist[r0 + lane]] = sm.sshort[r0 + lane];
+                }
+            } else {
+                for (int r0 = 64 * wave; r0 < d; r0 += 256) {
+                    float x[kIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    if (r0 + lane < d) row_features(sm, P, d, r0 + lane, level, rowmean, rowmax, x);
+#pragma unroll
+                    for (int u = 0; u < kIn; ++u) sm.X[wave][lane][u] = bf16_rne(x[u]);
+                    wave_sync_lds();
+                    mlp_score64(sm, wave, lane, r0, d, sm.sc + r0);
+                    wave_sync_lds();
+                }
             }
             for (int p = d + tid; p < ((d + 3) & ~3); p += 256) sm.sc[p] = -INFINITY;
             __syncthreads();
@@ -973,6 +1010,11 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
                 }
                 __syncthreads();
             }
+            if (scores_out) {
+                for (int p = tid; p < d; p += 256) scores_out[(int64_t)row * n + sm.nb[p]] = sm.sc[p];
+                if (tid < top) top_out[(int64_t)row * top + tid] = tid < T_ ? sm.nb[sm.toppos[tid]] : -1;
+                continue;
+            }
             // New order: the top candidates by rank, then the others in their (ascending) order.
             for (int p = tid; p < d; p += 256) {
                 int pos = -1, below = 0;
@@ -985,6 +1027,10 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
             }
         } else if (tid < T_) {
             sm.toppos[tid] = tid;   // too long to score: the first positions, order unchanged
+        }
+        if (scores_out) {
+            if (!scored && tid < top) top_out[(int64_t)row * top + tid] = tid < T_ ? nbr[tid] : -1;
+            continue;
         }
         __syncthreads();
         // 2. The sets {k} of the top candidates against every live edge of the row.
@@ -1117,18 +1163,23 @@ __global__ __launch_bounds__(256) void k_row_features(Batch b, int level, const 
 // grid: compute units; as many work-groups per unit as fit are launched.
 template <typename T>
 static hipError_t launch_row_order_t(hipStream_t s, const Batch &b, int level, const float *params, int top,
-                                     int grid) {
+                                     int by_abs, int short_k, int grid, float *scores_out, int *top_out) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_row_order<T>, 256, 0) != hipSuccess || per_cu < 1)
         per_cu = 2;
-    hipLaunchKernelGGL(k_row_order<T>, dim3(per_cu * grid), dim3(256), 0, s, b, level, params, top);
+    hipLaunchKernelGGL(k_row_order<T>, dim3(per_cu * grid), dim3(256), 0, s, b, level, params, top, by_abs, short_k,
+                       scores_out, top_out);
     return hipGetLastError();
 }
 
-hipError_t launch_row_order(hipStream_t s, const Batch &b, int level, const float *params, int top, int grid) {
-    if (top < 1 || top > kRowTopMax) return hipErrorInvalidValue;
-    if (b.prec == PC_PREC_FP64) return launch_row_order_t<double>(s, b, level, params, top, grid);
-    return launch_row_order_t<float>(s, b, level, params, top, grid);
+hipError_t launch_row_order(hipStream_t s, const Batch &b, int level, const float *params, int top, int by_abs,
+                            int short_k, int grid, float *scores_out, int *top_out) {
+    if (top < 1 || top > kRowTopMax || short_k < 0 || short_k > kRowShortMax) return hipErrorInvalidValue;
+    if (!by_abs && !params) return hipErrorInvalidValue;
+    if ((scores_out != nullptr) != (top_out != nullptr) || (scores_out && b.count != 1)) return hipErrorInvalidValue;
+    if (b.prec == PC_PREC_FP64)
+        return launch_row_order_t<double>(s, b, level, params, top, by_abs, short_k, grid, scores_out, top_out);
+    return launch_row_order_t<float>(s, b, level, params, top, by_abs, short_k, grid, scores_out, top_out);
 }
 
 hipError_t launch_row_features(hipStream_t s, const Batch &b, int level, long long *foff, long long cap, int *skip,

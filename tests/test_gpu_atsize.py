@@ -6,9 +6,16 @@ sampled outputs it computes one by one, and properties that hold at any size (ma
     sampled pairs, level-1 decisions of sampled edges recomputed entirely by the oracle (its own
     level-0 neighbour lists, then every size-1 set in both directions), and every sampled SepSet
     record of levels 1-3 passing the oracle's FP64 test.
+    The same workload is also checked whole: G after levels 1, 2 and 3 (BF16x3 and FP32) against
+    the oracle's stored result (tests/golden/n8000_d6_m2000_levels3.npz, written by
+    tests/golden/make_oracle_skeletons.py from the oracle alone; about 100 s of CPU).
   * n=2000 variables, m=1000 samples, expected degree 10: whole skeleton against the oracle, plain
     and with the learned order.
+  * The paper's scalability family: every pair on which the GPU and the oracle differ is tied to a
+    near-collinear test.
 """
+import hashlib
+import os
 import math
 
 import numpy as np
@@ -148,6 +155,45 @@ def test_n8000_levels_1_to_3_sampled_sepsets_pass_oracle(big):
             assert ind or abs(z - t) <= 1e-9 * t, (i, j, S, z, t)
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name, X):
+    g = np.load(os.path.join(GOLDEN, name), allow_pickle=False)
+    assert str(g["digest"]) == hashlib.sha256(np.ascontiguousarray(X, dtype=np.float64).tobytes()).hexdigest(), \
+        "stored oracle result is for another input"
+    return g
+
+
+def _dense_edges(E, n):
+    G = np.zeros((n, n), np.uint8)
+    G[E[:, 0], E[:, 1]] = 1
+    return G | G.T
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_n8000_levels_1_to_3_whole_graph_matches_stored_oracle(big, prec):
+    """G after each of levels 1, 2, 3 equals the oracle's, bit for bit, and so does the number of
+    edges each level removes."""
+    X, XT, alpha = big
+    m, n = X.shape
+    g = _golden("n8000_d6_m2000_levels3.npz", X)
+    ctx = pc.Context(precision=prec)
+    ws = ctx.workspace(n, m)
+    adj = ctx.adjacency(n)
+    recs, count = ctx.sepsets(n * n // 4)
+    Xd = torch.from_numpy(X).cuda()
+    for L in (1, 2, 3):
+        print(f"n8000 {prec} max_level {L}", flush=True)
+        st = pc.pc_run_stats()
+        assert ctx.pc_skeleton(Xd, alpha, adj, recs, count, ws, max_level=L, stats=st) == 0
+        G = pc.bits_to_dense(adj.cpu().numpy(), n)
+        ref = _dense_edges(g[f"edges_after_{L}"], n)
+        assert np.array_equal(G, ref), (L, np.argwhere(G != ref)[:8])
+        assert list(st.removed[:L + 1]) == list(g["removed"][:L + 1])
+        assert int(count.item()) == int(g["removed"][1:L + 1].sum())
+
+
 @pytest.fixture(scope="module")
 def apply_workload():
     X, sem, alpha = semgen.workload("n2000_d10_m1000_apply")
@@ -212,6 +258,14 @@ def test_paper_scalability_n1000_p01_m10000_fp64_matches_oracle():
 
     def degenerate(i, j, S):
         return any(A[np.ix_(V, V)].max() > 1 - 1e-6 for V in ([i] + list(S), [j] + list(S)))
+
+    # Every differing pair is decided by a near-collinear test: the GPU removed it with a
+    # degenerate S, or the oracle removed it with one (which the GPU then decided the other way).
+    ref_seps = ref.sepsets.as_dict()
+    for i, j in np.argwhere(np.triu(G != ref.G, 1)):
+        i, j = int(i), int(j)
+        S = seps[(i, j)][1] if G[i, j] == 0 else ref_seps.get((i, j), (0, ()))[1]
+        assert degenerate(i, j, S), ((i, j), int(G[i, j]), S)
 
     keys = list(seps)
     bad = 0

@@ -147,3 +147,43 @@ def test_graph_continues_past_recorded_levels(tail_tests):
                 check_one(X, a, -1, item, st)
         g.close()
     torch.cuda.synchronize()
+
+
+def test_batch256_in_one_graph_matches_oracle_on_sample():
+    """The 256 uneven datasets (n ~ U[20,400], expected degree ~ U[2,8], m ~ U[200,5000], alpha 0.01)
+    captured in one graph, replayed twice (second replay on the same data), then checked dataset by
+    dataset against the oracle: the datasets of largest n, largest m and most GPU levels, and a
+    seeded sample of 61 more (64 in all). Also every dataset's status and level count."""
+    import os
+    batch = semgen.batch_problems(256)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = pc.Context(stream=stream, precision="fp32")
+        items = [device_problem(ctx, X, a, -1) for X, _, a in batch]
+        probs = ctx.problems(items)
+        ws = ctx.batch_workspace(probs)
+        graph = ctx.pc_batch_capture(probs, ws)
+        st = (pc.pc_run_stats * len(items))()
+        for _ in range(2):
+            graph.pc_graph_launch()
+            r, status = graph.pc_graph_results(st)
+        torch.cuda.synchronize()
+        graph.close()
+    assert r == 0 and all(s == 0 for s in status)
+    ns = [X.shape[1] for X, _, _ in batch]
+    ms = [X.shape[0] for X, _, _ in batch]
+    levels = [st[d].levels_run for d in range(len(batch))]
+    pick = {int(np.argmax(ns)), int(np.argmax(ms)), int(np.argmax(levels))}
+    rng = np.random.default_rng(2560)
+    for d in rng.permutation(len(batch)):
+        if len(pick) >= 64:
+            break
+        pick.add(int(d))
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    try:
+        for d in sorted(pick):
+            X, _, a = batch[d]
+            print(f"batch256 dataset {d}: n={X.shape[1]} m={X.shape[0]} levels={levels[d]}", flush=True)
+            check_one(X, a, -1, items[d], status[d])
+    finally:
+        oracle.set_threads(1)

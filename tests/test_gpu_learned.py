@@ -310,3 +310,116 @@ def test_row_order_n2000_matches_oracle_with_trained_weights():
     assert np.array_equal(G, ref.G)
     assert set(seps) == set(ref.sepsets.as_dict())
     print("level-1 tests", st["tests"][1], "probe", st["probe_tests"][1], "probe removed", st["probe_removed"][1])
+
+
+# ---------------------------------------------------------------------------------------------
+# The BF16 scorer of the shared-set order against the FP64 reference network
+# ---------------------------------------------------------------------------------------------
+U_BF16 = 2.0 ** -9     # unit roundoff of BF16 (8 stored mantissa bits, round to nearest even)
+
+
+def _abs_network(theta, F):
+    """The network with |weights| and |inputs| (FP64): s_bar bounds every path sum of the score."""
+    p = mlp.unpack(np.asarray(theta, np.float64))
+    a1 = np.abs(F) @ np.abs(p["W1"]).T + np.abs(p["b1"])
+    a2 = a1 @ np.abs(p["W2"]).T + np.abs(p["b2"])
+    return a2 @ np.abs(p["W3"]) + abs(p["b3"][0])
+
+
+def _row_scores(ctx, n, m, alpha, adj, ws, order):
+    scores = torch.full((n, n), float("nan"), device="cuda")
+    top = torch.full((n, order.row_top), -2, dtype=torch.int32, device="cuda")
+    ctx.pc_row_scores(n, m, alpha, adj, order, scores, top, ws)
+    return scores.cpu().numpy(), top.cpu().numpy()
+
+
+def _expected_picks(vals, T):
+    """Best first by value, ties to the lower position (the kernel's argmax rounds)."""
+    idx = sorted(range(len(vals)), key=lambda q: (-vals[q], q))
+    return idx[:T]
+
+
+@pytest.mark.parametrize("seed,row_short", [(0, 0), (1, 0), (2, 8)])
+def test_row_scorer_matches_fp64_network(seed, row_short):
+    """k_row_order's BF16 MFMA scores equal the FP64 reference forward (oracle/mlp.py) of the same
+    features within the BF16 error bound, and its picks are the top of its own scores.
+
+    Bound: inputs, W1, W2 and the first hidden layer are rounded to BF16 (relative u = 2^-9 each),
+    so |dz1| <= 2u a1 (+ u a1 for rounding h1), |dz2| <= 4u a2 and |ds| <= 4u s_bar to first order,
+    where a1, a2, s_bar are the layer sums of the network with |weights| and |inputs|. FP32
+    accumulation (at most 64 terms, 2^-24 each) and second-order terms fit in the margin of 6u."""
+    rng = np.random.default_rng(500 + seed)
+    n, m, alpha = 150, 600, 0.05
+    X = semgen.sample(semgen.random_dag(n, 0.12, rng), m, rng)
+    ctx = pc.Context(precision="fp32")
+    ws = ctx.workspace(n, m)
+    adj = ctx.adjacency(n)
+    ctx.pc_corr(dev(X, torch.float64), alpha, ws, adj_out=adj)
+    G = pc.bits_to_dense(adj.cpu().numpy(), n).astype(bool)
+    need = int(G.sum())
+    feats = torch.empty((need, 8), device="cuda")
+    labels = torch.empty(need, device="cuda")
+    meta = torch.empty((need, 2), dtype=torch.int32, device="cuda")
+    assert ctx.pc_row_features(1, n, m, alpha, adj, feats, labels, meta, ws) == need
+    F, M = feats.cpu().numpy().astype(np.float64), meta.cpu().numpy()
+    theta = mlp.init(rng) * rng.uniform(0.5, 2.0)
+    th32 = theta.astype(np.float32)
+    T = 3
+    params = dev(th32)
+    order = ctx.order(None, row_params=params, row_top=T, row_short=row_short)
+    S, top = _row_scores(ctx, n, m, alpha, adj, ws, order)
+    s_ref, _ = mlp.forward(th32.astype(np.float64), F)
+    bound = 6 * U_BF16 * _abs_network(th32, F)
+    deg = G.sum(1)
+    checked = 0
+    for i in range(n):
+        rows = np.flatnonzero(M[:, 0] == i)
+        if deg[i] < 2:
+            continue
+        ks = M[rows, 1]
+        assert list(ks) == list(np.flatnonzero(G[i]))
+        got = S[i, ks].astype(np.float64)
+        if row_short and deg[i] > row_short:
+            short = set(_expected_picks(list(F[rows, 0]), row_short))   # |C_ik|, ties: lower position
+            inside = np.array([q in short for q in range(len(ks))])
+            assert np.all(np.isneginf(got[~inside]))
+        else:
+            inside = np.ones(len(ks), bool)
+        err = np.abs(got[inside] - s_ref[rows][inside])
+        assert np.all(err <= bound[rows][inside]), (i, err.max(), bound[rows][inside].max())
+        checked += int(inside.sum())
+        # picks: the top T of the kernel's own scores, best first, ties to the lower position
+        want = [int(ks[q]) for q in _expected_picks(list(got), min(T, len(ks)))]
+        assert list(top[i, :len(want)]) == want, (i, top[i], want)
+        assert np.all(top[i, len(want):] == -1)
+        # and, within the bound, the top T of the reference scores
+        ref_sorted = np.sort(s_ref[rows][inside])[::-1]
+        kth = ref_sorted[min(T, inside.sum()) - 1]
+        for k in want:
+            q = int(np.flatnonzero(ks == k)[0])
+            assert s_ref[rows][q] >= kth - 2 * bound[rows].max(), (i, k)
+    assert checked > 1000
+
+
+def test_row_scorer_abs_mode_ranks_by_abs_corr():
+    """row_rank 'abs': the score of candidate k of node i is |C_ik| itself and the picks are the
+    largest |C_ik| (ties to the lower position)."""
+    rng = np.random.default_rng(77)
+    n, m, alpha = 120, 500, 0.05
+    X = semgen.sample(semgen.random_dag(n, 0.1, rng), m, rng)
+    ctx = pc.Context(precision="fp32")
+    ws = ctx.workspace(n, m)
+    adj = ctx.adjacency(n)
+    C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    ctx.pc_corr(dev(X, torch.float64), alpha, ws, C_out=C, adj_out=adj)
+    G = pc.bits_to_dense(adj.cpu().numpy(), n).astype(bool)
+    Cn = C.cpu().numpy()
+    order = ctx.order(None, row_top=4, row_rank="abs")
+    S, top = _row_scores(ctx, n, m, alpha, adj, ws, order)
+    for i in range(n):
+        ks = np.flatnonzero(G[i])
+        if ks.size < 2:
+            continue
+        assert np.array_equal(S[i, ks], np.abs(Cn[i, ks]))
+        want = [int(ks[q]) for q in _expected_picks(list(np.abs(Cn[i, ks])), min(4, ks.size))]
+        assert list(top[i, :len(want)]) == want
