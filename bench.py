@@ -5,9 +5,9 @@ samples, alpha = 0.01. CI tests run in FP32 and borderline tests are re-done in 
 the learned conditioning-set order: a row model trained on 2000 generated n = 200 SEMs picks each
 node's best candidates k, and their sets {k} are tested first.
 
-One step is one whole skeleton, run by pc_skeleton_ordered on the stream. It covers
-standardization, the correlation GEMM with level 0, and every level with its re-checks. The data
-is resident in HBM. `ms_per_step` is the host wall time per step.
+One step is one whole skeleton: standardization, the correlation GEMM with level 0, and every
+level with its re-checks, captured once as a hipGraph (pc_batch_capture_ordered) and replayed. The
+data is resident in HBM. `ms_per_step` is the host wall time of back-to-back replays per replay.
 
 `value` is CI tests per second: the tests that the sequential PC-stable enumeration performs on this
 input (canonical order, first success ends an edge), divided by the time per step. The CPU oracle
@@ -19,8 +19,8 @@ The same skeleton is also run with plain lexicographic enumeration and with cand
 
 `roofline` prices the level-1 pass of a step (k_row_order + k_window + k_level<float,1>) on the
 canonical level-1 work. Each CI test reads 8 bytes (C_ij and C_jk) and each conditioning set
-{k} of a row reads 8 bytes (C_ik, C_kk). The pass is timed with HIP events inside the timed
-steps.
+{k} of a row reads 8 bytes (C_ik, C_kk). The pass is timed with HIP events on the same stream, in
+eager runs of the same skeleton right after the timed replays (a captured graph holds no events).
 
 Further legs (skipped with --no-extras):
 * the n = 1000, degree 4, m = 500 skeleton as a captured hipGraph;
@@ -182,48 +182,74 @@ def headline(args, torch, pc, semgen, out):
     m, n = X.shape
     Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
     row_w = learn.load_weights(learn.ROW_WEIGHTS)
+    # The levels the skeleton needs, from one eager run: every graph records all of them, so no
+    # replay needs the stream continuation of pc_graph_results.
+    ectx = pc.Context(precision="fp32")
+    eadj = ectx.adjacency(n)
+    erecs, ecount = ectx.sepsets(n * (n - 1) // 2)
+    est = pc.pc_run_stats()
+    assert ectx.pc_skeleton(Xd, alpha, eadj, erecs, ecount, ectx.workspace(n, m), stats=est) == 0
+    graph_levels = max(1, est.levels_run - 1)
+    stream = torch.cuda.Stream()
     modes = {}
-    for mode in ("learned", "abs", "plain"):
-        # Level kernels timed with HIP events inside every step (bit 2).
-        ctx = pc.Context(precision="fp32", timing=2)
-        order = None
-        if mode == "learned":
-            order = ctx.order(None, row_params=row_w, row_top=ROW_TOP)
-        elif mode == "abs":
-            order = ctx.order(None, row_top=ROW_TOP, row_rank="abs")
-        ws = ctx.ordered_workspace(n, m, order) if order is not None else ctx.workspace(n, m)
-        recs, count = ctx.sepsets(n * (n - 1) // 2)
-        modes[mode] = dict(ctx=ctx, order=order, ws=ws, adj=ctx.adjacency(n), recs=recs, count=count)
+    with torch.cuda.stream(stream):
+        for mode in ("learned", "abs", "plain"):
+            ctx = pc.Context(stream=stream, precision="fp32", graph_levels=graph_levels)
+            order = None
+            if mode == "learned":
+                order = ctx.order(None, row_params=row_w, row_top=ROW_TOP)
+            elif mode == "abs":
+                order = ctx.order(None, row_top=ROW_TOP, row_rank="abs")
+            adj = ctx.adjacency(n)
+            recs, count = ctx.sepsets(n * (n - 1) // 2)
+            probs = ctx.problems([(Xd, alpha, -1, adj, recs, count)])
+            ws = ctx.batch_workspace(probs)
+            graph = ctx.pc_batch_capture(probs, ws, order)
+            modes[mode] = dict(ctx=ctx, order=order, adj=adj, recs=recs, count=count, graph=graph, ws=ws,
+                               probs=probs)
 
-    def step(mode):
-        r = modes[mode]
-        st = pc.pc_run_stats()
-        if r["order"] is None:
-            s = r["ctx"].pc_skeleton(Xd, alpha, r["adj"], r["recs"], r["count"], r["ws"], stats=st)
-        else:
-            s = r["ctx"].pc_skeleton_ordered(Xd, alpha, r["adj"], r["recs"], r["count"], r["ws"], r["order"],
-                                             stats=st)
-        assert s == 0, pc.status_str(s)
-        return st
+    def results(mode):
+        st = (pc.pc_run_stats * 1)()
+        r, status = modes[mode]["graph"].pc_graph_results(st)
+        assert r == 0 and status[0] == 0, (mode, r, status)
+        d = st[0].as_dict()
+        assert d["levels_run"] - 1 <= graph_levels, "a replay needed levels beyond the recorded ones"
+        return d
 
     names = ("learned",) if args.headline_only else ("learned", "abs", "plain")
-    for mode in names:
-        for _ in range(args.warmup):
-            step(mode)
     res = {}
-    for mode in names:
-        torch.cuda.synchronize()
-        sts = []
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            sts.append(step(mode).as_dict())
-        torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / args.steps
-        last = sts[-1]
-        res[mode] = {"ms_per_step": sec * 1e3, "tests": last["tests"], "probe_tests": last["probe_tests"],
-                     "levels_run": last["levels_run"],
-                     "level1_pass_ms": float(np.mean([s["level_ms"][1] for s in sts])),
-                     "adj": modes[mode]["adj"].cpu().numpy()}
+    with torch.cuda.stream(stream):
+        for mode in names:
+            g = modes[mode]["graph"]
+            for _ in range(max(1, args.warmup)):
+                g.pc_graph_launch()
+                results(mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                g.pc_graph_launch()
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / args.steps
+            last = results(mode)
+            # The level-1 pass (the same kernels on the same stream), timed with HIP events around
+            # it in eager runs of the same skeleton (a captured graph holds no timing events).
+            tctx = pc.Context(stream=stream, precision="fp32", timing=32)
+            tadj = tctx.adjacency(n)
+            trecs, tcount = tctx.sepsets(n * (n - 1) // 2)
+            tws = tctx.workspace(n, m)
+            torder = modes[mode]["order"]
+            l1 = []
+            for _ in range(10):
+                st = pc.pc_run_stats()
+                if torder is None:
+                    tctx.pc_skeleton(Xd, alpha, tadj, trecs, tcount, tws, stats=st)
+                else:
+                    tctx.pc_skeleton_ordered(Xd, alpha, tadj, trecs, tcount, tws, torder, stats=st)
+                l1.append(st.level_ms[1])
+            del tws, trecs
+            res[mode] = {"ms_per_step": sec * 1e3, "tests": last["tests"], "probe_tests": last["probe_tests"],
+                         "rechecks": last["rechecks"], "levels_run": last["levels_run"],
+                         "level1_pass_ms": float(np.mean(l1)), "adj": modes[mode]["adj"].cpu().numpy()}
     G = {mode: pc.bits_to_dense(res[mode].pop("adj"), n) for mode in names}
     sec = res["learned"]["ms_per_step"] * 1e-3
     out.update({
@@ -234,7 +260,8 @@ def headline(args, torch, pc, semgen, out):
                    "order": {"form": "shared-set (row) model at level 1", "row_top": ROW_TOP,
                              "weights": "paper_1812_08491_amd/weights/order_row_mlp_n200.npy",
                              "trained_on": "2000 generated SEMs, n=200, degree~U[2,10], m=1000"},
-                   "step": "one pc_skeleton_ordered call: the whole skeleton on the stream"},
+                   "step": "one replay of the whole skeleton captured as a hipGraph (pc_batch_capture_ordered)",
+                   "graph_levels": graph_levels},
         "gpu_tests_per_step": int(sum(res["learned"]["tests"])),
         "orders": {mode: {k: v for k, v in r.items()} for mode, r in res.items()},
     })

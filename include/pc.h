@@ -72,7 +72,9 @@ typedef struct {
                                   many as fit on the device at once) */
     int32_t timing;            /* bit mask of phases timed with HIP events into pc_run_stats:
                                   1 = correlation kernel (incl. level 0), 2 = level kernels,
-                                  4 = compaction, 8 = FP64 re-check, 16 = standardization */
+                                  4 = compaction, 8 = FP64 re-check, 16 = standardization,
+                                  32 = the level kernels of level 1 only. No phase is timed
+                                  inside a captured graph. */
     int64_t recheck_cap;       /* capacity of the FP64 re-check queue in tests per level
                                   (0 = automatic: the sum of n^2/4 over the batch, at least
                                   2^16, at most 2^25); a level that needs more returns
@@ -307,6 +309,13 @@ size_t pc_ordered_workspace_bytes(int64_t n, int64_t m, const pc_options *opt, c
 pc_status pc_skeleton_ordered(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alpha,
                               int max_level, const pc_order *order, uint64_t *adj_out,
                               const pc_sepset *sep, pc_run_stats *st, void *ws, size_t ws_bytes);
+
+/* pc_batch_capture with a learned conditioning-set order recorded into the graph (the forms and
+ * fields of pc_order as for pc_skeleton_ordered; order NULL is pc_batch_capture). The order is
+ * copied, but the model parameters it points to are read at every replay: they must stay valid and
+ * unchanged while the graph is used. */
+pc_status pc_batch_capture_ordered(pc_ctx *ctx, const pc_problem *probs, int count, const pc_order *order,
+                                   void *ws, size_t ws_bytes, pc_graph **out);
 
 /* Candidate features of level `level` for the snapshot adj (device bit matrix, not modified), for
  * training data: rows ordered by i, then j = N_i[p], then k in N_i\{j}, as the ordered run uses them.

@@ -158,6 +158,9 @@ def lib() -> ct.CDLL:
         L.pc_batch_capture.argtypes = [vp, ct.POINTER(pc_problem), ct.c_int, vp, ct.c_size_t,
                                        ct.POINTER(vp)]
         L.pc_batch_capture.restype = ct.c_int
+        L.pc_batch_capture_ordered.argtypes = [vp, ct.POINTER(pc_problem), ct.c_int, ct.POINTER(pc_order), vp,
+                                               ct.c_size_t, ct.POINTER(vp)]
+        L.pc_batch_capture_ordered.restype = ct.c_int
         L.pc_graph_launch.argtypes = [vp]
         L.pc_graph_launch.restype = ct.c_int
         L.pc_graph_results.argtypes = [vp, ct.POINTER(pc_run_stats), ct.POINTER(ct.c_int)]
@@ -205,7 +208,8 @@ EXPORTED = ["pc_create", "pc_destroy", "pc_default_options", "pc_workspace_bytes
             "pc_batch_capture", "pc_graph_launch", "pc_graph_results", "pc_graph_destroy",
             "pc_ordered_workspace_bytes", "pc_skeleton_ordered", "pc_features", "pc_row_features", "pc_mlp_forward",
             "pc_mlp_backward", "pc_mlp_bce", "pc_mlp_adam", "pc_orient_workspace_bytes", "pc_orient",
-            "pc_corr_workspace_bytes", "pc_level_corr", "pc_skeleton_corr", "pc_row_scores"]
+            "pc_corr_workspace_bytes", "pc_level_corr", "pc_skeleton_corr", "pc_row_scores",
+            "pc_batch_capture_ordered"]
 
 
 def _check_abi(L: ct.CDLL) -> None:
@@ -381,6 +385,9 @@ class Context:
             m, n = X.shape
             arr[k] = pc_problem(X.data_ptr(), m, n, alpha, max_level, 0, adj.data_ptr(),
                                 pc_sepset(recs.data_ptr(), recs.shape[0], count.data_ptr()))
+        # The descriptors hold raw device pointers (and a captured graph keeps using them): the
+        # array keeps the tensors alive for as long as it lives.
+        arr._keep = items
         return arr
 
     def batch_workspace(self, probs):
@@ -397,11 +404,16 @@ class Context:
                                     ws.numel())
         return r, [int(x) for x in status]
 
-    def pc_batch_capture(self, probs, ws) -> "Graph":
+    def pc_batch_capture(self, probs, ws, order: "pc_order | None" = None) -> "Graph":
         g = ct.c_void_p()
-        _check(lib().pc_batch_capture(self.h, probs, len(probs), ct.c_void_p(ws.data_ptr()), ws.numel(),
-                                      ct.byref(g)), "pc_batch_capture", allow_warn=False)
-        return Graph(g, len(probs), keep=(probs, ws, self))
+        if order is None:
+            _check(lib().pc_batch_capture(self.h, probs, len(probs), ct.c_void_p(ws.data_ptr()), ws.numel(),
+                                          ct.byref(g)), "pc_batch_capture", allow_warn=False)
+        else:
+            _check(lib().pc_batch_capture_ordered(self.h, probs, len(probs), ct.byref(order),
+                                                  ct.c_void_p(ws.data_ptr()), ws.numel(), ct.byref(g)),
+                   "pc_batch_capture_ordered", allow_warn=False)
+        return Graph(g, len(probs), keep=(probs, ws, self, order))
 
     # -- learned ordering ----------------------------------------------------------------------
     @staticmethod

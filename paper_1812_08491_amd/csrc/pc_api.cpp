@@ -53,6 +53,8 @@ struct pc_graph {
     int captured;                   // levels recorded in the graph
     int top;                        // last level any dataset may need (PC_MAX_LEVEL + 1 = planning)
     bool tail;                      // the graph ends with the tail kernel (from level captured + 1)
+    bool has_order;                 // a learned order was recorded (kept for the continuation)
+    pc_order order;
 };
 
 namespace {
@@ -372,6 +374,13 @@ int level_lds_bytes(const pc_ctx *ctx) {
 
 bool timed(const pc_ctx *ctx, int bit, bool capturing) { return !capturing && (ctx->opt.timing & bit); }
 
+// Level kernels of level l are timed: every level (bit 2) or level 1 alone (bit 32). Not inside a
+// captured graph (an event recorded during capture only marks a dependency, it is not re-recorded
+// by the replays).
+bool timed_level(const pc_ctx *ctx, int level, bool capturing) {
+    return timed(ctx, 2, capturing) || (level == 1 && timed(ctx, 32, capturing));
+}
+
 // Standardize + correlation + level 0 for every problem of the batch.
 pc_status enqueue_corr(pc_ctx *ctx, const Batch &b, const Plan &L, bool capturing) {
     hipStream_t s = ctx->stream;
@@ -433,7 +442,7 @@ pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, co
     const bool row_order = ord && level == 1 && row_order_on(ord->order);
     if (ord && probe_level(ord->order, level) && !row_order)
         PC_HIP(launch_probe(s, b, level, ord->order->params, ord->order->top, ctx->num_cu));
-    if (timed(ctx, 2, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][0], s));
+    if (timed_level(ctx, level, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][0], s));
     if (row_order) {
         // Shared-set order: each row's best-scored candidates move to the front of its neighbour
         // list and their sets are tested first (in the ordering kernel), then the level kernel runs
@@ -448,7 +457,7 @@ pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, co
     } else {
         PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx), auto_grid(ctx, level)));
     }
-    if (timed(ctx, 2, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][1], s));
+    if (timed_level(ctx, level, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][1], s));
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][0], s));
     PC_HIP(launch_recheck(s, b, level, ctx->recheck_grid));
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][1], s));
@@ -602,7 +611,8 @@ void fill_times(pc_ctx *ctx, pc_run_stats *st, int top_level) {
     if (tm & 1) (void)hipEventElapsedTime(&st->corr_ms, ctx->ev_corr[0], ctx->ev_corr[1]);
     for (int l = 1; l <= std::min(top_level, PC_MAX_LEVEL); ++l) {
         if (tm & 4) (void)hipEventElapsedTime(&st->compact_ms[l], ctx->ev_compact[l][0], ctx->ev_compact[l][1]);
-        if (tm & 2) (void)hipEventElapsedTime(&st->level_ms[l], ctx->ev_level[l][0], ctx->ev_level[l][1]);
+        if ((tm & 2) || ((tm & 32) && l == 1))
+            (void)hipEventElapsedTime(&st->level_ms[l], ctx->ev_level[l][0], ctx->ev_level[l][1]);
         if (tm & 8) (void)hipEventElapsedTime(&st->recheck_ms[l], ctx->ev_recheck[l][0], ctx->ev_recheck[l][1]);
     }
 }
@@ -1004,7 +1014,13 @@ pc_status pc_batch_skeleton(pc_ctx *ctx, const pc_problem *probs, int count, pc_
 
 pc_status pc_batch_capture(pc_ctx *ctx, const pc_problem *probs, int count, void *ws,
                            size_t ws_bytes, pc_graph **out) {
+    return pc_batch_capture_ordered(ctx, probs, count, nullptr, ws, ws_bytes, out);
+}
+
+pc_status pc_batch_capture_ordered(pc_ctx *ctx, const pc_problem *probs, int count, const pc_order *order, void *ws,
+                                   size_t ws_bytes, pc_graph **out) {
     if (!ctx || !probs || count < 1 || !out) return PC_ERR_INVALID_ARG;
+    if (order && !valid_order(order)) return PC_ERR_INVALID_ARG;
     *out = nullptr;
     if (ctx->stream == nullptr) return PC_ERR_INVALID_ARG;  // the null stream cannot be captured
     Plan L;
@@ -1025,7 +1041,9 @@ pc_status pc_batch_capture(pc_ctx *ctx, const pc_problem *probs, int count, void
         delete g;
         return PC_ERR_HIP;
     }
-    s = enqueue_skeletons(ctx, probs, count, L, g->ws, true);
+    g->has_order = order != nullptr;
+    if (order) g->order = *order;
+    s = enqueue_skeletons(ctx, probs, count, L, g->ws, true, order);
     g->tail = ctx->tail_enqueued;
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
@@ -1070,7 +1088,8 @@ pc_status pc_graph_results(pc_graph *g, pc_run_stats *st, pc_status *status) {
             if (from > 0 && from <= g->top && !ds.done && (s = enqueue_plan(ctx, b, from, false)) != PC_OK) return s;
         }
         if (from > 0 && from <= g->top) {
-            pc_status s = run_levels_eager(ctx, b, L, g->ws, from, g->top, nullptr);
+            const OrderRun ord{&g->order, &L, g->ws};
+            pc_status s = run_levels_eager(ctx, b, L, g->ws, from, g->top, g->has_order ? &ord : nullptr);
             if (s != PC_OK) return s;
         }
     }

@@ -50,14 +50,23 @@ __device__ inline void write_record(const Prob &P, int lo, int hi, int level, co
 }
 
 // Pushes a test to the re-check queue; cls is the FP32 classification (0 dependent, 1 independent,
-// 2 inside the band).
+// 2 inside the band). The lanes of a wavefront that reach this call together reserve consecutive
+// slots with one atomic add by the lowest of them: same-address device atomics serialise, and a
+// level can push millions of tests (BF16x3 bands).
 template <int L>
 __device__ inline void push_recheck(const Batch &b, int d, int row, int j, const int (&sid)[L], int cls) {
-    const unsigned long long k = atomicAdd(&b.st->rq_count, 1ull);
-    if (k >= (unsigned long long)b.rq_cap) {
-        atomicOr(&b.st->rq_overflow, 1);
-        return;
+    const unsigned long long act = __ballot(1);
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((long long)act) - 1;
+    const unsigned long long cnt = (unsigned long long)__popcll(act);
+    unsigned long long base = 0ull;
+    if (lane == leader) {
+        base = atomicAdd(&b.st->rq_count, cnt);
+        if (base + cnt > (unsigned long long)b.rq_cap) atomicOr(&b.st->rq_overflow, 1);
     }
+    base = __shfl(base, leader, 64);
+    const unsigned long long k = base + (unsigned long long)__popcll(act & ((1ull << lane) - 1ull));
+    if (k >= (unsigned long long)b.rq_cap) return;
     RqEntry *e = b.rq + k;
     e->prob = d;
     e->i = row;

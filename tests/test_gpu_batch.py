@@ -187,3 +187,33 @@ def test_batch256_in_one_graph_matches_oracle_on_sample():
             check_one(X, a, -1, items[d], status[d])
     finally:
         oracle.set_threads(1)
+
+
+@pytest.mark.parametrize("rank", ["abs", "model"])
+def test_ordered_graph_replays_match_oracle(rank):
+    """pc_batch_capture_ordered: the shared-set order recorded into the graph (|C_ik| ranking, or a
+    random row model scoring a short list), two ragged datasets, replayed twice; each skeleton is
+    the oracle's and every SepSet passes the oracle's test."""
+    from oracle import mlp
+    batch = uneven_batch(2, seed=91, nmax=300, mmax=1500)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = pc.Context(stream=stream, precision="fp32", graph_levels=12)
+        items = [device_problem(ctx, X, a, ml) for X, a, ml in batch]
+        probs = ctx.problems(items)
+        ws = ctx.batch_workspace(probs)
+        params = torch.from_numpy(mlp.init(np.random.default_rng(9)).astype(np.float32)).cuda()
+        order = (ctx.order(None, row_top=3, row_rank="abs") if rank == "abs"
+                 else ctx.order(None, row_params=params, row_top=2, row_short=12))
+        graph = ctx.pc_batch_capture(probs, ws, order)
+        st = (pc.pc_run_stats * len(items))()
+        for _ in range(2):
+            graph.pc_graph_launch()
+            r, status = graph.pc_graph_results(st)
+        torch.cuda.synchronize()
+        graph.close()
+    assert r == 0
+    for d, (X, a, ml) in enumerate(batch):
+        check_one(X, a, ml, items[d], status[d])
+        if st[d].levels_run > 1:
+            assert st[d].probe_tests[1] > 0
