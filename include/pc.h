@@ -211,6 +211,20 @@ pc_status pc_skeleton(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double
                       int max_level, uint64_t *adj_out, const pc_sepset *sep, pc_run_stats *st,
                       void *ws, size_t ws_bytes);
 
+/* pc_skeleton without a workspace argument, for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc between calls). The workspace is a device array
+ * of PC_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the process
+ * ends; the call itself allocates nothing (no hipMalloc, hipFree or host pinning: the context
+ * created those beforehand). Inputs and outputs are the caller's, as for pc_skeleton.
+ * Limits: pc_workspace_bytes(n, m, opt) <= PC_NOALLOC_SCRATCH_BYTES (about n = 1000 at m = 500 in
+ * FP32) and n <= 8191; larger problems return PC_ERR_WORKSPACE and run nothing.
+ * All calls on one GPU share its array, and each call overwrites it (the call clears what must start
+ * at zero): calls that overlap in time on the same GPU, from any context or stream, race and give
+ * undefined results. Synchronises the stream. */
+#define PC_NOALLOC_SCRATCH_BYTES (64u << 20)
+pc_status pc_skeleton_noalloc(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alpha,
+                              int max_level, uint64_t *adj_out, const pc_sepset *sep, pc_run_stats *st);
+
 /* One dataset of a batch (Sec. 5 of the paper runs one dataset at a time; a batch runs many
  * independent skeletons together, their work items tagged by dataset).
  *   X        device m x n FP64 row-major data.

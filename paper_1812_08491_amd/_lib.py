@@ -143,6 +143,9 @@ def lib() -> ct.CDLL:
         L.pc_skeleton_corr.argtypes = [vp, vp, i64, ct.c_double, ct.c_double, ct.c_int, vp, ct.POINTER(pc_sepset),
                                        ct.POINTER(pc_run_stats), vp, ct.c_size_t]
         L.pc_skeleton_corr.restype = ct.c_int
+        L.pc_skeleton_noalloc.argtypes = [vp, vp, i64, i64, ct.c_double, ct.c_int, vp, ct.POINTER(pc_sepset),
+                                          ct.POINTER(pc_run_stats)]
+        L.pc_skeleton_noalloc.restype = ct.c_int
         L.pc_sync_status.argtypes = [vp, vp, ct.c_size_t]
         L.pc_sync_status.restype = ct.c_int
         L.pc_comb_unrank.argtypes = [ct.c_int32, ct.c_int32, ct.c_uint64, ct.c_int32,
@@ -209,7 +212,8 @@ EXPORTED = ["pc_create", "pc_destroy", "pc_default_options", "pc_workspace_bytes
             "pc_ordered_workspace_bytes", "pc_skeleton_ordered", "pc_features", "pc_row_features", "pc_mlp_forward",
             "pc_mlp_backward", "pc_mlp_bce", "pc_mlp_adam", "pc_orient_workspace_bytes", "pc_orient",
             "pc_corr_workspace_bytes", "pc_level_corr", "pc_skeleton_corr", "pc_row_scores",
-            "pc_batch_capture_ordered"]
+            "pc_batch_capture_ordered",
+            "pc_skeleton_noalloc"]
 
 
 def _check_abi(L: ct.CDLL) -> None:
@@ -373,6 +377,16 @@ class Context:
                                              ct.c_void_p(adj.data_ptr()), ct.byref(sep),
                                              ct.byref(stats) if stats is not None else None,
                                              ct.c_void_p(ws.data_ptr()), ws.numel()), "pc_skeleton_corr")
+
+    def pc_skeleton_noalloc(self, X, alpha: float, adj, recs, count, max_level: int = -1,
+                            stats: pc_run_stats | None = None) -> int:
+        m, n = X.shape
+        assert X.is_cuda and X.dtype == _torch().float64 and X.is_contiguous()
+        sep = pc_sepset(recs.data_ptr(), recs.shape[0], count.data_ptr())
+        return _check(lib().pc_skeleton_noalloc(self.h, ct.c_void_p(X.data_ptr()), m, n, alpha, max_level,
+                                                ct.c_void_p(adj.data_ptr()), ct.byref(sep),
+                                                ct.byref(stats) if stats is not None else None),
+                      "pc_skeleton_noalloc")
 
     # -- batches ---------------------------------------------------------------------------------
     @staticmethod

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -39,6 +40,7 @@ struct pc_ctx {
     int level_grid[kLevels];        // work-groups of the level kernels: all that fit at once
     int recheck_grid;               // work-groups of the re-check kernel: at most 4 per CU, all resident
     bool tail_enqueued;             // the last enqueue_skeletons ended its levels with the tail kernel
+    void *scratch;                  // this device's address of the no-allocation workspace array
 };
 
 struct pc_graph {
@@ -57,7 +59,29 @@ struct pc_graph {
     pc_order order;
 };
 
+// Workspace of pc_skeleton_noalloc: a static device array, one copy per GPU, held until the process
+// ends. In host code its name is only a stand-in: kernels and copies use the device address that
+// hipGetSymbolAddress returns for the current device (resolved once per device in pc_create).
+static __device__ __align__(256) unsigned char scratch[PC_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+
+// This device's address of `scratch` (the device must be current); resolved once per device.
+pc_status scratch_address(int dev, void **out) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (dev < 0 || dev >= kMaxDevices) return PC_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PC_ERR_HIP;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return PC_OK;
+}
 
 constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24, unit roundoff of FP32
 // Default bound on the CI tests of a lane per work item. When every row can have a work-group of
@@ -771,6 +795,7 @@ pc_status pc_create(pc_ctx **out, void *stream, const pc_options *opt) {
         c->recheck_grid = (nb > 0 ? std::min(nb, 4) : 4) * c->num_cu;
     }
     if (ok && ensure_binom(c, 8191) != PC_OK) ok = false;
+    if (ok && scratch_address(dev, &c->scratch) != PC_OK) ok = false;
     // Pinned staging for problem tables, so that single-problem calls need no allocation later.
     if (ok) {
         if (hipHostMalloc(&c->staging, (size_t)1 << 16, hipHostMallocDefault) == hipSuccess) c->staging_bytes = (size_t)1 << 16;
@@ -991,6 +1016,20 @@ pc_status pc_skeleton(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double
         st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;
+}
+
+pc_status pc_skeleton_noalloc(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double alpha, int max_level,
+                              uint64_t *adj_out, const pc_sepset *sep, pc_run_stats *st) {
+    if (!ctx || !sep) return PC_ERR_INVALID_ARG;
+    if (!ctx->scratch) return PC_ERR_HIP;
+    pc_status s = check_shape(n, m);
+    if (s != PC_OK) return s;
+    // Everything pc_skeleton would allocate must already exist: the workspace fits the array, the
+    // binomial table covers n, the problem table fits the pinned staging.
+    const Plan L = make_plan(&n, &m, 1, ctx->opt);
+    if (L.total > (size_t)PC_NOALLOC_SCRATCH_BYTES || n + 1 > ctx->binom_rows || L.table_bytes > ctx->staging_bytes)
+        return PC_ERR_WORKSPACE;
+    return pc_skeleton(ctx, X, m, n, alpha, max_level, adj_out, sep, st, ctx->scratch, PC_NOALLOC_SCRATCH_BYTES);
 }
 
 pc_status pc_batch_skeleton(pc_ctx *ctx, const pc_problem *probs, int count, pc_run_stats *st,
