@@ -53,7 +53,11 @@ C3_GOLDEN = os.path.join(ROOT, "tests", "golden", "n8000_d6_m2000_levels3.npz")
 PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix
 PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
-ROW_TOP = 2           # candidates per node the ordered forms test first at level 1
+# Level-1 orders compared on the headline workload (each the fastest of a sweep over its
+# parameters on this workload): candidates tested first per node (row_top), the remaining sets
+# enumerated by descending |C_ik| (row_sort) and run in two passes split at rank row_split.
+LEARNED_ORDER = dict(row_top=2, row_sort=True, row_split=32)   # + row_short = learn.ROW_SHORT
+ABS_ORDER = dict(row_top=1, row_sort=True, row_split=8)
 TAIL_TESTS = 2048     # c2 graph: levels with more CI tests than this run as level kernels
 TAIL_MAX_LEVEL = 8    # deepest level the tail kernel runs
 TRAFFIC = {
@@ -197,9 +201,9 @@ def headline(args, torch, pc, semgen, out):
             ctx = pc.Context(stream=stream, precision="fp32", graph_levels=graph_levels)
             order = None
             if mode == "learned":
-                order = ctx.order(None, row_params=row_w, row_top=ROW_TOP)
+                order = ctx.order(None, row_params=row_w, row_short=learn.ROW_SHORT, **LEARNED_ORDER)
             elif mode == "abs":
-                order = ctx.order(None, row_top=ROW_TOP, row_rank="abs")
+                order = ctx.order(None, row_rank="abs", **ABS_ORDER)
             adj = ctx.adjacency(n)
             recs, count = ctx.sepsets(n * (n - 1) // 2)
             probs = ctx.problems([(Xd, alpha, -1, adj, recs, count)])
@@ -257,7 +261,8 @@ def headline(args, torch, pc, semgen, out):
         "config": {"workload": "pc_stable_skeleton_n2000_deg10_m1000_alpha0.01_fp32_recheck_learned_order",
                    "n": n, "m": m, "expected_degree": 10, "alpha": alpha,
                    "precision": "fp32 CI tests + fp64 re-check of borderline tests",
-                   "order": {"form": "shared-set (row) model at level 1", "row_top": ROW_TOP,
+                   "order": {"form": "shared-set (row) model at level 1", **LEARNED_ORDER,
+                             "row_short": learn.ROW_SHORT, "abs_order": ABS_ORDER,
                              "weights": "paper_1812_08491_amd/weights/order_row_mlp_n200.npy",
                              "trained_on": "2000 generated SEMs, n=200, degree~U[2,10], m=1000"},
                    "step": "one replay of the whole skeleton captured as a hipGraph (pc_batch_capture_ordered)",

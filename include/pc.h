@@ -303,6 +303,11 @@ typedef struct {
     int32_t row_short;    /* row model only: 0 = it scores every candidate of a node; K in
                              row_top..64 = it scores only the K candidates of largest |C_ik| (ties:
                              lower position first), and the row_top chosen come from those */
+    int32_t row_sort;     /* 1: the candidates after the row_top chosen are enumerated by
+                             descending |C_ik| instead of ascending id (0) */
+    int32_t row_split;    /* > row_top: the remaining sets of level 1 run in two level-kernel passes,
+                             ranks [row_top, row_split) of every node first, then the rest; 0 = one
+                             pass */
 } pc_order;
 
 /* Workspace of pc_skeleton_ordered (the probe keeps its features and scores on chip, so this is
@@ -310,10 +315,13 @@ typedef struct {
 size_t pc_ordered_workspace_bytes(int64_t n, int64_t m, const pc_options *opt, const pc_order *order);
 
 /* pc_skeleton with a learned order of the conditioning sets (two forms, either or both):
- *  - shared-set order (row_params, row_top): at level 1 the model scores every candidate k of node
- *    i from (i, k) features (|C_ik|, |C_ik| over the row's largest, |N_i & N_k| / d_i and / d_k, d_i, d_k,
- *    the level, the row mean of |C_ij|), and the sets {k} of the row_top best are tested against
- *    every edge of the row before the rest of the enumeration (rows of degree <= 1024);
+ *  - shared-set order (row_top, with row_params or row_rank 1): at level 1 every node i of degree
+ *    2..1024 ranks its candidates k. k*, the candidate of largest |C_ik|, always comes first; the row
+ *    model picks the next row_top - 1 from (i, k) features (|C_ik|, |C_ik| over the row's largest,
+ *    the overlap of N_i and N_k against a random graph's, d_k / (d_i + d_k), |C_k k*|,
+ *    |rho_ik.k*|, the row mean of |C_ij| over its largest, |N_i & N_k| / d_i), or |C_ik| ranks
+ *    them all (row_rank 1). The sets {k} of the row_top chosen are tested against every edge of the
+ *    row before the rest of the enumeration (row_sort, row_split: how the rest is ordered and cut);
  *  - probe pass (params): before every level l with min_level <= l <= max_level and l <= top. The probe runs in one kernel per level: for every row i of G' with l + 1 <= d_i <= 48,
  * the MLP (BF16 weights and activations, FP32 accumulation) scores every candidate k of every
  * edge (i, j), and for every live edge the C(top, l) subsets of its best-scored candidates are

@@ -59,7 +59,8 @@ PC_MLP_PARAMS = 4801
 class pc_order(ct.Structure):
     _fields_ = [("params", ct.c_void_p), ("row_params", ct.c_void_p), ("min_level", ct.c_int32),
                 ("max_level", ct.c_int32), ("top", ct.c_int32), ("row_top", ct.c_int32),
-                ("row_rank", ct.c_int32), ("row_short", ct.c_int32)]
+                ("row_rank", ct.c_int32), ("row_short", ct.c_int32), ("row_sort", ct.c_int32),
+                ("row_split", ct.c_int32)]
 
 
 class pc_problem(ct.Structure):
@@ -432,19 +433,21 @@ class Context:
     # -- learned ordering ----------------------------------------------------------------------
     @staticmethod
     def order(params=None, min_level: int = 2, top: int = 4, max_level: int = 0, row_params=None,
-              row_top: int = 0, row_rank: str = "model", row_short: int = 0) -> pc_order:
+              row_top: int = 0, row_rank: str = "model", row_short: int = 0, row_sort: bool = False,
+              row_split: int = 0) -> pc_order:
         """Learned order: the probe pass of the edge model `params` at levels min_level .. max_level
         (0 = 8) that are <= top, and/or the shared-set order at level 1 (the row_top best candidates
         per node first), ranked by the row model `row_params` (row_rank "model"; with row_short > 0
         it scores only the row_short candidates of largest |C_ik|) or by |C_ik| alone
-        (row_rank "abs")."""
+        (row_rank "abs"); row_sort enumerates the remaining candidates by descending |C_ik|, and
+        row_split > row_top runs the remaining ranks in two passes split there."""
         torch = _torch()
         for p in (params, row_params):
             assert p is None or (p.is_cuda and p.dtype == torch.float32 and p.numel() == PC_MLP_PARAMS)
         rank = {"model": 0, "abs": 1}[row_rank]
         o = pc_order(params.data_ptr() if params is not None else None,
                      row_params.data_ptr() if row_params is not None else None,
-                     min_level, max_level, top, row_top, rank, row_short)
+                     min_level, max_level, top, row_top, rank, row_short, int(row_sort), row_split)
         o._keep = (params, row_params)    # the struct holds raw pointers: keep the tensors alive
         return o
 

@@ -308,6 +308,7 @@ Batch make_batch(const pc_ctx *ctx, const Plan &L, unsigned char *ws) {
     b.rank_lo = 0;
     b.rank_hi = ~0ull;
     b.probe = 0;
+    b.l1_perm = 0;
     b.probs = reinterpret_cast<Prob *>(ws + L.table);
     b.count = L.count;
     b.prec = L.prec;
@@ -473,9 +474,19 @@ pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, co
         // the remaining ranks; together they cover every set of the level once, on the same G'.
         const int T = ord->order->row_top;
         PC_HIP(launch_row_order(s, b, level, ord->order->row_params, T, ord->order->row_rank,
-                                ord->order->row_short, ctx->num_cu));
+                                ord->order->row_short, ord->order->row_sort, ctx->num_cu));
+        // The remaining ranks in one pass, or two (the strongest sets of every row first).
+        const int split = ord->order->row_split;
         Batch bm = b;
+        bm.l1_perm = ord->order->row_sort;
         bm.rank_lo = (unsigned long long)T;
+        if (split > T) {
+            bm.rank_hi = (unsigned long long)split;
+            PC_HIP(launch_window(s, bm, level, R));
+            PC_HIP(launch_level(s, bm, level, R, level_lds_bytes(ctx), auto_grid(ctx, level)));
+            bm.rank_lo = (unsigned long long)split;
+            bm.rank_hi = ~0ull;
+        }
         PC_HIP(launch_window(s, bm, level, R));
         PC_HIP(launch_level(s, bm, level, R, level_lds_bytes(ctx), auto_grid(ctx, level)));
     } else {
@@ -712,6 +723,7 @@ bool valid_order(const pc_order *o) {
     if (o->row_rank != 0 && o->row_rank != 1) return false;
     if (row_order_on(o)) {
         if (!(o->row_top >= 1 && o->row_top <= 16)) return false;
+        if ((o->row_sort != 0 && o->row_sort != 1) || o->row_split < 0) return false;
         if (o->row_short != 0 && (o->row_rank != 0 || o->row_short < o->row_top || o->row_short > 64)) return false;
     }
     return true;
@@ -1264,7 +1276,7 @@ pc_status pc_row_scores(pc_ctx *ctx, int64_t n, int64_t m, double alpha, const u
     pc_status s = features_setup(ctx, 1, n, m, alpha, adj, ws, ws_bytes, L, b);
     if (s != PC_OK) return s;
     PC_HIP(launch_row_order(ctx->stream, b, 1, order->row_params, order->row_top, order->row_rank, order->row_short,
-                            ctx->num_cu, scores, top));
+                            order->row_sort, ctx->num_cu, scores, top));
     PC_HIP(hipStreamSynchronize(ctx->stream));
     return PC_OK;
 }

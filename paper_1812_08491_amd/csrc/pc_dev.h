@@ -126,8 +126,21 @@ struct Batch {
     // whose tests and removals are also counted as probe statistics.
     unsigned long long rank_lo, rank_hi;
     int probe;
-    int pad2;
+    // Level 1 after the shared-set order with sorted enumeration: a row of G' that the order
+    // ranked (l1_ranked below) keeps its ascending neighbour list, and its set ranks t map to list
+    // positions through the permutation stored after the list, nbr[i*n + d + t].
+    int l1_perm;
 };
+
+// Rows the level-1 shared-set order ranks: degree up to kRowOrderCap and at most kRowOrderWords
+// adjacency words (both staged in LDS by the ordering kernel).
+constexpr int kRowOrderCap = 1024;
+constexpr int kRowOrderWords = 256;
+__host__ __device__ inline bool l1_ranked(int64_t d, int64_t W) { return d <= kRowOrderCap && W <= kRowOrderWords; }
+// The rank permutation fits after the neighbour list of a row of degree d when 2 d <= n.
+__host__ __device__ inline bool l1_perm_row(const Batch &b, int64_t d, int64_t W, int64_t n) {
+    return b.l1_perm && l1_ranked(d, W) && 2 * d <= n;
+}
 
 // The ranks [lo, hi) of a row with nS conditioning sets that a launch covers.
 __host__ __device__ inline void rank_window(const Batch &b, unsigned long long nS, unsigned long long &lo,
@@ -226,7 +239,8 @@ hipError_t launch_features(hipStream_t s, const Batch &b, int level, const long 
 // Shared-set order: reorders each row's neighbour list, the `top` best-scored candidates first, and
 // tests their sets. grid: compute units (the launch fills them).
 hipError_t launch_row_order(hipStream_t s, const Batch &b, int level, const float *params, int top, int by_abs,
-                            int short_k, int grid, float *scores_out = nullptr, int *top_out = nullptr);
+                            int short_k, int sort_rest, int grid, float *scores_out = nullptr,
+                            int *top_out = nullptr);
 // Training rows of the shared-set order (features, labels, meta (i, k)) after a compaction.
 hipError_t launch_row_features(hipStream_t s, const Batch &b, int level, long long *foff, long long cap, int *skip,
                                float *feats, float *labels, int *meta);

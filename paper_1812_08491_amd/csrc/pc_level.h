@@ -432,6 +432,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
     __shared__ unsigned long long s_stage_t[kStageCap];
     __shared__ unsigned long long s_rec_base;
     __shared__ int s_livepos[kDcap];   // positions p whose edge (i, N_i[p]) is live at item start
+    __shared__ int s_perm[L == 1 ? kLevelThreads : 1];   // level 1: list positions of the item's ranks
     __shared__ long long s_scan[kLevelThreads / 64];
 
     DevState *st = b.st;
@@ -586,20 +587,44 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         const long long r1 = (long long)whi < r0 + Rr ? (long long)whi : r0 + Rr;
         const long long nr = r1 - r0;
         // `split` threads share each conditioning set and divide its j loop; each group of them
-        // takes qn consecutive sets. At level 1 a set needs no factor, so a whole wavefront shares
-        // it: its lanes then read one row of C (or of the staged block) at consecutive neighbour
-        // positions, instead of 64 rows at once, and a wavefront's later sets skip the edges its
-        // earlier ones removed. Above (where sets are many and their j loops short), one thread per
-        // set, unless the item has fewer sets than threads.
+        // takes qn sets. At level 1 a set needs no factor, so up to a whole wavefront shares it: its
+        // lanes then read one row of C (or of the staged block) at consecutive neighbour positions,
+        // instead of 64 rows at once, and a group's later sets skip the edges its earlier ones
+        // removed. Above (where sets are many and their j loops short), one thread per set, unless
+        // the item has fewer sets than threads.
         int split = 1;
-        if (L <= kWaveSetLevels) split = 64;
-        else if (nr < kLevelThreads)
+        if (L <= kWaveSetLevels) {
+            // A set's lanes are sized to the live list: when few edges of the row are still live
+            // (a row left with its surviving edges, which every set must test), a wavefront takes
+            // several sets at once, and its lanes still carry about kBatch candidates each.
+            split = 64;
+            if ((mode & 5) == 5)
+                while (split > 4 && (split / 2) * 8 >= nlive) split >>= 1;
+        } else if (nr < kLevelThreads) {
             while (split * 2 * nr <= kLevelThreads) split *= 2;
+        }
         const int groups = kLevelThreads / split;
         const int slice = tid % split;
         const int qn = (int)((nr + groups - 1) / groups);
-        const long long my_t = r0 + (long long)(tid / split) * qn;
-        const long long my_end = my_t + qn < r1 ? my_t + qn : r1;
+        // Level 1: the wavefronts of an item take its sets round robin, so that all of them start
+        // with the item's first sets (the strongest, when the order sorted them). Above: each
+        // thread group takes qn consecutive sets and steps through them by the successor rule.
+        const bool interleave = L == 1;
+        const long long my_t = interleave ? r0 + tid / split : r0 + (long long)(tid / split) * qn;
+        const long long my_end = interleave ? r1 : (my_t + qn < r1 ? my_t + qn : r1);
+        const long long t_stride = interleave ? groups : 1;
+        // Level 1 after a sorted shared-set order: rank t is list position perm[t]; the item's
+        // positions are staged in LDS first (an item has at most kLevelThreads ranks at level 1),
+        // so the set loop does not wait on a global load per set.
+        const bool perm = L == 1 && l1_perm_row(b, d, W, n);
+        const bool perm_lds = perm && nr <= kLevelThreads;   // (more ranks per item: read in place)
+        const glb_ptr<const int> permg = (glb_ptr<const int>)(P.nbr + (int64_t)row * n + d);
+        if constexpr (L == 1) {
+            if (perm_lds) {
+                if (tid < nr) s_perm[tid] = permg[r0 + tid];
+                __syncthreads();
+            }
+        }
         int since_refresh = 0;
 
         int binoff = -1;
@@ -608,7 +633,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         int P_[L];
 #pragma unroll
         for (int c = 0; c < L; ++c) P_[c] = 0;
-        if (my_t < my_end) {
+        if (my_t < my_end && L > 1) {
             if (binoff > 0) comb_unrank<L>(d, (unsigned long long)my_t, P_, lbinom);
             else comb_unrank<L>(d, (unsigned long long)my_t, P_, binom);
         }
@@ -650,9 +675,10 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                 return (wv >> (j & 63)) & 1ull;
             };
             for (int step = 0; step < qn; ++step) {
-                const long long t = my_t + step;
+                const long long t = my_t + step * t_stride;
                 if (t >= my_end) break;
-                if (step > 0) comb_next<L>(d, P_);
+                if constexpr (L == 1) P_[0] = perm_lds ? s_perm[t - r0] : (perm ? permg[t] : (int)t);
+                else if (step > 0) comb_next<L>(d, P_);
 
                 // Shared per-S work: Cholesky of M2 = C[S,S], y = L^-1 C[S,i]^T, H11 = 1 - y.y.
                 SetFactor<T, L> f;
@@ -708,7 +734,9 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                             const int slot = atomicAdd(&s_nstage, 1);
                             if (slot < kStageCap) {
                                 s_stage_j[slot] = j;
-                                s_stage_t[slot] = (unsigned long long)t;
+                                // the rank; at level 1 the list position itself (rank and
+                                // position differ once the order sorted the sets)
+                                s_stage_t[slot] = L == 1 ? (unsigned long long)P_[0] : (unsigned long long)t;
                             } else {
                                 const int lo = row < j ? row : j, hi = row < j ? j : row;
                                 if (take_edge(P.adj, W, lo, hi)) {

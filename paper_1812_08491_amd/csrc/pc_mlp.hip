@@ -724,10 +724,13 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe(Batch b, const float *p
 // A conditioning set of the level kernel serves every edge of its row (the set sharing of cuPC-S,
 // Sec. 3.4), so the unit the model ranks here is the candidate k of node i. Its features, all
 // from quantities the method computes (C and G' at the start of the level):
-//   |C_ik|, |C_ik| / max_q |C_iq|, |N_i & N_k| / d_i, |N_i & N_k| / d_k, d_i / 256, d_k / 256,
-//   level / 8, the mean of |C_ij| over the row.
-constexpr int kRowCap = 1024;     // rows up to this degree are ranked (neighbour list in LDS)
-constexpr int kRowWords = 256;    // adjacency words of a row staged in LDS (n <= 16384)
+//   |C_ik|, |C_ik| / max_q |C_iq|, min(n |N_i & N_k| / (d_i d_k), 8) / 8, d_k / (d_i + d_k),
+//   |C_k k*| and |rho_ik.k*| (k* the candidate of largest |C_ik|; 1 and 0 for k = k*),
+//   mean_j |C_ij| / max_q |C_iq|, |N_i & N_k| / d_i.
+// The fifth and sixth tell the model how much a candidate adds to k*, which the order always tests
+// first; the model picks the others.
+constexpr int kRowCap = kRowOrderCap;      // rows up to this degree are ranked (neighbour list in LDS)
+constexpr int kRowWords = kRowOrderWords;  // adjacency words of a row staged in LDS (n <= 16384)
 constexpr int kRowTopMax = 16;
 constexpr int kRowShortMax = 64;   // longest short list the model scores (one tile per wavefront)
 
@@ -750,7 +753,8 @@ struct __align__(16) RowSmem {
     long long tests, removed;
     float red[4], redmax[4];
     float b3;
-    int taken[kRowCap];    // candidate already among the top (argmax rounds)
+    alignas(16) int taken[kRowCap];   // candidate chosen (argmax rounds); separated-by-k* flags
+    int kstar;             // position of the candidate of largest |C_ik| (lowest position on ties)
     int slist[kRowShortMax];     // short list: positions of the largest |C_ik|, in that order
     float sshort[kRowShortMax];  // model scores of the short list
     float bestv[4];
@@ -845,42 +849,71 @@ __device__ inline float stage_row(Smem &sm, const Prob &P, int row, int d, int t
     }
     for (int p = d + tid; p < ((d + 3) & ~3); p += nthreads) sm.ac[p] = -1.0f;
     for (int w = tid; w < W && w < kRowWords; w += nthreads) sm.arow[w] = P.adj[(int64_t)row * W + w];
-    float mx = 0.0f;
-    for (int p = tid; p < d; p += nthreads) mx = fmaxf(mx, sm.ac[p]);
+    // The largest |C_ik| and its lowest position.
+    float mx = -1.0f;
+    int mp = 0x7fffffff;
+    for (int p = tid; p < d; p += nthreads)
+        if (sm.ac[p] > mx) {   // ascending p per thread: the first maximum is kept
+            mx = sm.ac[p];
+            mp = p;
+        }
     for (int o = 32; o >= 1; o >>= 1) {
         s += __shfl_xor(s, o, 64);
-        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        const float om = __shfl_xor(mx, o, 64);
+        const int op = __shfl_xor(mp, o, 64);
+        if (om > mx || (om == mx && op < mp)) { mx = om; mp = op; }
     }
     if ((tid & 63) == 0) {
         sm.red[tid >> 6] = s;
         sm.redmax[tid >> 6] = mx;
+        sm.besti[tid >> 6] = mp;
     }
     __syncthreads();
-    rowmax = fmaxf(fmaxf(sm.redmax[0], sm.redmax[1]), fmaxf(sm.redmax[2], sm.redmax[3]));
+    float bm = sm.redmax[0];
+    int bp = sm.besti[0];
+    for (int w = 1; w < 4; ++w)
+        if (sm.redmax[w] > bm || (sm.redmax[w] == bm && sm.besti[w] < bp)) { bm = sm.redmax[w]; bp = sm.besti[w]; }
+    rowmax = bm > 0.0f ? bm : 0.0f;
+    if (tid == 0) sm.kstar = bp;
+    __syncthreads();
     return ((sm.red[0] + sm.red[1]) + (sm.red[2] + sm.red[3])) / (float)d;
 }
 
-// Features of candidate position p of the staged row (see above).
-template <class Smem>
+// Features of candidate position p of the staged row (see above). All of them are ratios or
+// correlations, so that a model trained on small graphs carries over to larger, sparser ones.
+template <typename T, class Smem>
 __device__ inline void row_features(const Smem &sm, const Prob &P, int d, int p, int level, float rowmean,
                                     float rowmax, float (&x)[kIn]) {
+    (void)level;
     const int64_t W = P.W;
+    const T *C = static_cast<const T *>(P.C);
     const float a = sm.ac[p];
     const int k = sm.nb[p];
+    const int ps = sm.kstar, ks = sm.nb[ps];
+    // C_k k*, and the partial correlation of i and k given k* (zero for k* itself)
+    const float ckk = p == ps ? 1.0f : (float)C[(int64_t)ks * P.n + k];
+    float rho = 0.0f;
+    if (p != ps) {
+        const float cik = (float)sm.ci[p], cis = (float)sm.ci[ps];
+        const float den = (1.0f - cis * cis) * (1.0f - ckk * ckk);
+        rho = den > 0.0f ? fminf(1.0f, fabsf(cik - cis * ckk) * __builtin_amdgcn_rsqf(den)) : 0.0f;
+    }
     // G is not written while the order is computed (before the level's tests), so plain loads.
     const unsigned long long *ak = P.adj + (int64_t)k * W;
     int cn = 0;   // |N_i & N_k| (the caller guarantees W <= kRowWords)
 #pragma unroll 8
     for (int64_t w = 0; w < W; ++w) cn += __popcll(sm.arow[w] & ak[w]);
-    const float dk = (float)P.deg[k];
+    const float di = (float)d, dk = (float)P.deg[k];
+    // overlap against a random graph of the same degrees: n |N_i & N_k| / (d_i d_k)
+    const float lift = dk > 0.0f ? (float)cn * (float)P.n / (di * dk) : 0.0f;
     x[0] = a;
     x[1] = rowmax > 0.0f ? a / rowmax : 0.0f;
-    x[2] = (float)cn / (float)d;
-    x[3] = dk > 0.0f ? (float)cn / dk : 0.0f;
-    x[4] = (float)d / 256.0f;
-    x[5] = dk / 256.0f;
-    x[6] = (float)level / 8.0f;
-    x[7] = rowmean;
+    x[2] = fminf(lift, 8.0f) / 8.0f;
+    x[3] = dk / (di + dk);
+    x[4] = fabsf(ckk);
+    x[5] = rho;
+    x[6] = rowmax > 0.0f ? rowmean / rowmax : 0.0f;
+    x[7] = (float)cn / di;
 }
 
 // One work-group per row of G' at level 1 (grid-stride), the first part of the level with the
@@ -898,7 +931,7 @@ template <typename T>
 // score at [i][k] (-inf for candidates outside the short list) and the chosen candidates at
 // top_out[i][0 .. top) (best first, -1 past the row's choices), and runs no test.
 __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const float *params, int top, int by_abs,
-                                                    int short_k, float *scores_out, int *top_out) {
+                                                    int short_k, int sort_rest, float *scores_out, int *top_out) {
     __shared__ RowSmem<T> sm;
     if (b.st->done) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -933,7 +966,7 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
         const int64_t n = P.n, W = P.W;
         const T *C = static_cast<const T *>(P.C);
         int *nbr = P.nbr + (int64_t)row * n;
-        const bool scored = d <= kRowCap && W <= kRowWords;
+        const bool scored = l1_ranked(d, W);
         const int T_ = top < d ? top : d;
         if (scored) {
             float rowmax = 0.0f;
@@ -948,9 +981,12 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
                 for (int p = tid; p < d; p += 256) {
                     const float a = sm.ac[p];
                     int r = 0;
-                    for (int q = 0; q < d; ++q) {
-                        const float c = sm.ac[q];
-                        r += (c > a || (c == a && q < p)) ? 1 : 0;
+                    for (int q = 0; q < d; q += 4) {   // entries past d hold -1
+                        const float4 c = *reinterpret_cast<const float4 *>(&sm.ac[q]);
+                        r += (c.x > a || (c.x == a && q < p)) ? 1 : 0;
+                        r += (c.y > a || (c.y == a && q + 1 < p)) ? 1 : 0;
+                        r += (c.z > a || (c.z == a && q + 2 < p)) ? 1 : 0;
+                        r += (c.w > a || (c.w == a && q + 3 < p)) ? 1 : 0;
                     }
                     sm.sc[p] = -INFINITY;
                     if (r < short_k) sm.slist[r] = p;
@@ -958,7 +994,7 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
                 __syncthreads();
                 for (int r0 = 64 * wave; r0 < short_k; r0 += 256) {
                     float x[kIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                    if (r0 + lane < short_k) row_features(sm, P, d, sm.slist[r0 + lane], level, rowmean, rowmax, x);
+                    if (r0 + lane < short_k) row_features<T>(sm, P, d, sm.slist[r0 + lane], level, rowmean, rowmax, x);
 #pragma unroll
                     for (int u = 0; u < kIn; ++u) sm.X[wave][lane][u] = bf16_rne(x[u]);
                     wave_sync_lds();
@@ -969,7 +1005,7 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
             } else {
                 for (int r0 = 64 * wave; r0 < d; r0 += 256) {
                     float x[kIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                    if (r0 + lane < d) row_features(sm, P, d, r0 + lane, level, rowmean, rowmax, x);
+                    if (r0 + lane < d) row_features<T>(sm, P, d, r0 + lane, level, rowmean, rowmax, x);
 #pragma unroll
                     for (int u = 0; u < kIn; ++u) sm.X[wave][lane][u] = bf16_rne(x[u]);
                     wave_sync_lds();
@@ -979,6 +1015,12 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
             }
             for (int p = d + tid; p < ((d + 3) & ~3); p += 256) sm.sc[p] = -INFINITY;
             __syncthreads();
+            // The model picks the candidates after k* (largest |C_ik|), which always comes first
+            // (written once every wavefront's scores are in).
+            if (!by_abs) {
+                if (tid == 0) sm.sc[sm.kstar] = INFINITY;
+                __syncthreads();
+            }
             // The top T_ by score: T_ rounds of a work-group argmax (ties: lower position first).
             for (int p = tid; p < d; p += 256) sm.taken[p] = 0;
             __syncthreads();
@@ -1015,15 +1057,58 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
                 if (tid < top) top_out[(int64_t)row * top + tid] = tid < T_ ? sm.nb[sm.toppos[tid]] : -1;
                 continue;
             }
-            // New order: the top candidates by rank, then the others in their (ascending) order.
-            for (int p = tid; p < d; p += 256) {
-                int pos = -1, below = 0;
-                for (int u = 0; u < T_; ++u) {
-                    const int tp = sm.toppos[u];
-                    if (tp == p) pos = u;
-                    below += tp < p ? 1 : 0;
+            if (sort_rest && 2 * (int64_t)d <= n) {
+                // Sorted enumeration: the list stays ascending (the level kernel's lanes then read
+                // ascending columns of C), and the set order goes after it as a permutation of
+                // positions: the chosen candidates, then the others by descending |C_ik| in 256
+                // buckets (a counting sort; the order inside a bucket is that of the LDS atomics,
+                // which only changes which separating set a level finds first).
+                int *cnt = sm.stage;    // bucket counters, then offsets (free until the tests)
+                cnt[tid] = 0;
+                __syncthreads();
+                int mine[4], slot[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int p = tid + 256 * c;
+                    mine[c] = -1;
+                    if (p < d && !sm.taken[p]) {
+                        const int key = (int)(sm.ac[p] * 255.99f);
+                        mine[c] = 255 - (key < 0 ? 0 : (key > 255 ? 255 : key));
+                        slot[c] = atomicAdd(&cnt[mine[c]], 1);
+                    }
                 }
-                nbr[pos >= 0 ? pos : T_ + p - below] = sm.nb[p];
+                __syncthreads();
+                if (tid < 64) {   // exclusive scan of the 256 counters, four per lane
+                    int v[4], tot = 0;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) { v[c] = cnt[4 * tid + c]; tot += v[c]; }
+                    int incl = tot;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int t = __shfl_up(incl, o, 64);
+                        if (tid >= o) incl += t;
+                    }
+                    int run = incl - tot;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) { cnt[4 * tid + c] = run; run += v[c]; }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (mine[c] >= 0) nbr[d + T_ + cnt[mine[c]] + slot[c]] = tid + 256 * c;
+                if (tid < T_) nbr[d + tid] = sm.toppos[tid];
+                __syncthreads();   // the counters' storage is the tests' staging area
+            } else {
+                // New order: the top candidates by rank, then the others in their (ascending) order.
+                for (int p = tid; p < d; p += 256) {
+                    int pos = -1, below = 0;
+                    for (int u = 0; u < T_; ++u) {
+                        const int tp = sm.toppos[u];
+                        if (tp == p) pos = u;
+                        below += tp < p ? 1 : 0;
+                    }
+                    nbr[pos >= 0 ? pos : T_ + p - below] = sm.nb[p];
+                }
             }
         } else if (tid < T_) {
             sm.toppos[tid] = tid;   // too long to score: the first positions, order unchanged
@@ -1115,9 +1200,11 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
 }
 
 // Training rows of the shared-set order at level 1: the features of every candidate k of every
-// node i, and as label the fraction of the other edges (i, j), j in N_i \ {k}, that {k} separates by
-// the FP32 test |rho_ij.k| <= tanh(tau_1) (Eq. 3-6 at l = 1, without the re-check band), so the
-// model ranks first the candidates that remove the most edges. meta gets (i, k).
+// node i, and a label from the FP32 test |rho_ij.k| <= tanh(tau_1) (Eq. 3-6 at l = 1, without the
+// re-check band) over the other edges (i, j), j in N_i \ {k}: for k*, the candidate of largest
+// |C_ik|, the fraction of them that {k*} separates; for every other k, the fraction that {k}
+// separates and {k*} does not. The model thus ranks k* by what it removes and the others by what
+// they add to it, which is what the second and later choices are worth. meta gets (i, k).
 template <typename T>
 __global__ __launch_bounds__(256) void k_row_features(Batch b, int level, const long long *foff, float *feats,
                                                       float *labels, int *meta, const int *skip) {
@@ -1136,9 +1223,19 @@ __global__ __launch_bounds__(256) void k_row_features(Batch b, int level, const 
     const T *C = static_cast<const T *>(P.C);
     const float tl = (float)tanh(P.tau[1]);
     const long long base = foff[grow];
+    auto separates = [&](int q, int k, float cik) -> bool {   // {k} separates (i, N_i[q])
+        const int j = sm.nb[q];
+        const float cij = (float)C[(int64_t)row * n + j], cjk = (float)C[(int64_t)j * n + k];
+        const float den = (1.0f - cik * cik) * (1.0f - cjk * cjk);
+        return den > 0.0f && fabsf(cij - cik * cjk) <= tl * sqrtf(den);
+    };
+    const int ps = sm.kstar, kst = sm.nb[ps];
+    const float cist = (float)C[(int64_t)row * n + kst];
+    for (int q = tid; q < d; q += 256) sm.taken[q] = q != ps && separates(q, kst, cist) ? 1 : 0;
+    __syncthreads();
     for (int p = tid; p < d; p += 256) {
         float x[kIn];
-        row_features(sm, P, d, p, level, rowmean, rowmax, x);
+        row_features<T>(sm, P, d, p, level, rowmean, rowmax, x);
         float *f = feats + (base + p) * kIn;
 #pragma unroll
         for (int u = 0; u < kIn; ++u) f[u] = x[u];
@@ -1147,10 +1244,8 @@ __global__ __launch_bounds__(256) void k_row_features(Batch b, int level, const 
         int sep = 0;
         for (int q = 0; q < d; ++q) {
             if (q == p) continue;
-            const int j = sm.nb[q];
-            const float cij = (float)C[(int64_t)row * n + j], cjk = (float)C[(int64_t)j * n + k];
-            const float den = (1.0f - cik * cik) * (1.0f - cjk * cjk);
-            sep += (den > 0.0f && fabsf(cij - cik * cjk) <= tl * sqrtf(den)) ? 1 : 0;
+            if (p != ps && sm.taken[q]) continue;   // already separated by k*
+            sep += separates(q, k, cik) ? 1 : 0;
         }
         labels[base + p] = d > 1 ? (float)sep / (float)(d - 1) : 0.0f;
         if (meta) {
@@ -1163,23 +1258,25 @@ __global__ __launch_bounds__(256) void k_row_features(Batch b, int level, const 
 // grid: compute units; as many work-groups per unit as fit are launched.
 template <typename T>
 static hipError_t launch_row_order_t(hipStream_t s, const Batch &b, int level, const float *params, int top,
-                                     int by_abs, int short_k, int grid, float *scores_out, int *top_out) {
+                                     int by_abs, int short_k, int sort_rest, int grid, float *scores_out,
+                                     int *top_out) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_row_order<T>, 256, 0) != hipSuccess || per_cu < 1)
         per_cu = 2;
     hipLaunchKernelGGL(k_row_order<T>, dim3(per_cu * grid), dim3(256), 0, s, b, level, params, top, by_abs, short_k,
-                       scores_out, top_out);
+                       sort_rest, scores_out, top_out);
     return hipGetLastError();
 }
 
 hipError_t launch_row_order(hipStream_t s, const Batch &b, int level, const float *params, int top, int by_abs,
-                            int short_k, int grid, float *scores_out, int *top_out) {
+                            int short_k, int sort_rest, int grid, float *scores_out, int *top_out) {
     if (top < 1 || top > kRowTopMax || short_k < 0 || short_k > kRowShortMax) return hipErrorInvalidValue;
     if (!by_abs && !params) return hipErrorInvalidValue;
     if ((scores_out != nullptr) != (top_out != nullptr) || (scores_out && b.count != 1)) return hipErrorInvalidValue;
     if (b.prec == PC_PREC_FP64)
-        return launch_row_order_t<double>(s, b, level, params, top, by_abs, short_k, grid, scores_out, top_out);
-    return launch_row_order_t<float>(s, b, level, params, top, by_abs, short_k, grid, scores_out, top_out);
+        return launch_row_order_t<double>(s, b, level, params, top, by_abs, short_k, sort_rest, grid, scores_out,
+                                          top_out);
+    return launch_row_order_t<float>(s, b, level, params, top, by_abs, short_k, sort_rest, grid, scores_out, top_out);
 }
 
 hipError_t launch_row_features(hipStream_t s, const Batch &b, int level, long long *foff, long long cap, int *skip,

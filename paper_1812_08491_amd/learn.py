@@ -30,6 +30,7 @@ WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights"
 DEFAULT_WEIGHTS = os.path.join(WEIGHTS_DIR, "order_mlp_n200.npy")
 ROW_WEIGHTS = os.path.join(WEIGHTS_DIR, "order_row_mlp_n200.npy")
 PROBE_MAX_LEVEL = 8     # the probe pass runs for levels 1 .. 8
+ROW_SHORT = 8           # the row model scores the 8 candidates of largest |C_ik| of a node
 
 
 def _torch():
@@ -277,47 +278,6 @@ class NodeRowCollector:
         self.ctx.close()
 
 
-def edge_coverage(scores, node, cand, C, adj_dense, alpha: float, m: int, tops=(1, 2, 4, 8)) -> dict:
-    """For one dataset: the fraction of level-1-separable edges (i, j) of G' (some k in N_i or N_j
-    gives |rho_ij.k| <= tanh(tau_1)) that a set {k} of the T best-scored candidates of i or of j
-    separates, for each T in tops."""
-    torch = _torch()
-    from ._lib import pc_threshold
-    n = C.shape[0]
-    th = math.tanh(pc_threshold(alpha, m, 1))
-    G = adj_dense
-    Cd = C.double()
-    # independence of (i, j) given k for all triples with k adjacent to i or j
-    ii, jj = torch.nonzero(torch.triu(G, 1), as_tuple=True)
-    if ii.numel() == 0:
-        return {T: float("nan") for T in tops}
-    cij, cik, cjk = Cd[ii, jj].unsqueeze(1), Cd[ii], Cd[jj]
-    den = ((1 - cik ** 2) * (1 - cjk ** 2)).clamp_min(0)
-    indep = ((cij - cik * cjk).abs() <= th * den.sqrt()) & (den > 0)
-    kmask = (G[ii] | G[jj])
-    kmask[torch.arange(ii.numel()), ii] = False
-    kmask[torch.arange(ii.numel()), jj] = False
-    sep = (indep & kmask).any(1)
-    # rank of each candidate within its node by score (ties: lower candidate id first)
-    rank = torch.full((n, n), 1 << 30, dtype=torch.long, device="cuda")
-    order = torch.argsort(cand.double() - scores.double() * 1e6, stable=True)   # score desc, then id
-    order = order[torch.argsort(node[order], stable=True)]
-    nd = node[order]
-    start = torch.ones_like(nd, dtype=torch.bool)
-    start[1:] = nd[1:] != nd[:-1]
-    seg = torch.cumsum(start.long(), 0) - 1
-    first = torch.nonzero(start).squeeze(1)
-    rank[nd, cand[order]] = torch.arange(nd.numel(), device="cuda") - first[seg]
-    out = {}
-    for T in tops:
-        topk = (rank < T)
-        cover = indep & ((topk[ii] & G[ii]) | (topk[jj] & G[jj]))
-        cover[torch.arange(ii.numel()), ii] = False
-        cover[torch.arange(ii.numel()), jj] = False
-        out[T] = float((cover.any(1) & sep).sum().item() / max(int(sep.sum().item()), 1))
-    return out
-
-
 def compare_orders(X, alpha: float, params, precision: str = "fp32", min_level: int = 2, top: int = 4,
                    repeats: int = 3, max_level: int = 0, row_params=None, row_top: int = 0):
     """Plain vs learned-order skeleton on the same data: identical adjacency is required; returns
@@ -368,19 +328,40 @@ def compare_orders(X, alpha: float, params, precision: str = "fp32", min_level: 
     return {"same_skeleton": same, **res}
 
 
+def short_list_mask(absc, node, K: int):
+    """Rows (grouped by node, ascending candidate position within a node) whose |C_ik| (absc) is
+    among the K largest of their node, ties to the lower position: the candidates the row model
+    scores when pc_order.row_short = K."""
+    torch = _torch()
+    order = torch.argsort(-absc.double(), stable=True)
+    order = order[torch.argsort(node[order], stable=True)]
+    nd = node[order]
+    start = torch.ones_like(nd, dtype=torch.bool)
+    start[1:] = nd[1:] != nd[:-1]
+    seg = torch.cumsum(start.long(), 0) - 1
+    first = torch.nonzero(start).squeeze(1)
+    rank = torch.empty_like(order)
+    rank[order] = torch.arange(nd.numel(), device=nd.device) - first[seg]
+    return rank < K
+
+
 def train_rows(args, log) -> None:
-    """Shared-set (row) model: level-1 rows of generated n = 200 SEMs, weighted BCE, and the edge
-    coverage of its top-T candidates per node against |C_ik| order and a random order."""
+    """Shared-set (row) model: level-1 rows of generated n = 200 SEMs, restricted to each node's
+    short list (the ROW_SHORT candidates of largest |C_ik|), soft-label cross-entropy, Adam. With
+    --eval, the edge coverage of its top-T candidates per node is reported against the |C_ik| order
+    and a random order on held-out SEMs (tests/ref/coverage.py; run from the repository root)."""
     torch = _torch()
     import semgen
     from ._lib import bits_to_dense
+    K = args.short
     t0 = time.time()
     coll = NodeRowCollector(200, 1000)
     feats, labels = [], []
     for k, (X, _, a) in enumerate(semgen.training_sems(args.sems, instance=0)):
-        f, y, _, _, _ = coll.run(X, a)
-        feats.append(f)
-        labels.append(y)
+        f, y, mi, _, _ = coll.run(X, a)
+        keep = short_list_mask(f[:, 0], mi, K)
+        feats.append(f[keep])
+        labels.append(y[keep])
         if (k + 1) % 200 == 0:
             log(f"collected {k + 1} datasets, {sum(x.shape[0] for x in feats)} rows, {time.time() - t0:.1f} s")
     X = torch.cat(feats)
@@ -388,45 +369,63 @@ def train_rows(args, log) -> None:
     t_collect = time.time() - t0
     pos = float(y.sum().item())
     pos_weight = 1.0   # soft labels (fractions of the row's edges separated): plain cross-entropy
-    log(f"{X.shape[0]} training rows, mean label {pos / max(y.numel(), 1):.3f}")
+    log(f"{X.shape[0]} training rows (short lists of {K}), mean label {pos / max(y.numel(), 1):.3f}")
     val = []
     for Xv, _, a in semgen.training_sems(args.val_sems, instance=1):
         f, yv, mi, mk, C = coll.run(Xv, a)
         G = torch.from_numpy(bits_to_dense(coll.adj.cpu().numpy(), 200).astype(bool)).cuda()
-        val.append((f, yv, mi, mk, C, G, a))
+        val.append((f, yv, mi, mk, C, G, a, short_list_mask(f[:, 0], mi, K)))
     trainer = Trainer(seed=args.seed, lr=args.lr)
 
     def coverage(score_fn):
+        from tests.ref.coverage import edge_coverage
         acc = {T: [] for T in (1, 2, 4, 8)}
-        for f, yv, mi, mk, C, G, a in val:
-            cov = edge_coverage(score_fn(f), mi, mk, C, G, a, 1000)
+        for f, yv, mi, mk, C, G, a, sl in val:
+            cov = edge_coverage(score_fn(f, sl), mi, mk, C, G, a, 1000)
             for T in acc:
                 if cov[T] == cov[T]:
                     acc[T].append(cov[T])
         return {T: float(np.mean(v)) if v else float("nan") for T, v in acc.items()}
 
-    base_abs = coverage(lambda f: f[:, 0].contiguous())
-    base_rand = coverage(lambda f: torch.rand(f.shape[0], device="cuda"))
-    log(f"|C_ik| order coverage@1/2/4/8: {base_abs[1]:.3f} {base_abs[2]:.3f} {base_abs[4]:.3f} {base_abs[8]:.3f}")
-    log(f"random order coverage@1/2/4/8: {base_rand[1]:.3f} {base_rand[2]:.3f} {base_rand[4]:.3f} {base_rand[8]:.3f}")
-    vX = torch.cat([v[0] for v in val])
-    vy = torch.cat([v[1] for v in val])
+    def learned(f, sl):
+        sc = trainer.scores_of(f)
+        return torch.where(sl, sc, torch.full_like(sc, -1e30))
+
+    base_abs = base_rand = None
+    if args.eval:
+        base_abs = coverage(lambda f, sl: f[:, 0].contiguous())
+        base_rand = coverage(lambda f, sl: torch.rand(f.shape[0], device="cuda"))
+        log(f"|C_ik| order coverage@1/2/4/8: {base_abs[1]:.3f} {base_abs[2]:.3f} {base_abs[4]:.3f} {base_abs[8]:.3f}")
+        log(f"random order coverage@1/2/4/8: {base_rand[1]:.3f} {base_rand[2]:.3f} {base_rand[4]:.3f} "
+            f"{base_rand[8]:.3f}")
+    vX = torch.cat([v[0][v[7]] for v in val])
+    vy = torch.cat([v[1][v[7]] for v in val])
     history = []
     t1 = time.time()
     for ep in range(args.epochs):
         tl = trainer.epoch(X, y, pos_weight)
         vl = bce_loss(trainer, vX, vy, pos_weight)
-        cov = coverage(lambda f: trainer.scores_of(f))
-        history.append({"epoch": ep + 1, "train_loss": tl, "val_loss": vl, "coverage": cov})
-        log(f"epoch {ep + 1}: train {tl:.4f} val {vl:.4f} coverage@1/2/4/8 {cov[1]:.3f} {cov[2]:.3f} {cov[4]:.3f} "
-            f"{cov[8]:.3f}")
+        h = {"epoch": ep + 1, "train_loss": tl, "val_loss": vl}
+        msg = f"epoch {ep + 1}: train {tl:.4f} val {vl:.4f}"
+        if args.eval:
+            cov = coverage(learned)
+            h["coverage"] = cov
+            msg += f" coverage@1/2/4/8 {cov[1]:.3f} {cov[2]:.3f} {cov[4]:.3f} {cov[8]:.3f}"
+        history.append(h)
+        log(msg)
     t_train = time.time() - t1
     coll.close()
     out = args.out or ROW_WEIGHTS
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     np.save(out, trainer.params.cpu().numpy().astype(np.float32), allow_pickle=False)
     meta = {"model": "row", "sems": args.sems, "n": 200, "m": 1000, "degree": "U[2,10]", "alpha": 0.01,
-            "rows": int(X.shape[0]), "positive_fraction": pos / max(y.numel(), 1), "pos_weight": pos_weight,
+            "row_short": K, "label": "k*: fraction of the row's edges it separates; others: fraction they "
+                                     "separate and k* does not",
+            "features": ["|C_ik|", "|C_ik|/max_q|C_iq|", "min(n|N_i&N_k|/(d_i d_k), 8)/8", "d_k/(d_i+d_k)",
+                         "|C_kk*|", "|rho_ik.k*|", "mean_j|C_ij|/max_q|C_iq|", "|N_i&N_k|/d_i"],
+            "order": "k* (largest |C_ik|) first; the model picks the next from the row_short candidates of "
+                     "largest |C_ik|",
+            "rows": int(X.shape[0]), "mean_label": pos / max(y.numel(), 1), "pos_weight": pos_weight,
             "epochs": args.epochs, "lr": args.lr, "batch": trainer.batch, "collect_s": t_collect, "train_s": t_train,
             "abs_corr_coverage": base_abs, "random_coverage": base_rand, "history": history}
     with open(os.path.splitext(out)[0] + ".json", "w") as f:
@@ -446,6 +445,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--short", type=int, default=ROW_SHORT, help="row model: candidates per node it scores")
+    ap.add_argument("--eval", action="store_true", help="row model: report held-out edge coverage")
     args = ap.parse_args(argv)
     import semgen  # the project's seeded SEM generator (repository root)
     torch = _torch()

@@ -197,7 +197,8 @@ def test_training_pipeline_beats_random_order_and_keeps_skeleton():
 
 def test_row_features_match_recomputation():
     """Shared-set (row) features and labels of level 1 against values recomputed on the host from
-    the same FP32 C and G'."""
+    the same FP32 C and G': the label of k* (largest |C_ik|) is the fraction of the row's other
+    edges {k*} separates; that of any other k, the fraction {k} separates and {k*} does not."""
     rng = np.random.default_rng(21)
     n, m, alpha = 90, 400, 0.05
     X = semgen.sample(semgen.random_dag(n, 0.08, rng), m, rng)
@@ -218,20 +219,39 @@ def test_row_features_match_recomputation():
     F, Y, M = feats.cpu().numpy(), labels.cpu().numpy(), meta.cpu().numpy()
     assert [tuple(r) for r in M] == [(i, k) for i in range(n) for k in np.flatnonzero(G[i])]
     th = math.tanh(pc.pc_threshold(alpha, m, 1))
+
+    def sep_bounds(i, k, js):
+        # {k} separates (i, j): sure (outside FP32 ties) and possible (ties either way)
+        lhs = np.abs(Cn[i, js] - Cn[i, k] * Cn[js, k])
+        rhs = th * np.sqrt(np.clip((1 - Cn[i, k] ** 2) * (1 - Cn[js, k] ** 2), 0, None))
+        ties = np.abs(lhs - rhs) < 1e-5
+        return (lhs <= rhs) & ~ties, (lhs <= rhs) | ties
+
     checked = 0
     for r, (i, k) in enumerate(M):
         Ni = np.flatnonzero(G[i])
         d = Ni.size
         a = np.abs(Cn[i, Ni])
         p = int(np.flatnonzero(Ni == k)[0])
+        ps = int(np.argmax(a))                 # k*: largest |C_ik|, first position on ties
+        ks = int(Ni[ps])
         cn = int(np.sum(G[i] & G[k]))
-        want = [a[p], a[p] / a.max(), cn / d, cn / deg[k] if deg[k] else 0.0, d / 256, deg[k] / 256, 1 / 8, a.mean()]
+        ckk = 1.0 if p == ps else Cn[ks, k]
+        den = (1 - Cn[i, ks] ** 2) * (1 - ckk ** 2)
+        rho = 0.0 if p == ps or den <= 0 else min(1.0, abs(Cn[i, k] - Cn[i, ks] * ckk) / math.sqrt(den))
+        lift = cn * n / (d * deg[k])
+        want = [a[p], a[p] / a.max(), min(lift, 8.0) / 8.0, deg[k] / (d + deg[k]), abs(ckk), rho,
+                a.mean() / a.max(), cn / d]
         assert np.allclose(F[r], want, atol=2e-5), (i, k, F[r], want)
         js = Ni[Ni != k]
-        lhs = np.abs(Cn[i, js] - Cn[i, k] * Cn[js, k])
-        rhs = th * np.sqrt((1 - Cn[i, k] ** 2) * (1 - Cn[js, k] ** 2))
-        ties = np.abs(lhs - rhs) < 1e-5          # FP32 ties: either decision is right
-        lo_, hi_ = np.sum((lhs <= rhs) & ~ties), np.sum((lhs <= rhs) | ties)
+        sure, maybe = sep_bounds(i, k, js)
+        if p != ps:
+            # what {k} separates beyond {k*}
+            sure_s, maybe_s = sep_bounds(i, ks, js)
+            sure_s &= js != ks                 # {k*} is not tested against its own edge
+            maybe_s &= js != ks
+            sure, maybe = sure & ~maybe_s, maybe & ~sure_s
+        lo_, hi_ = int(np.sum(sure)), int(np.sum(maybe))
         assert lo_ / max(d - 1, 1) - 1e-6 <= Y[r] <= hi_ / max(d - 1, 1) + 1e-6, (i, k, Y[r], lo_, hi_)
         checked += 1
     assert checked == rows and Y.sum() > 0
@@ -342,7 +362,8 @@ def _expected_picks(vals, T):
 @pytest.mark.parametrize("seed,row_short", [(0, 0), (1, 0), (2, 8)])
 def test_row_scorer_matches_fp64_network(seed, row_short):
     """k_row_order's BF16 MFMA scores equal the FP64 reference forward (oracle/mlp.py) of the same
-    features within the BF16 error bound, and its picks are the top of its own scores.
+    features within the BF16 error bound, and its picks are k* (largest |C_ik|) and then the top of
+    its own scores.
 
     Bound: inputs, W1, W2 and the first hidden layer are rounded to BF16 (relative u = 2^-9 each),
     so |dz1| <= 2u a1 (+ u a1 for rounding h1), |dz2| <= 4u a2 and |ds| <= 4u s_bar to first order,
@@ -379,6 +400,10 @@ def test_row_scorer_matches_fp64_network(seed, row_short):
         ks = M[rows, 1]
         assert list(ks) == list(np.flatnonzero(G[i]))
         got = S[i, ks].astype(np.float64)
+        # k* (largest |C_ik|, first position on ties) always comes first: its score is +inf
+        ps = _expected_picks(list(F[rows, 0]), 1)[0]
+        assert got[ps] == np.inf
+        got[ps] = s_ref[rows][ps]
         if row_short and deg[i] > row_short:
             short = set(_expected_picks(list(F[rows, 0]), row_short))   # |C_ik|, ties: lower position
             inside = np.array([q in short for q in range(len(ks))])
@@ -388,16 +413,21 @@ def test_row_scorer_matches_fp64_network(seed, row_short):
         err = np.abs(got[inside] - s_ref[rows][inside])
         assert np.all(err <= bound[rows][inside]), (i, err.max(), bound[rows][inside].max())
         checked += int(inside.sum())
-        # picks: the top T of the kernel's own scores, best first, ties to the lower position
-        want = [int(ks[q]) for q in _expected_picks(list(got), min(T, len(ks)))]
+        # picks: k*, then the top of the kernel's own scores, best first, ties to the lower position
+        own = got.copy()
+        own[ps] = np.inf
+        want = [int(ks[q]) for q in _expected_picks(list(own), min(T, len(ks)))]
         assert list(top[i, :len(want)]) == want, (i, top[i], want)
         assert np.all(top[i, len(want):] == -1)
-        # and, within the bound, the top T of the reference scores
-        ref_sorted = np.sort(s_ref[rows][inside])[::-1]
-        kth = ref_sorted[min(T, inside.sum()) - 1]
-        for k in want:
-            q = int(np.flatnonzero(ks == k)[0])
-            assert s_ref[rows][q] >= kth - 2 * bound[rows].max(), (i, k)
+        # and, within the bound, the top of the reference scores among the others
+        others = inside.copy()
+        others[ps] = False
+        if others.sum() >= 1 and T > 1:
+            ref_sorted = np.sort(s_ref[rows][others])[::-1]
+            kth = ref_sorted[min(T - 1, others.sum()) - 1]
+            for k in want[1:]:
+                q = int(np.flatnonzero(ks == k)[0])
+                assert s_ref[rows][q] >= kth - 2 * bound[rows].max(), (i, k)
     assert checked > 1000
 
 
@@ -423,3 +453,40 @@ def test_row_scorer_abs_mode_ranks_by_abs_corr():
         assert np.array_equal(S[i, ks], np.abs(Cn[i, ks]))
         want = [int(ks[q]) for q in _expected_picks(list(np.abs(Cn[i, ks])), min(4, ks.size))]
         assert list(top[i, :len(want)]) == want
+
+
+@pytest.mark.parametrize("seed,prec,rank,sort,split", [(0, "fp32", "abs", True, 0), (1, "fp32", "abs", True, 16),
+                                                       (2, "fp64", "model", True, 8), (3, "bf16x3", "abs", False, 12),
+                                                       (4, "fp32", "model", True, 32)])
+def test_sorted_and_split_level1_equals_oracle(seed, prec, rank, sort, split):
+    """Level 1 with the remaining sets enumerated by descending |C_ik| (a permutation stored after
+    each ascending neighbour list; rows with 2 d > n fall back to moving the chosen to the front)
+    and/or split into two level-kernel passes: the skeleton is the oracle's, every removal level
+    matches and every SepSet separates. Dense and sparse rows are both present (n ~ 60-200)."""
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(60, 200))
+    # a dense block (its rows have 2 d > n after level 0) inside a sparse graph
+    sem = semgen.random_dag(n, float(rng.uniform(0.05, 0.12)), rng)
+    X = semgen.sample(sem, int(rng.integers(300, 1200)), rng)
+    k = n // 4
+    Z = rng.standard_normal((X.shape[0], 1))
+    X[:, :k] += 2.0 * Z
+    alpha = 0.05
+    row_params = dev(mlp.init(rng))
+    kw = dict(row_top=2, row_sort=sort, row_split=split)
+    if rank == "abs":
+        kw["row_rank"] = "abs"
+    else:
+        kw.update(row_params=row_params, row_short=8)
+    G, seps, st, status = ordered_run(X, alpha, None, prec, **kw)
+    C = oracle.corr(X)
+    ref = oracle.skeleton_corr(C, X.shape[0], alpha, keep_levels=True)
+    assert status == 0
+    assert np.array_equal(G, ref.G), np.argwhere(G != ref.G)[:8]
+    ref_seps = ref.sepsets.as_dict()
+    assert set(seps) == set(ref_seps)
+    for e, (l, S) in seps.items():
+        assert ref_seps[e][0] == l
+        assert oracle.ci_test(C, e[0], e[1], list(S), X.shape[0], alpha)[0], (e, S)
+    Gp = ref.G_after[0]
+    assert (2 * Gp.sum(1) > n).any() and (2 * Gp.sum(1) <= n).any()
