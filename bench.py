@@ -137,13 +137,16 @@ def write_traffic(leg: str, fetch_csv: str, write_csv: str, copy_fetch_csv: str,
     cw, _ = per_dispatch(copy_write_csv, "__amd_rocclr_copyBuffer")
     f_fetch, f_write = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
     kernels, total = {}, 0.0
+    # a level-1 pass dispatches the first kernel of the list once (and k_level once per pass of a
+    # split order): per-pass bytes = all dispatches' bytes / the first kernel's dispatches
+    _, passes = per_dispatch(fetch_csv, LEVEL1_KERNELS[leg][0])
     for k in LEVEL1_KERNELS[leg]:
         fetch, nf = per_dispatch(fetch_csv, k)
         write, nw = per_dispatch(write_csv, k)
         b = (fetch * f_fetch + write * f_write) * 1024.0
         kernels[k] = {"fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
-                      "bytes_per_launch": b}
-        total += b
+                      "bytes_per_launch": b, "launches_per_pass": nf / max(passes, 1)}
+        total += b * nf / max(passes, 1)
     out = {"leg": leg, "kernels": kernels, "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": f_fetch, "write_scale": f_write, "bytes_per_pass": total,
            "source_hash": level_source_hash()}
@@ -192,7 +195,8 @@ def headline(args, torch, pc, semgen, out):
     eadj = ectx.adjacency(n)
     erecs, ecount = ectx.sepsets(n * (n - 1) // 2)
     est = pc.pc_run_stats()
-    assert ectx.pc_skeleton(Xd, alpha, eadj, erecs, ecount, ectx.workspace(n, m), stats=est) == 0
+    eorder = ectx.order(None, row_params=row_w, row_short=learn.ROW_SHORT, **LEARNED_ORDER)
+    assert ectx.pc_skeleton_ordered(Xd, alpha, eadj, erecs, ecount, ectx.workspace(n, m), eorder, stats=est) == 0
     graph_levels = max(1, est.levels_run - 1)
     stream = torch.cuda.Stream()
     modes = {}

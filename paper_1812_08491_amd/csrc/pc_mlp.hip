@@ -757,6 +757,7 @@ struct __align__(16) RowSmem {
     int kstar;             // position of the candidate of largest |C_ik| (lowest position on ties)
     int slist[kRowShortMax];     // short list: positions of the largest |C_ik|, in that order
     float sshort[kRowShortMax];  // model scores of the short list
+    int scn[kRowShortMax];       // |N_i & N_k| of the short list
     float bestv[4];
     int besti[4];
 };
@@ -883,7 +884,7 @@ __device__ inline float stage_row(Smem &sm, const Prob &P, int row, int d, int t
 // correlations, so that a model trained on small graphs carries over to larger, sparser ones.
 template <typename T, class Smem>
 __device__ inline void row_features(const Smem &sm, const Prob &P, int d, int p, int level, float rowmean,
-                                    float rowmax, float (&x)[kIn]) {
+                                    float rowmax, float (&x)[kIn], int cn_given = -1) {
     (void)level;
     const int64_t W = P.W;
     const T *C = static_cast<const T *>(P.C);
@@ -899,10 +900,13 @@ __device__ inline void row_features(const Smem &sm, const Prob &P, int d, int p,
         rho = den > 0.0f ? fminf(1.0f, fabsf(cik - cis * ckk) * __builtin_amdgcn_rsqf(den)) : 0.0f;
     }
     // G is not written while the order is computed (before the level's tests), so plain loads.
-    const unsigned long long *ak = P.adj + (int64_t)k * W;
-    int cn = 0;   // |N_i & N_k| (the caller guarantees W <= kRowWords)
+    int cn = cn_given;   // |N_i & N_k| (the caller guarantees W <= kRowWords)
+    if (cn < 0) {
+        const unsigned long long *ak = P.adj + (int64_t)k * W;
+        cn = 0;
 #pragma unroll 8
-    for (int64_t w = 0; w < W; ++w) cn += __popcll(sm.arow[w] & ak[w]);
+        for (int64_t w = 0; w < W; ++w) cn += __popcll(sm.arow[w] & ak[w]);
+    }
     const float di = (float)d, dk = (float)P.deg[k];
     // overlap against a random graph of the same degrees: n |N_i & N_k| / (d_i d_k)
     const float lift = dk > 0.0f ? (float)cn * (float)P.n / (di * dk) : 0.0f;
@@ -981,6 +985,7 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
                 for (int p = tid; p < d; p += 256) {
                     const float a = sm.ac[p];
                     int r = 0;
+#pragma unroll 8
                     for (int q = 0; q < d; q += 4) {   // entries past d hold -1
                         const float4 c = *reinterpret_cast<const float4 *>(&sm.ac[q]);
                         r += (c.x > a || (c.x == a && q < p)) ? 1 : 0;
@@ -991,10 +996,20 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
                     sm.sc[p] = -INFINITY;
                     if (r < short_k) sm.slist[r] = p;
                 }
+                // |N_i & N_k| of the short list, all threads at once: one (candidate, word) pair
+                // each, so the adjacency rows of the K candidates are read in one round.
+                if (tid < short_k) sm.scn[tid] = 0;
+                __syncthreads();
+                for (int e = tid; e < short_k * (int)W; e += 256) {
+                    const int r = e / (int)W, w = e - r * (int)W;
+                    const int c = __popcll(sm.arow[w] & P.adj[(int64_t)sm.nb[sm.slist[r]] * W + w]);
+                    if (c) atomicAdd(&sm.scn[r], c);
+                }
                 __syncthreads();
                 for (int r0 = 64 * wave; r0 < short_k; r0 += 256) {
                     float x[kIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                    if (r0 + lane < short_k) row_features<T>(sm, P, d, sm.slist[r0 + lane], level, rowmean, rowmax, x);
+                    if (r0 + lane < short_k)
+                        row_features<T>(sm, P, d, sm.slist[r0 + lane], level, rowmean, rowmax, x, sm.scn[r0 + lane]);
 #pragma unroll
                     for (int u = 0; u < kIn; ++u) sm.X[wave][lane][u] = bf16_rne(x[u]);
                     wave_sync_lds();
