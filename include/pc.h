@@ -77,7 +77,8 @@ typedef struct {
                                   inside a captured graph. */
     int64_t recheck_cap;       /* capacity of the FP64 re-check queue in tests per level
                                   (0 = automatic: the sum of n^2/4 over the batch, at least
-                                  2^16, at most 2^25); a level that needs more returns
+                                  2^17, at most 2^25), held in 16 equal slices that work-groups
+                                  fill by their index; a level that fills a slice returns
                                   PC_ERR_WORKSPACE */
     int32_t graph_levels;      /* levels recorded in a captured graph (pc_batch_capture; 0 = 10).
                                   A replay whose datasets need more levels continues them on the

@@ -128,7 +128,7 @@ bool valid_options(const pc_options &o) {
 // with BF16x3, whose split error dominates its band).
 int64_t rq_cap_of(const pc_options &o, double sum_n2) {
     if (o.recheck_cap > 0) return o.recheck_cap;
-    return std::min<int64_t>((int64_t)1 << 25, std::max<int64_t>((int64_t)1 << 16, (int64_t)(sum_n2 / 4.0)));
+    return std::min<int64_t>((int64_t)1 << 25, std::max<int64_t>((int64_t)1 << 17, (int64_t)(sum_n2 / 4.0)));
 }
 
 int graph_levels_of(const pc_options &o) { return o.graph_levels > 0 ? o.graph_levels : 10; }

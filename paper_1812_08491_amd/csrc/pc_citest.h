@@ -51,23 +51,34 @@ __device__ inline void write_record(const Prob &P, int lo, int hi, int level, co
 
 // Pushes a test to the re-check queue; cls is the FP32 classification (0 dependent, 1 independent,
 // 2 inside the band). The lanes of a wavefront that reach this call together reserve consecutive
-// slots with one atomic add by the lowest of them: same-address device atomics serialise, and a
-// level can push millions of tests (BF16x3 bands).
+// slots with one atomic add by the lowest of them, in the queue slice of their work-group: same-
+// address device atomics serialise, and a level can push millions of tests (BF16x3 bands). Lanes
+// that find the slice full move on to the next slices; only when every slice is full is the test
+// dropped and the overflow flagged.
 template <int L>
 __device__ inline void push_recheck(const Batch &b, int d, int row, int j, const int (&sid)[L], int cls) {
-    const unsigned long long act = __ballot(1);
     const int lane = (int)__lane_id();
-    const int leader = __ffsll((long long)act) - 1;
-    const unsigned long long cnt = (unsigned long long)__popcll(act);
-    unsigned long long base = 0ull;
-    if (lane == leader) {
-        base = atomicAdd(&b.st->rq_count, cnt);
-        if (base + cnt > (unsigned long long)b.rq_cap) atomicOr(&b.st->rq_overflow, 1);
+    const unsigned long long cap_s = (unsigned long long)(b.rq_cap / kRqSlices);
+    unsigned long long act = __ballot(1);          // lanes still without a slot (uniform)
+    int slice = (int)(blockIdx.x % kRqSlices);
+    long long pos = -1;
+    for (int tries = 0; tries < kRqSlices && act; ++tries) {
+        const int leader = __ffsll((long long)act) - 1;
+        unsigned long long base = 0ull;
+        if (lane == leader) base = atomicAdd(&b.st->rq_slice[slice], (unsigned long long)__popcll(act));
+        base = __shfl(base, leader, 64);
+        if (pos < 0 && ((act >> lane) & 1ull)) {
+            const unsigned long long k = base + (unsigned long long)__popcll(act & ((1ull << lane) - 1ull));
+            if (k < cap_s) pos = (long long)((unsigned long long)slice * cap_s + k);
+        }
+        act = __ballot(pos < 0);
+        slice = slice + 1 == kRqSlices ? 0 : slice + 1;
     }
-    base = __shfl(base, leader, 64);
-    const unsigned long long k = base + (unsigned long long)__popcll(act & ((1ull << lane) - 1ull));
-    if (k >= (unsigned long long)b.rq_cap) return;
-    RqEntry *e = b.rq + k;
+    if (pos < 0) {
+        atomicOr(&b.st->rq_overflow, 1);
+        return;
+    }
+    RqEntry *e = b.rq + pos;
     e->prob = d;
     e->i = row;
     e->j = j;

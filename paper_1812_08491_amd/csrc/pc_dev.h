@@ -83,16 +83,23 @@ struct Prob {
     int maxdeg[kLevels];
 };
 
+// The re-check queue is cut into kRqSlices slices with a counter each; a work-group pushes to the
+// slice of its index, so the pushes of a level (millions on the BF16x3 path) do not all serialise
+// on one address.
+constexpr int kRqSlices = 16;
+
 // Device-resident queue state of the current level (one per batch).
 struct DevState {
     unsigned long long total_items;  // work items planned for the current level
     unsigned long long next_item;    // queue head (atomic)
-    unsigned long long rq_count;     // entries pushed to the re-check queue this level
+    unsigned long long rq_slice[kRqSlices];   // entries pushed to each re-check queue slice this level
     int done;                        // 1 once a planning pass found no work in any problem
     int overflow;                    // a row's subset count exceeded the supported range
-    int rq_overflow;                 // the re-check queue filled up
+    int rq_overflow;                 // a re-check queue slice filled up
     int pad[3];
 };
+static_assert(sizeof(DevState) <= 64 * sizeof(int), "the re-arm kernel clears DevState with 64 threads");
+
 
 // Re-check queue entry: a test whose FP32 decision fell in the error band (or, on the FP64 path,
 // whose M2 is rank deficient).
@@ -130,6 +137,28 @@ struct Batch {
     // ranked (l1_ranked below) keeps its ascending neighbour list, and its set ranks t map to list
     // positions through the permutation stored after the list, nbr[i*n + d + t].
     int l1_perm;
+};
+
+
+// The re-check entries of a level: slice s holds min(rq_slice[s], cap_s) entries from index
+// s * cap_s on, cap_s = rq_cap / kRqSlices. Entries are numbered 0 .. total() - 1 across slices.
+struct RqView {
+    long long cap_s;
+    long long start[kRqSlices + 1];
+    __device__ explicit RqView(const Batch &b) {
+        cap_s = b.rq_cap / kRqSlices;
+        start[0] = 0;
+        for (int s = 0; s < kRqSlices; ++s) {
+            const unsigned long long c = b.st->rq_slice[s];
+            start[s + 1] = start[s] + (c < (unsigned long long)cap_s ? (long long)c : cap_s);
+        }
+    }
+    __device__ long long total() const { return start[kRqSlices]; }
+    __device__ long long index(long long e) const {   // queue position of entry e
+        int s = 0;
+        while (s + 1 < kRqSlices && start[s + 1] <= e) ++s;
+        return (long long)s * cap_s + (e - start[s]);
+    }
 };
 
 // Rows the level-1 shared-set order ranks: degree up to kRowOrderCap and at most kRowOrderWords

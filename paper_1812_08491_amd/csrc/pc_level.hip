@@ -102,12 +102,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level, int w
         b.item_off[N] = total;
         st->total_items = (unsigned long long)total;
         st->next_item = 0ull;
-        if (!window) {
-            st->rq_count = 0ull;
-            if (total == 0) st->done = 1;
-        }
+        if (!window && total == 0) st->done = 1;
     }
     if (window) return;   // a window of a planned level: its statistics and stop flag stand
+    if (tid < kRqSlices) st->rq_slice[tid] = 0ull;   // a new level's re-check queue
     __syncthreads();
     // Levels the tail kernel already ran keep the statistics it recorded.
     for (int d = tid; d < b.count; d += kPlanThreads)

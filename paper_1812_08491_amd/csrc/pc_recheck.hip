@@ -22,15 +22,15 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck(Batch b, int level) {
     __shared__ int s_v[kW][16];
     __shared__ int s_prob, s_cls;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const unsigned long long pushed = b.st->rq_count;
-    const long long count = pushed < (unsigned long long)b.rq_cap ? (long long)pushed : b.rq_cap;
+    const RqView view(b);
+    const long long count = view.total();
     const int l = level, k = l + 2;
     RcStats rs;
     if (count <= 2 * (long long)gridDim.x) {
         double *Gw = G[0];
         int *vw = s_v[0];
         for (long long e = blockIdx.x; e < count; e += gridDim.x) {
-            const RqEntry *qe = b.rq + e;
+            const RqEntry *qe = b.rq + view.index(e);
             if (tid < 16) vw[tid] = tid == 0 ? qe->i : (tid == 1 ? qe->j : (tid < k ? (int)qe->S[tid - 2] : -1));
             if (tid == 0) {
                 s_prob = qe->prob;
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck(Batch b, int level) {
         double *Gw = G[wave];
         int *vw = s_v[wave];
         for (long long e = (long long)blockIdx.x * kW + wave; e < count; e += (long long)gridDim.x * kW) {
-            const RqEntry *qe = b.rq + e;
+            const RqEntry *qe = b.rq + view.index(e);
             if (lane < 16) vw[lane] = lane == 0 ? qe->i : (lane == 1 ? qe->j : (lane < k ? (int)qe->S[lane - 2] : -1));
             const int prob = qe->prob, cls = qe->cls;
             wave_sync();
@@ -129,12 +129,12 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_deep(Batch b, int level)
     __shared__ int s_v[32];        // variables of the tile rows: i, j, S..., then -1
     __shared__ int s_prob, s_cls;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const unsigned long long pushed = b.st->rq_count;
-    const long long count = pushed < (unsigned long long)b.rq_cap ? (long long)pushed : b.rq_cap;
+    const RqView view(b);
+    const long long count = view.total();
     const int l = level, k = l + 2;
     RcStats rs;
     for (long long e = blockIdx.x; e < count; e += gridDim.x) {
-        const RqEntry *qe = b.rq + e;
+        const RqEntry *qe = b.rq + view.index(e);
         if (tid < 32) s_v[tid] = tid == 0 ? qe->i : (tid == 1 ? qe->j : (tid < k ? (int)qe->S[tid - 2] : -1));
         if (tid == 0) {
             s_prob = qe->prob;
