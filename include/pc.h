@@ -78,8 +78,13 @@ typedef struct {
     int64_t recheck_cap;       /* capacity of the FP64 re-check queue in tests per level
                                   (0 = automatic: the sum of n^2/4 over the batch, at least
                                   2^17, at most 2^25), held in 16 equal slices that work-groups
-                                  fill by their index; a level that fills a slice returns
-                                  PC_ERR_WORKSPACE */
+                                  fill by their index, spilling to the next slice. A level whose
+                                  borderline tests fill every slice stops the level loop; the
+                                  library then completes that level and the levels after it in
+                                  FP64 (C recomputed in FP64 from the standardized data of the
+                                  workspace), so the result stays exact (pc_run_stats.fp64_from).
+                                  Only the tail kernel (tail_tests), whose share of the queue is
+                                  recheck_cap / problems, still returns PC_ERR_WORKSPACE. */
     int32_t graph_levels;      /* levels recorded in a captured graph (pc_batch_capture; 0 = 10).
                                   A replay whose datasets need more levels continues them on the
                                   stream in pc_graph_results. */
@@ -127,7 +132,10 @@ typedef struct {
                                                 in removed) */
     int32_t max_degree[PC_MAX_LEVEL + 1];/* max degree of G' at the start of the level (0 at level 0) */
     int32_t levels_run;                  /* levels executed, level 0 included */
-    int32_t pad;
+    int32_t fp64_from;                   /* 0, or the level from which the run was completed in
+                                            FP64 because the FP64 re-check queue (recheck_cap)
+                                            overflowed there; that level's counts include both of
+                                            its passes */
     float prep_ms;                       /* column statistics + standardization (timing & 16) */
     float corr_ms;                       /* correlation GEMM with the level-0 test (timing & 1) */
     float compact_ms[PC_MAX_LEVEL + 1];  /* compaction + planning of level l (timing & 4) */

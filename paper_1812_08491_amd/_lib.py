@@ -77,7 +77,7 @@ class pc_run_stats(ct.Structure):
                 ("rechecks", ct.c_int64 * _NL), ("items", ct.c_int64 * _NL),
                 ("audit_violations", ct.c_int64 * _NL), ("probe_tests", ct.c_int64 * _NL),
                 ("probe_removed", ct.c_int64 * _NL), ("max_degree", ct.c_int32 * _NL),
-                ("levels_run", ct.c_int32), ("pad", ct.c_int32), ("prep_ms", ct.c_float),
+                ("levels_run", ct.c_int32), ("fp64_from", ct.c_int32), ("prep_ms", ct.c_float),
                 ("corr_ms", ct.c_float), ("compact_ms", ct.c_float * _NL),
                 ("level_ms", ct.c_float * _NL), ("recheck_ms", ct.c_float * _NL),
                 ("wall_ms", ct.c_double)]
@@ -86,6 +86,7 @@ class pc_run_stats(ct.Structure):
         k = max(1, self.levels_run)
         return {
             "levels_run": self.levels_run,
+            "fp64_from": self.fp64_from,
             "tests": list(self.tests[:k]),
             "removed": list(self.removed[:k]),
             "rechecks": list(self.rechecks[:k]),

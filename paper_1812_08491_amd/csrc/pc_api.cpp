@@ -196,7 +196,7 @@ pc_status check_shape(int64_t n, int64_t m) {
 // Workspace layout of a batch
 // ---------------------------------------------------------------------------------------------
 struct Region {
-    size_t mu, inv, zt64, zlo, zhi, c, adj, nbr, deg;
+    size_t mu, inv, zt64, zlo, zhi, c, c64, adj, nbr, deg;
 };
 
 struct Plan {
@@ -253,6 +253,8 @@ Plan make_plan(const int64_t *ns, const int64_t *ms, int count, const pc_options
                      : L.prec == PC_PREC_BF16X3 ? sizeof(uint16_t) * n * mp : 0);
         r.zhi = take(L.prec == PC_PREC_BF16X3 ? sizeof(uint16_t) * n * mp : 0);
         r.c = take((L.prec == PC_PREC_FP64 ? sizeof(double) : sizeof(float)) * n * n);
+        // FP64 copy of C for a level whose FP32 re-check queue overflows (redone in FP64)
+        r.c64 = take(L.prec == PC_PREC_FP64 ? 0 : sizeof(double) * n * n);
         r.adj = take(sizeof(unsigned long long) * n * (size_t)words_per_row((int64_t)n));
         r.nbr = take(sizeof(int32_t) * n * n);
         r.deg = take(sizeof(int32_t) * n);
@@ -309,6 +311,7 @@ Batch make_batch(const pc_ctx *ctx, const Plan &L, unsigned char *ws) {
     b.rank_hi = ~0ull;
     b.probe = 0;
     b.l1_perm = 0;
+    b.corr_only = 0;
     b.probs = reinterpret_cast<Prob *>(ws + L.table);
     b.count = L.count;
     b.prec = L.prec;
@@ -389,8 +392,10 @@ int ranks_per_item(const pc_ctx *ctx, int level) {
     return q * kLevelThreads;
 }
 
-int level_lds_bytes(const pc_ctx *ctx) {
-    const size_t fixed = level_lds_fixed(ctx->opt.precision);
+// Dynamic LDS of a level launch: the kernel's fixed part for its precision (the context's, or
+// FP64 for a promoted level) and the row-staging budget.
+int level_lds_bytes(const pc_ctx *ctx, int prec = -1) {
+    const size_t fixed = level_lds_fixed(prec >= 0 ? prec : ctx->opt.precision);
     size_t budget = (size_t)ctx->opt.lds_budget;
     const size_t limit = 60 * 1024 - fixed;  // with the kernel's static staging, within 64 KiB
     if (budget > limit) budget = limit;
@@ -483,14 +488,14 @@ pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, co
         if (split > T) {
             bm.rank_hi = (unsigned long long)split;
             PC_HIP(launch_window(s, bm, level, R));
-            PC_HIP(launch_level(s, bm, level, R, level_lds_bytes(ctx), auto_grid(ctx, level)));
+            PC_HIP(launch_level(s, bm, level, R, level_lds_bytes(ctx, b.prec), auto_grid(ctx, level)));
             bm.rank_lo = (unsigned long long)split;
             bm.rank_hi = ~0ull;
         }
         PC_HIP(launch_window(s, bm, level, R));
-        PC_HIP(launch_level(s, bm, level, R, level_lds_bytes(ctx), auto_grid(ctx, level)));
+        PC_HIP(launch_level(s, bm, level, R, level_lds_bytes(ctx, b.prec), auto_grid(ctx, level)));
     } else {
-        PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx), auto_grid(ctx, level)));
+        PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx, b.prec), auto_grid(ctx, level)));
     }
     if (timed_level(ctx, level, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][1], s));
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][0], s));
@@ -607,7 +612,7 @@ pc_status problem_result(const Prob &P, const DevState &ds, pc_run_stats *st) {
     }
     if (P.err) return (pc_status)P.err;
     if (ds.overflow) return PC_ERR_UNSUPPORTED;
-    if (ds.rq_overflow) return PC_ERR_WORKSPACE;
+    if (ds.rq_overflow || ds.rq_overflow_tail) return PC_ERR_WORKSPACE;
     return res;
 }
 
@@ -630,12 +635,13 @@ pc_status results(const std::vector<Prob> &host, const DevState &ds, pc_run_stat
 
 // Copies the problem table and queue state back (synchronising) and fills per-problem results.
 pc_status collect(pc_ctx *ctx, size_t table_off, size_t st_off, int count, unsigned char *ws,
-                  pc_run_stats *st, pc_status *status, std::vector<Prob> &host) {
+                  pc_run_stats *st, pc_status *status, std::vector<Prob> &host, DevState *ds_out = nullptr) {
     host.resize(count);
     DevState ds;
     PC_HIP(hipMemcpyAsync(host.data(), ws + table_off, sizeof(Prob) * count, hipMemcpyDeviceToHost, ctx->stream));
     PC_HIP(hipMemcpyAsync(&ds, ws + st_off, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
     PC_HIP(hipStreamSynchronize(ctx->stream));
+    if (ds_out) *ds_out = ds;
     return results(host, ds, st, status);
 }
 
@@ -713,6 +719,54 @@ pc_status enqueue_skeletons(pc_ctx *ctx, const pc_problem *pp, int count, const 
     if (top < 2) return PC_OK;
     if ((s = enqueue_plan(ctx, b, 2, false)) != PC_OK) return s;
     return run_levels_eager(ctx, b, L, ws, 2, top, po);
+}
+
+// The FP32 (or BF16x3) re-check queue of `level` overflowed, so the device stopped the level loop
+// after that level with some borderline tests undecided. Every decision that was made is exact
+// (outside the error band, or re-checked in FP64), so the level is completed by testing it again in
+// FP64: C in FP64 from the standardized data (the GEMM without its level-0 epilogue), the level's
+// sets over its own snapshot G' (still in the neighbour lists: no later compaction ran), and the
+// remaining levels in FP64 as well. Removals already made, and their SepSets, stand.
+pc_status promote_fp64(pc_ctx *ctx, const Plan &L, unsigned char *ws, std::vector<Prob> &host, int level, int top) {
+    hipStream_t s = ctx->stream;
+    for (int d = 0; d < L.count; ++d) host[d].C = ws + L.reg[d].c64;
+    pc_status st = upload_table(ctx, L, ws, host);
+    if (st != PC_OK) return st;
+    Batch b = make_batch(ctx, L, ws);
+    b.prec = PC_PREC_FP64;
+    Batch bc = b;
+    bc.corr_only = 1;
+    PC_HIP(launch_corr(s, bc, L.tiles, ctx->num_cu));
+    PC_HIP(launch_rearm(s, b));
+    const int R = ranks_per_item(ctx, level);
+    PC_HIP(launch_window(s, b, level, R));
+    PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx, PC_PREC_FP64), auto_grid(ctx, level)));
+    PC_HIP(launch_recheck(s, b, level, ctx->recheck_grid));
+    ctx->top_run = std::max(ctx->top_run, level);
+    if (level >= top) return PC_OK;
+    if ((st = enqueue_plan(ctx, b, level + 1, false)) != PC_OK) return st;
+    return run_levels_eager(ctx, b, L, ws, level + 1, top, nullptr);
+}
+
+// collect(), after completing in FP64 a level whose re-check queue overflowed (see promote_fp64).
+// *promoted: 0, or the level from which the run went on in FP64 (also in every st[d].fp64_from).
+pc_status collect_promoting(pc_ctx *ctx, const Plan &L, unsigned char *ws, int top, pc_run_stats *st,
+                            pc_status *status, std::vector<Prob> &host, int *promoted = nullptr) {
+    DevState ds;
+    if (promoted) *promoted = 0;
+    const pc_status r = collect(ctx, L.table, L.st, L.count, ws, st, status, host, &ds);
+    if (L.prec == PC_PREC_FP64 || ds.rq_overflow <= 0 || ds.rq_overflow_tail || r == PC_ERR_HIP) return r;
+    const pc_status s = promote_fp64(ctx, L, ws, host, ds.rq_overflow, top);
+    if (s != PC_OK) return s;
+    pc_status s2;
+    const pc_status r2 = collect(ctx, L.table, L.st, L.count, ws, st, status, host);
+    // The table points at the plan's own C again (a captured graph replays with it).
+    for (int d = 0; d < L.count; ++d) host[d].C = ws + L.reg[d].c;
+    if (r2 != PC_ERR_HIP && (s2 = upload_table(ctx, L, ws, host)) != PC_OK) return s2;
+    if (st)
+        for (int d = 0; d < L.count; ++d) st[d].fp64_from = ds.rq_overflow;
+    if (promoted) *promoted = ds.rq_overflow;
+    return r2;
 }
 
 bool valid_order(const pc_order *o) {
@@ -914,7 +968,8 @@ pc_status level_common(pc_ctx *ctx, int level, int64_t n, int64_t m, double alph
     if ((s = enqueue_level(ctx, b, level, false)) != PC_OK) return s;
     std::vector<Prob> host;
     pc_status status = PC_OK;
-    const pc_status r = collect(ctx, L.table, L.st, 1, w, nullptr, &status, host);
+    int promoted = 0;
+    const pc_status r = collect_promoting(ctx, L, w, level, nullptr, &status, host, &promoted);
     if (r < 0 && r != PC_ERR_SEPSET_CAPACITY) return r;
     const Prob &P = host[0];
     if (st) {
@@ -924,6 +979,7 @@ pc_status level_common(pc_ctx *ctx, int level, int64_t n, int64_t m, double alph
         st->items[level] = P.items[level];
         st->audit_violations[level] = P.audit_viol[level];
         st->max_degree[level] = P.maxdeg[level];
+        st->fp64_from = promoted;
         const int tm = ctx->opt.timing;
         if (tm & 4) (void)hipEventElapsedTime(&st->compact_ms[level], ctx->ev_compact[level][0], ctx->ev_compact[level][1]);
         if (tm & 2) (void)hipEventElapsedTime(&st->level_ms[level], ctx->ev_level[level][0], ctx->ev_level[level][1]);
@@ -1021,7 +1077,7 @@ pc_status pc_skeleton(pc_ctx *ctx, const double *X, int64_t m, int64_t n, double
     if ((s = enqueue_skeletons(ctx, &p, 1, L, w, false)) != PC_OK) return s;
     std::vector<Prob> host;
     pc_status status = PC_OK;
-    const pc_status r = collect(ctx, L.table, L.st, 1, w, st, &status, host);
+    const pc_status r = collect_promoting(ctx, L, w, levels_to_enqueue(&p, 1), st, &status, host);
     if (r == PC_ERR_HIP) return r;
     if (st) {
         fill_times(ctx, st, ctx->top_run);
@@ -1055,7 +1111,7 @@ pc_status pc_batch_skeleton(pc_ctx *ctx, const pc_problem *probs, int count, pc_
     unsigned char *w = static_cast<unsigned char *>(ws);
     if ((s = enqueue_skeletons(ctx, probs, count, L, w, false)) != PC_OK) return s;
     std::vector<Prob> host;
-    const pc_status r = collect(ctx, L.table, L.st, count, w, st, status, host);
+    const pc_status r = collect_promoting(ctx, L, w, levels_to_enqueue(probs, count), st, status, host);
     if (st) {
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         for (int d = 0; d < count; ++d) st[d].wall_ms = ms;
@@ -1145,7 +1201,8 @@ pc_status pc_graph_results(pc_graph *g, pc_run_stats *st, pc_status *status) {
         }
     }
     std::vector<Prob> host;
-    return collect(ctx, g->table_off, g->st_off, g->count, g->ws, st, status, host);
+    const Plan L = plan_of(g->probs.data(), g->count, ctx->opt);
+    return collect_promoting(ctx, L, g->ws, g->top, st, status, host);
 }
 
 void pc_graph_destroy(pc_graph *g) {
@@ -1185,7 +1242,7 @@ pc_status pc_skeleton_ordered(pc_ctx *ctx, const double *X, int64_t m, int64_t n
     if ((s = enqueue_skeletons(ctx, &p, 1, L, w, false, order)) != PC_OK) return s;
     std::vector<Prob> host;
     pc_status status = PC_OK;
-    const pc_status r = collect(ctx, L.table, L.st, 1, w, st, &status, host);
+    const pc_status r = collect_promoting(ctx, L, w, levels_to_enqueue(&p, 1), st, &status, host);
     if (r == PC_ERR_HIP) return r;
     if (st) {
         fill_times(ctx, st, ctx->top_run);

@@ -57,6 +57,8 @@ __device__ inline void write_record(const Prob &P, int lo, int hi, int level, co
 // dropped and the overflow flagged.
 template <int L>
 __device__ inline void push_recheck(const Batch &b, int d, int row, int j, const int (&sid)[L], int cls) {
+    // Once the queue has overflowed, the level will be redone: further pushes are moot.
+    if (__hip_atomic_load(&b.st->rq_overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const int lane = (int)__lane_id();
     const unsigned long long cap_s = (unsigned long long)(b.rq_cap / kRqSlices);
     unsigned long long act = __ballot(1);          // lanes still without a slot (uniform)
@@ -75,7 +77,10 @@ __device__ inline void push_recheck(const Batch &b, int d, int row, int j, const
         slice = slice + 1 == kRqSlices ? 0 : slice + 1;
     }
     if (pos < 0) {
-        atomicOr(&b.st->rq_overflow, 1);
+        // The level's result would be incomplete: record it and stop the level loop, so that the
+        // host can redo this level (in FP64) from its snapshot G', which no later level overwrote.
+        atomicMax(&b.st->rq_overflow, L);
+        b.st->done = 1;
         return;
     }
     RqEntry *e = b.rq + pos;

@@ -346,6 +346,7 @@ __global__ __launch_bounds__(256) void k_corr(Batch bt) {
                 const T val = (T)acc[mi][nj][v];
                 C[ar * a.n + b] = val;
                 C[b * a.n + ar] = val;
+                if (bt.corr_only) continue;   // C alone (an FP64 copy for a promoted level)
                 bool keep, border = false;
                 if constexpr (PREC == PC_PREC_FP64) {
                     keep = !(fisher_z((double)val) <= tau0);
@@ -394,6 +395,7 @@ __global__ __launch_bounds__(256) void k_corr(Batch bt) {
         __syncthreads();
     }
 
+    if (bt.corr_only) return;
     const int64_t W = a.W;
     if (tid < kT) {
         const int64_t r = a0 + tid;

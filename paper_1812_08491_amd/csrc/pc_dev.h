@@ -95,8 +95,10 @@ struct DevState {
     unsigned long long rq_slice[kRqSlices];   // entries pushed to each re-check queue slice this level
     int done;                        // 1 once a planning pass found no work in any problem
     int overflow;                    // a row's subset count exceeded the supported range
-    int rq_overflow;                 // a re-check queue slice filled up
-    int pad[3];
+    int rq_overflow;                 // 0, or the level whose re-check queue filled up (the level loop
+                                     // then stops: done is set)
+    int rq_overflow_tail;            // a problem's share of the queue filled up in the tail kernel
+    int pad[2];
 };
 static_assert(sizeof(DevState) <= 64 * sizeof(int), "the re-arm kernel clears DevState with 64 threads");
 
@@ -137,6 +139,7 @@ struct Batch {
     // ranked (l1_ranked below) keeps its ascending neighbour list, and its set ranks t map to list
     // positions through the permutation stored after the list, nbr[i*n + d + t].
     int l1_perm;
+    int corr_only;    // the correlation kernel writes C only (no level-0 test, no adjacency)
 };
 
 

@@ -468,6 +468,8 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                 else if (tid == 0) g = gridDim.x + atomicAdd(&st->next_item, 1ull);
             }
             g = __shfl(g, 0, 64);
+            // A re-check queue overflow stops the level (it is redone in FP64): no further items.
+            if (__hip_atomic_load(&st->rq_overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) g = total;
             if (g >= total) {
                 if (tid == 0) s_grow = -1;
             } else {
@@ -859,6 +861,8 @@ __global__ __launch_bounds__(kLevelThreads) void k_level_deep(Batch b, int R) {
                 else if (tid == 0) g = gridDim.x + atomicAdd(&st->next_item, 1ull);
             }
             g = __shfl(g, 0, 64);
+            // A re-check queue overflow stops the level (it is redone in FP64): no further items.
+            if (__hip_atomic_load(&st->rq_overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) g = total;
             if (g >= total) {
                 if (tid == 0) s_grow = -1;
             } else {

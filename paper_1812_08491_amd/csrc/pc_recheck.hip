@@ -9,6 +9,14 @@ namespace pcg {
 // ---------------------------------------------------------------------------------------------
 constexpr int kRcThreads = 256;            // re-check work-group: 4 wavefronts per queued test
 
+// After a queue overflow at level L the level loop stops and nothing clears the queue, which keeps
+// level L's tests: the re-check launches of the levels after L (already enqueued) have none of
+// their own, and must not read L's entries as tests of their level.
+__device__ inline bool stale_queue(const Batch &b, int level) {
+    const int ovf = __hip_atomic_load(&b.st->rq_overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return ovf != 0 && level > ovf;
+}
+
 // Queued tests of levels up to 14 (at most 16 variables). The FP64 Gram block of the standardized
 // rows (i, j, S) is one 16 x 16 tile Z Z^T (gram_part); rows past l + 2 stay zero. On the FP64 path
 // the block is read from C. With few queued tests a work-group takes each one and its four
@@ -21,6 +29,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck(Batch b, int level) {
     __shared__ double work[kW][kWorks];
     __shared__ int s_v[kW][16];
     __shared__ int s_prob, s_cls;
+    if (stale_queue(b, level)) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const RqView view(b);
     const long long count = view.total();
@@ -128,6 +137,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_deep(Batch b, int level)
     __shared__ double work[kWork];
     __shared__ int s_v[32];        // variables of the tile rows: i, j, S..., then -1
     __shared__ int s_prob, s_cls;
+    if (stale_queue(b, level)) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const RqView view(b);
     const long long count = view.total();

@@ -140,7 +140,7 @@ __device__ void tail_tests(const Batch &b, Prob &P, int pd, TailSmem &sm, RqEntr
 #pragma unroll
                         for (int c = 0; c < PC_MAX_LEVEL; ++c) e->S[c] = c < L ? (uint16_t)sid[c] : (uint16_t)0xffff;
                     } else {
-                        atomicOr(&b.st->rq_overflow, 1);
+                        atomicOr(&b.st->rq_overflow_tail, 1);
                     }
                 }
             }

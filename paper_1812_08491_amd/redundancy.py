@@ -2,7 +2,7 @@
 
 The set-sharing kernel factors M2 = C[S,S] once per (row i, set S) and reuses it for every j of the
 row. Sharing it across rows as well would need a search of the whole graph for the rows that hold
-S; the paper (Sec. 5, on global against local sharing) measures, at level 2, in how many rows of
+S; the paper (Sec. 5.5, global against local sharing) measures, at level 2, in how many rows of
 A'_G each set appears and finds the counts small. This module measures the same histogram on
 G' of a given level, from the library's own skeleton run up to the level before it:
 

@@ -3,7 +3,7 @@
 This module only draws random inputs. It holds none of the PC-stable arithmetic (no correlation, no
 CI test), so that both the CPU oracle and the HIP library can be fed from it without sharing code.
 
-Generator (the family of the paper's own synthetic workloads, Sec. 5.5, with signed weights):
+Generator (the family of the paper's own synthetic workloads, Sec. 5.6, with signed weights):
   * a uniformly random topological order pi over n variables;
   * for every pair a < b in pi order, an edge pi[a] -> pi[b] with probability p;
   * edge weights: sign +-1 with probability 1/2 each, magnitude U[0.1, 1];
@@ -115,7 +115,7 @@ def workload(name: str, instance: int = 0):
 
 
 def scalability(n: int = 1000, p: float = 0.1, m: int = 10000, instance: int = 0):
-    """The paper's own scalability family (Sec. 5, scalability): every ordered pair gets an edge with
+    """The paper's own scalability family (Sec. 5.6): every ordered pair gets an edge with
     probability p (a dense graph: about p (n - 1) / 2 parents per node), positive weights U[0.1, 1],
     unit-variance Gaussian noise, m samples. Returns (X, sem, alpha = 0.01)."""
     rng = np.random.default_rng(1000 * 6 + 10 * int(round(p * 100)) + instance)

@@ -301,3 +301,89 @@ def test_skeleton_deep_levels_hub(prec):
     assert ref.levels_run >= 17 and st["levels_run"] == ref.levels_run
     assert sum(st["tests"][14:ref.levels_run]) > 0
 
+
+
+# ---------------------------------------------------------------------------------------------
+# Re-check queue overflow: the run is completed in FP64 from the overflowing level
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_recheck_overflow_completes_level_in_fp64(prec):
+    """With every FP32 test sent to the re-check queue (audit mode) and a queue of 2048 entries, level
+    1 overflows it: the device stops the level loop, the level is redone in FP64 on its snapshot G'
+    and the rest of the skeleton runs in FP64. The result is the oracle's, with status OK."""
+    X = sem_data(31, 300, 0.03, 600)
+    print(f"overflow {prec}", flush=True)
+    st, ref = compare_with_oracle(X, 0.05, prec, force_recheck_all=1, recheck_cap=2048)
+    assert st["fp64_from"] == 1
+
+
+def test_recheck_overflow_at_a_later_level():
+    """A queue that holds all of level 1's tests but not level 2's (a collider hub with 20 parents:
+    about 20 * 19 tests at level 1, 20 * C(19, 2) at level 2): the run goes on in FP64 from level 2,
+    and the re-check launches of levels 3.. (enqueued behind it) leave the stale queue alone."""
+    X = hub_data(20, 3000, 41)
+    print("overflow at level 2: sizing run", flush=True)
+    st, ref = compare_with_oracle(X, 0.01, "fp32", max_level=4, force_recheck_all=1, recheck_cap=1 << 22)
+    t1, t2 = st["tests"][1], st["tests"][2]
+    assert st["fp64_from"] == 0
+    # Every level-1 test is queued in audit mode; pushes <= capacity never overflow (a wavefront
+    # tries every slice, and slices only fill up).
+    cap = (t1 + 15) // 16 * 16 + 256
+    assert cap < t2, (t1, t2)
+    print(f"overflow at level 2: cap {cap}", flush=True)
+    for graph in (False, True):
+        if not graph:
+            st, ref = compare_with_oracle(X, 0.01, "fp32", max_level=4, force_recheck_all=1, recheck_cap=cap)
+            assert st["fp64_from"] == 2
+            continue
+        m, n = X.shape
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            gctx = pc.Context(stream=stream, precision="fp32", force_recheck_all=1, recheck_cap=cap)
+            gadj = gctx.adjacency(n)
+            grecs, gcount = gctx.sepsets(n * n)
+            probs = gctx.problems([(torch.from_numpy(X).cuda(), 0.01, 4, gadj, grecs, gcount)])
+            gws = gctx.batch_workspace(probs)
+            g = gctx.pc_batch_capture(probs, gws)
+            gst = (pc.pc_run_stats * 1)()
+            g.pc_graph_launch()
+            r, status = g.pc_graph_results(gst)
+            torch.cuda.synchronize()
+            g.close()
+        assert r == 0 and status[0] == 0 and gst[0].fp64_from == 2
+        assert np.array_equal(pc.bits_to_dense(gadj.cpu().numpy(), n), ref.G)
+
+
+def test_recheck_overflow_through_pc_level_and_graph():
+    """The same completion through pc_level (one level from the oracle's snapshot) and through a
+    captured graph (pc_graph_results finishes the overflowed level and the levels after it)."""
+    X = sem_data(32, 200, 0.05, 500)
+    m, n = X.shape
+    alpha = 0.05
+    C64 = oracle.corr(X)
+    ref = oracle.skeleton_corr(C64, m, alpha, keep_levels=True)
+    print("overflow through pc_level", flush=True)
+    ctx, ws, Xt, C, G0 = gpu_corr(X, alpha, "fp32", force_recheck_all=1, recheck_cap=1024)
+    recs, count = ctx.sepsets(n * n)
+    adj = torch.from_numpy(pc.dense_to_bits(ref.G_after[0])).cuda()
+    st = pc.pc_run_stats()
+    assert ctx.pc_level(1, n, m, alpha, adj, recs, count, ws, stats=st) == 0
+    assert st.fp64_from == 1
+    assert np.array_equal(pc.bits_to_dense(adj.cpu().numpy(), n), ref.G_after[1])
+    print("overflow through a captured graph", flush=True)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        gctx = pc.Context(stream=stream, precision="fp32", force_recheck_all=1, recheck_cap=1024)
+        gadj = gctx.adjacency(n)
+        grecs, gcount = gctx.sepsets(n * n)
+        probs = gctx.problems([(torch.from_numpy(np.ascontiguousarray(X)).cuda(), alpha, -1, gadj, grecs, gcount)])
+        gws = gctx.batch_workspace(probs)
+        graph = gctx.pc_batch_capture(probs, gws)
+        gst = (pc.pc_run_stats * 1)()
+        for replay in range(2):
+            graph.pc_graph_launch()
+            r, status = graph.pc_graph_results(gst)
+            torch.cuda.synchronize()
+            assert r == 0 and status[0] == 0 and gst[0].fp64_from == 1
+            assert np.array_equal(pc.bits_to_dense(gadj.cpu().numpy(), n), ref.G), replay
+        graph.close()
