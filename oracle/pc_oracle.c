@@ -42,6 +42,16 @@
 /* Correlation (Pearson, two-pass).                                                           */
 /* ------------------------------------------------------------------------------------------ */
 
+/* s_ab / sqrt(s_aa s_bb), the Pearson correlation of two centred columns. The product s_aa s_bb
+ * leaves the FP64 range for columns whose scale is beyond about 1e75 (dense SEMs with positive
+ * weights reach 1e100), so outside the normal range the two square roots are taken apart. */
+static double pearson_ratio(double s_ab, double s_aa, double s_bb)
+{
+    const double den = s_aa * s_bb;
+    if (isfinite(den) && den >= DBL_MIN) return s_ab / sqrt(den);
+    return s_ab / (sqrt(s_aa) * sqrt(s_bb));
+}
+
 int oc_corr(const double *X, int64_t m, int64_t n, double *C)
 {
     if (m < 2 || n < 1) return OC_ERR_SHAPE;
@@ -70,7 +80,7 @@ int oc_corr(const double *X, int64_t m, int64_t n, double *C)
         for (int64_t b = a + 1; b < n; ++b) {
             double s = 0.0;
             for (int64_t r = 0; r < m; ++r) s += D[a * m + r] * D[b * m + r];
-            double c = s / sqrt(ss[a] * ss[b]);
+            const double c = pearson_ratio(s, ss[a], ss[b]);
             C[a * n + b] = c;
             C[b * n + a] = c;
         }
@@ -94,7 +104,7 @@ int oc_corr_pair(const double *X, int64_t m, int64_t n, int64_t a, int64_t b, do
         sab += da * db;
     }
     if (!(saa > 0.0) || !(sbb > 0.0)) return OC_ERR_CONSTANT;
-    *out = sab / sqrt(saa * sbb);
+    *out = pearson_ratio(sab, saa, sbb);
     return OC_OK;
 }
 

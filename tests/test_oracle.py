@@ -376,3 +376,37 @@ def test_threads_give_identical_results():
     assert a.tests == b.tests and a.removed == b.removed
     assert a.sepsets.as_dict() == b.sepsets.as_dict()
     assert all(np.array_equal(x, y) for x, y in zip(a.G_after, b.G_after))
+
+
+def test_dense_sampler_draws_the_same_sem_as_the_sequential_one():
+    """semgen.sample_dense (one triangular solve) and semgen.sample (variable by variable in
+    topological order) give the same samples from the same noise, up to rounding; the scalability
+    grid covers the paper's points (Sec. 5.6)."""
+    rng = np.random.default_rng(12)
+    sem = semgen.random_dag(80, 0.3, rng, signed=False)
+    a = semgen.sample(sem, 400, np.random.default_rng(3))
+    b = semgen.sample_dense(sem, 400, np.random.default_rng(3))
+    assert np.allclose(a, b, rtol=1e-11, atol=1e-11)
+    sem = semgen.random_dag(50, 0.2, rng)
+    a = semgen.sample(sem, 300, np.random.default_rng(4))
+    b = semgen.sample_dense(sem, 300, np.random.default_rng(4))
+    assert np.allclose(a, b, rtol=1e-11, atol=1e-11)
+    grid = set(semgen.SCALABILITY_GRID)
+    assert {(n, 0.1, 10000) for n in (1000, 2000, 3000, 4000)} <= grid
+    assert {(1000, 0.1, m) for m in (2000, 4000, 6000, 8000, 10000)} <= grid
+    assert {(1000, d, 10000) for d in (0.1, 0.2, 0.3, 0.4, 0.5)} <= grid
+
+
+def test_correlation_is_scale_invariant_up_to_extreme_scales():
+    """Pearson's r does not depend on the scale of either column. Columns scaled by 10^-100 ..
+    10^100 (the dense SEMs of the paper's scalability grid reach standard deviations of 1e100)
+    give the correlation of the unscaled data, which numpy's corrcoef fixes; a product of the two
+    sums of squares would overflow there."""
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((300, 6))
+    X[:, 1] += 0.8 * X[:, 0]
+    X[:, 2] = X[:, 1] - 0.3 * X[:, 3]
+    scales = 10.0 ** np.array([100.0, 90.0, -100.0, 0.0, 75.0, -80.0])
+    C = oracle.corr(X * scales)
+    assert np.allclose(C, np.corrcoef(X, rowvar=False), rtol=0, atol=1e-13)
+    assert abs(C[0, 1]) > 0.5
