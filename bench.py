@@ -27,7 +27,7 @@ Further legs (skipped with --no-extras):
 * the n = 8000, degree 6, m = 2000 skeleton with the BF16x3 GEMM, levels 1-3;
 * 256 uneven datasets in one graph;
 * orientation of the n = 1000 skeleton;
-* the paper's scalability family.
+* the paper's scalability grid (n = 1000-4000, m = 2000-10000, d = 0.1-0.5).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
                     [--headline-only] [--copy-calibration MiB] [--write-traffic ...]
@@ -522,37 +522,50 @@ def leg_orient(args, torch, pc, out, c2):
 
 
 def leg_scalability(args, torch, pc, semgen, out):
-    progress("paper scalability family")
-    Xs, _, alpha_s = semgen.scalability(1000, 0.1, 10000)
-    ms_s, ns_s = Xs.shape
-    Xsd = torch.from_numpy(np.ascontiguousarray(Xs)).cuda()
-    leg = {"workload": "n=1000, edge probability 0.1, positive weights, m=10000, alpha 0.01"}
-    # FP64 only: on this family nearly every FP32 test falls inside its error band (near-collinear
-    # variables), so the FP32 path would re-check almost everything in FP64 anyway.
-    for prec in ("fp64",):
-        progress(f"paper scalability: {prec}")
-        sctx = pc.Context(precision=prec)
-        sws = sctx.workspace(ns_s, ms_s)
-        sadj = sctx.adjacency(ns_s)
-        srecs, scount = sctx.sepsets(ns_s * (ns_s - 1) // 2)
-        walls = []
-        for r in range(3):
-            sst = pc.pc_run_stats()
-            torch.cuda.synchronize()
-            s0 = time.perf_counter()
-            try:
-                sstatus = sctx.pc_skeleton(Xsd, alpha_s, sadj, srecs, scount, sws, stats=sst)
-            except pc.PCError as e:
-                sstatus = e.status
-            torch.cuda.synchronize()
-            if r:
-                walls.append(time.perf_counter() - s0)
-        sd = sst.as_dict()
-        leg[prec] = {"ms": float(np.median(walls)) * 1e3, "status": sstatus, "levels_run": sd["levels_run"],
-                     "gpu_tests": int(sum(sd["tests"])), "rechecks": int(sum(sd["rechecks"])),
-                     "edges": int(pc.bits_to_dense(sadj.cpu().numpy(), ns_s).sum()) // 2}
-        del sws
-    out["paper_scalability"] = leg
+    """The paper's scalability grid (Sec. 5.6, Fig. 10): n = 1000-4000 at d = 0.1, m = 2000-10000 at
+    n = 1000, d = 0.1-0.5 at n = 1000; one graph per point, FP64 tests. FP32 tests at two points
+    (nearly every FP32 test lies in the error band there: the re-check queue overflows and the run
+    is completed in FP64 from that level)."""
+    progress("paper scalability grid")
+    points = []
+    fp32_at = {(1000, 0.1, 10000), (1000, 0.3, 10000)}
+    for n, p, m in semgen.SCALABILITY_GRID:
+        X, _, alpha = semgen.scalability(n, p, m)
+        Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+        del X
+        point = {"n": n, "d": p, "m": m}
+        for prec in ("fp64", "fp32") if (n, p, m) in fp32_at else ("fp64",):
+            progress(f"paper scalability n={n} d={p} m={m}: {prec}")
+            sctx = pc.Context(precision=prec)
+            sws = sctx.workspace(n, m)
+            sadj = sctx.adjacency(n)
+            srecs, scount = sctx.sepsets(n * (n - 1) // 2)
+            walls = []
+            for r in range(3):
+                sst = pc.pc_run_stats()
+                torch.cuda.synchronize()
+                s0 = time.perf_counter()
+                try:
+                    sstatus = sctx.pc_skeleton(Xd, alpha, sadj, srecs, scount, sws, stats=sst)
+                except pc.PCError as e:
+                    sstatus = e.status
+                torch.cuda.synchronize()
+                if r:
+                    walls.append(time.perf_counter() - s0)
+            sd = sst.as_dict()
+            point[prec] = {"ms": float(np.median(walls)) * 1e3, "status": sstatus,
+                           "levels_run": sd["levels_run"], "gpu_tests": int(sum(sd["tests"])),
+                           "rechecks": int(sum(sd["rechecks"])), "fp64_from": sd["fp64_from"],
+                           "edges": int(pc.bits_to_dense(sadj.cpu().numpy(), n).sum()) // 2}
+            assert sstatus == 0, (n, p, m, prec, sstatus)
+            del sws, sadj, srecs, scount
+            sctx.close()
+        points.append(point)
+        del Xd
+        torch.cuda.empty_cache()
+    out["paper_scalability"] = {
+        "workload": "paper's family: edge probability d per pair, positive weights U[0.1, 1], alpha 0.01",
+        "points": points}
 
 
 def main() -> int:

@@ -11,8 +11,9 @@ sampled outputs it computes one by one, and properties that hold at any size (ma
     tests/golden/make_oracle_skeletons.py from the oracle alone; about 100 s of CPU).
   * n=2000 variables, m=1000 samples, expected degree 10: whole skeleton against the oracle, plain
     and with the learned order.
-  * The paper's scalability family: every pair on which the GPU and the oracle differ is tied to a
-    near-collinear test.
+  * Points of the paper's scalability grid (n up to 2000, m 2000-10000, d 0.1-0.5; FP64, and FP32
+    completed in FP64 after a re-check queue overflow): every pair on which the GPU and the oracle
+    differ is tied to a near-collinear test.
 """
 import hashlib
 import os
@@ -234,68 +235,60 @@ def _have_weights():
     return os.path.exists(learn.DEFAULT_WEIGHTS)
 
 
-def test_paper_scalability_n1000_p01_m10000_fp64_matches_oracle():
-    """The paper's own scalability family (edge probability 0.1, positive weights, m = 10000).
-    Variances grow along the order (about 50 parents per node), so many late variables are
-    collinear to FP64 rounding: 66 k pairs have |C| that rounds to 1 and 180 k are within 1e-12 of
-    it. There H11 = 1 - C_ik^2 of a level-1 test can round to <= 0 on one side (rho := 0,
-    independent) and to a tiny positive value on the other (|rho| >= 1, dependent), so exact parity
-    is not defined for those tests: parity partial. Checked: the two skeletons differ in at most
-    0.01% of the pairs, the same number of levels runs, and every sampled GPU SepSet passes the
-    oracle's FP64 test unless its variables are near-collinear (some |C| > 1 - 1e-6 within {i} u S
-    or {j} u S)."""
-    X, sem, alpha = semgen.scalability(1000, 0.1, 10000)
-    print("paper scalability n=1000 p=0.1 m=10000 fp64", flush=True)
-    m, n = X.shape
-    C = oracle.corr(X)
-    ref = oracle.skeleton_corr(C, m, alpha)
-    G, seps, st, status = pc.skeleton(np.ascontiguousarray(X), alpha, precision="fp64")
+def _degenerate(A, i, j, S):
+    return any(A[np.ix_(V, V)].max() > 1 - 1e-6 for V in ([i] + list(S), [j] + list(S)))
+
+
+_ORACLE_SCAL = {}
+
+
+def _scal_oracle(n, p, m):
+    if (n, p, m) not in _ORACLE_SCAL:
+        _ORACLE_SCAL.clear()
+        X, sem, alpha = semgen.scalability(n, p, m)
+        C = oracle.corr(X)
+        _ORACLE_SCAL[(n, p, m)] = (X, alpha, C, oracle.skeleton_corr(C, m, alpha))
+    return _ORACLE_SCAL[(n, p, m)]
+
+
+@pytest.mark.parametrize("n,p,m,prec", [
+    (1000, 0.1, 10000, "fp64"), (1000, 0.1, 10000, "fp32"), (1000, 0.1, 2000, "fp64"),
+    (1000, 0.3, 10000, "fp64"), (1000, 0.3, 10000, "fp32"), (1000, 0.5, 10000, "fp64"),
+    (2000, 0.1, 10000, "fp64")])
+def test_paper_scalability_grid_matches_oracle(n, p, m, prec):
+    """Points of the paper's scalability grid (Sec. 5.6, Fig. 10: edge probability p per pair,
+    positive weights, m samples). Variances grow along the order (at n = 1000, p = 0.1 about 50
+    parents per node), so many late variables are collinear to FP64 rounding: at n = 1000, p = 0.1,
+    m = 10000, 179 k pairs have |C| within 1e-12 of 1, and at p = 0.3 three quarters of all pairs.
+    There H11 = 1 - C_ik^2 of a level-1 test can round to <= 0 on one side (rho := 0, independent)
+    and to a tiny positive value on the other (|rho| >= 1, dependent), so exact parity is not
+    defined for those tests: parity partial. Checked: every pair on which the GPU and the oracle
+    differ is decided by such a near-collinear test (some |C| > 1 - 1e-6 within {i} u S or {j} u S,
+    with S the SepSet of the side that removed it), the same number of levels runs, and every
+    sampled GPU SepSet passes the oracle's FP64 test unless it is near-collinear. In FP32 nearly
+    every test falls inside the error band, the re-check queue overflows, and the run is completed
+    in FP64 from that level (fp64_from)."""
+    print(f"paper scalability n={n} p={p} m={m} {prec}", flush=True)
+    X, alpha, C, ref = _scal_oracle(n, p, m)
+    G, seps, st, status = pc.skeleton(np.ascontiguousarray(X), alpha, precision=prec)
     assert status == 0
-    diff = int((G != ref.G).sum()) // 2
-    assert diff <= n * (n - 1) // 2 // 10000, diff
-    assert st["levels_run"] == ref.levels_run and st["max_degree"][1] == n - 1
-    A = np.abs(C - np.eye(n))
-
-    def degenerate(i, j, S):
-        return any(A[np.ix_(V, V)].max() > 1 - 1e-6 for V in ([i] + list(S), [j] + list(S)))
-
-    # Every differing pair is decided by a near-collinear test: the GPU removed it with a
-    # degenerate S, or the oracle removed it with one (which the GPU then decided the other way).
-    ref_seps = ref.sepsets.as_dict()
-    for i, j in np.argwhere(np.triu(G != ref.G, 1)):
-        i, j = int(i), int(j)
-        S = seps[(i, j)][1] if G[i, j] == 0 else ref_seps.get((i, j), (0, ()))[1]
-        assert degenerate(i, j, S), ((i, j), int(G[i, j]), S)
-
-    keys = list(seps)
-    bad = 0
-    for t in np.random.default_rng(3).choice(len(keys), min(3000, len(keys)), replace=False):
-        e = keys[t]
-        l, S = seps[e]
-        if not oracle.ci_test(C, e[0], e[1], list(S), m, alpha)[0]:
-            assert degenerate(e[0], e[1], S), (e, S)
-            bad += 1
-    print("sampled GPU SepSets on near-collinear tests:", bad, flush=True)
-
-
-def test_paper_scalability_fp32_completes_through_fp64_levels():
-    """The same family in FP32: nearly every test falls in the FP32 error band (near-collinear
-    variables), so the re-check queue overflows at level 1; that level and the rest of the skeleton
-    are then completed in FP64. The result must agree with the oracle as closely as the FP64 path
-    does (differing pairs all decided by near-collinear tests)."""
-    X, sem, alpha = semgen.scalability(1000, 0.1, 10000)
-    print("paper scalability n=1000 p=0.1 m=10000 fp32", flush=True)
-    m, n = X.shape
-    C = oracle.corr(X)
-    ref = oracle.skeleton_corr(C, m, alpha)
-    G, seps, st, status = pc.skeleton(np.ascontiguousarray(X), alpha, precision="fp32")
-    assert status == 0 and st["fp64_from"] >= 1
-    diff = int((G != ref.G).sum()) // 2
-    assert diff <= n * (n - 1) // 2 // 10000, diff
+    if prec == "fp32":
+        assert st["fp64_from"] >= 1
     assert st["levels_run"] == ref.levels_run
     A = np.abs(C - np.eye(n))
     ref_seps = ref.sepsets.as_dict()
-    for i, j in np.argwhere(np.triu(G != ref.G, 1)):
+    diff = np.argwhere(np.triu(G != ref.G, 1))
+    print("pairs that differ:", len(diff), flush=True)
+    for i, j in diff:
         i, j = int(i), int(j)
         S = seps[(i, j)][1] if G[i, j] == 0 else ref_seps.get((i, j), (0, ()))[1]
-        assert any(A[np.ix_(V, V)].max() > 1 - 1e-6 for V in ([i] + list(S), [j] + list(S))), (i, j, S)
+        assert _degenerate(A, i, j, S), ((i, j), int(G[i, j]), S)
+    keys = list(seps)
+    bad = 0
+    for t in np.random.default_rng(3).choice(len(keys), min(2000, len(keys)), replace=False):
+        e = keys[t]
+        l, S = seps[e]
+        if not oracle.ci_test(C, e[0], e[1], list(S), m, alpha)[0]:
+            assert _degenerate(A, e[0], e[1], S), (e, S)
+            bad += 1
+    print("sampled GPU SepSets on near-collinear tests:", bad, flush=True)
