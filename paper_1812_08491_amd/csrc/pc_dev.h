@@ -99,6 +99,7 @@ struct DevState {
                                      // then stops: done is set)
     int rq_overflow_tail;            // a problem's share of the queue filled up in the tail kernel
     int pad[2];
+    unsigned long long item_stride;  // queue order: pop g takes item (g * item_stride) mod total_items
 };
 static_assert(sizeof(DevState) <= 64 * sizeof(int), "the re-arm kernel clears DevState with 64 threads");
 

@@ -437,7 +437,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
 
     DevState *st = b.st;
     const int done = st->done;
-    const unsigned long long total = st->total_items;
+    const unsigned long long total = st->total_items, stride = st->item_stride;
     if (done) return;
     const int tid = threadIdx.x;
     // Typed LDS pointers: every access below compiles to a ds_* instruction, never a flat one.
@@ -473,7 +473,12 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
             if (g >= total) {
                 if (tid == 0) s_grow = -1;
             } else {
+                // (in queue order, rows only grow: the search starts at the last row)
                 long long lo = last_row, hi = b.total_rows;
+                if (stride > 1ull) {
+                    g = g * stride % total;
+                    lo = 0;
+                }
                 while (hi - lo > 1) {
                     const long long step = (hi - lo + 63) / 64;
                     const long long idx = lo + (long long)tid * step;
@@ -578,6 +583,38 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
             }
             nlive = base;
         }
+        // A row longer than kDcap keeps its neighbour list in global memory. When its still-live
+        // candidates fit, they are compacted into the LDS list itself (ids and C_ij, ascending j),
+        // straight from the live bits: every live edge of G is an edge of the snapshot G'. Sets
+        // are still ranked over the whole list (their ids and C_ik come from global memory). Level 1
+        // only: long rows at higher levels are rare, and the extra placement costs the deeper
+        // kernels a wavefront of occupancy in registers.
+        bool compact = false;
+        if (L == 1 && !(mode & 1) && (mode & 4)) {
+            static_assert(kWcap <= kLevelThreads, "one live-bit word per thread");
+            unsigned long long wv = 0ull;
+            if (tid < W) {
+                wv = lds_live[tid];
+                // a caller-supplied G may carry stray bits: the diagonal and columns >= n
+                if (tid == (row >> 6)) wv &= ~(1ull << (row & 63));
+                if (tid == W - 1 && (n & 63)) wv &= (1ull << (n & 63)) - 1ull;
+            }
+            long long tot = 0;
+            const long long pre = block_exclusive_scan<kLevelThreads>((long long)__popcll(wv), s_scan, tot);
+            if (tot <= kDcap) {
+                int q = (int)pre;
+                while (wv) {
+                    const int j = tid * 64 + __ffsll((long long)wv) - 1;
+                    lds_nb[q] = j;
+                    lds_ci[q] = C[(int64_t)row * n + j];
+                    ++q;
+                    wv &= wv - 1ull;
+                }
+                nlive = (int)tot;
+                compact = true;
+            }
+            __syncthreads();
+        }
         const double tau = P.tau[L];
         const float tl = P.t[L], band = P.band[L];
 
@@ -600,7 +637,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
             // (a row left with its surviving edges, which every set must test), a wavefront takes
             // several sets at once, and its lanes still carry about kBatch candidates each.
             split = 64;
-            if ((mode & 5) == 5)
+            if ((mode & 5) == 5 || compact)
                 while (split > 4 && (split / 2) * 8 >= nlive) split >>= 1;
         } else if (nr < kLevelThreads) {
             while (split * 2 * nr <= kLevelThreads) split *= 2;
@@ -640,24 +677,29 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
             else comb_unrank<L>(d, (unsigned long long)my_t, P_, binom);
         }
         // The set loop, specialised on where the row's data sits: K = 7 all of it in LDS, K = 5 all
-        // but the block C[N_i, N_i] (gathered from global C), K = 0 any mix (decided per access). In
-        // the specialised forms every load of a set is branch-free, so the compiler issues them
+        // but the block C[N_i, N_i] (gathered from global C), K = 1 a row longer than kDcap whose
+        // live candidates were compacted into LDS, K = 0 any mix (decided per access). In the
+        // specialised forms every load of a set is branch-free, so the compiler issues them
         // together instead of waiting on each one.
         auto run_sets = [&](auto kind) {
             constexpr int K = decltype(kind)::value;
-            // Candidate positions: the live list (K != 0) or all of N_i.
+            // Candidates: list positions of the live list (K = 5, 7), entries of the compacted
+            // list (K = 1), or all positions of N_i (K = 0).
             const int ncand = K != 0 ? nlive : d;
             const int psteps = (ncand + split - 1) / split;
             auto POS = [&](int idx) -> int {
-                if constexpr (K != 0) return s_livepos[idx];
+                if constexpr (K >= 5) return s_livepos[idx];
                 else return idx;
             };
+            // Id, C_ik and C[N_p, N_q] at positions of N_i (sets always; candidates unless K = 1).
             auto NB = [&](int p) -> int {
-                if constexpr (K != 0) return lds_nb[p];
+                if constexpr (K >= 5) return lds_nb[p];
+                else if constexpr (K == 1) return nbg[p];
                 else return (mode & 1) ? lds_nb[p] : nbg[p];
             };
             auto CI = [&](int p) -> T {
-                if constexpr (K != 0) return lds_ci[p];
+                if constexpr (K >= 5) return lds_ci[p];
+                else if constexpr (K == 1) return C[(int64_t)row * n + nbg[p]];
                 else return (mode & 1) ? lds_ci[p] : C[(int64_t)row * n + nbg[p]];
             };
             auto CS = [&](int p, int q) -> T {
@@ -665,6 +707,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                 // From global C, the row of the set element q (C is exactly symmetric): at level 1
                 // the lanes of a wavefront share q and read ascending columns N_p of one row.
                 else if constexpr (K == 5) return p == q ? (T)1 : C[(int64_t)lds_nb[q] * n + lds_nb[p]];
+                else if constexpr (K == 1) return p == q ? (T)1 : C[(int64_t)nbg[q] * n + nbg[p]];
                 else {
                     if (p == q) return (T)1;
                     return (mode & 2) ? lds_blk[p * d + q] : C[(int64_t)NB(q) * n + NB(p)];
@@ -698,7 +741,9 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                         since_refresh = 0;
                         const int idx = pp0 * split + slice;
                         if (idx < ncand) {
-                            const int j = NB(POS(idx));
+                            int j;
+                            if constexpr (K == 1) j = lds_nb[idx];
+                            else j = NB(POS(idx));
                             lds_and(lds_live + (j >> 6), live_word(adj_row + (j >> 6)));
                         }
                     }
@@ -710,15 +755,29 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                         const int idx = (pp0 + u) * split + slice;
                         bool ok = pp0 + u < psteps && idx < ncand;
                         const int p = ok ? POS(idx) : 0;
+                        int j;
+                        if constexpr (K == 1) {
+                            // compacted entry p: the candidate is excluded by id, not position
+                            j = ok ? lds_nb[p] : 0;
     #pragma unroll
-                        for (int c = 0; c < L; ++c) ok &= P_[c] != p;
-                        const int j = ok ? NB(p) : 0;
+                            for (int c = 0; c < L; ++c) ok &= sid[c] != j;
+                        } else {
+    #pragma unroll
+                            for (int c = 0; c < L; ++c) ok &= P_[c] != p;
+                            j = ok ? NB(p) : 0;
+                        }
                         ok = ok && LIVE(j);
                         go[u] = ok;
                         jb[u] = j;
+                        if constexpr (K == 1) {
     #pragma unroll
-                        for (int r = 0; r < L; ++r) col[u][r] = ok ? CS(p, P_[r]) : (T)0;
-                        cij[u] = ok ? CI(p) : (T)0;
+                            for (int r = 0; r < L; ++r) col[u][r] = ok ? C[(int64_t)sid[r] * n + j] : (T)0;
+                            cij[u] = ok ? lds_ci[p] : (T)0;
+                        } else {
+    #pragma unroll
+                            for (int r = 0; r < L; ++r) col[u][r] = ok ? CS(p, P_[r]) : (T)0;
+                            cij[u] = ok ? CI(p) : (T)0;
+                        }
                     }
     #pragma unroll
                     for (int u = 0; u < kBatch; ++u) {
@@ -754,6 +813,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         };
         if (mode == 7) run_sets(IntTag<7>{});
         else if (mode == 5) run_sets(IntTag<5>{});
+        else if (L == 1 && compact) run_sets(IntTag<L == 1 ? 1 : 0>{});
         else run_sets(IntTag<0>{});
         // Settle the staged removals: every ticket is taken at once (one thread each), the
         // winners get consecutive SepSet slots from one atomic add, and re-derive S from its rank.
@@ -839,7 +899,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level_deep(Batch b, int R) {
 
     DevState *st = b.st;
     const int done = st->done;
-    const unsigned long long total = st->total_items;
+    const unsigned long long total = st->total_items, stride = st->item_stride;
     if (done) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const TableBinom binom{b.binom};
@@ -867,6 +927,10 @@ __global__ __launch_bounds__(kLevelThreads) void k_level_deep(Batch b, int R) {
                 if (tid == 0) s_grow = -1;
             } else {
                 long long lo = last_row, hi = b.total_rows;
+                if (stride > 1ull) {
+                    g = g * stride % total;
+                    lo = 0;
+                }
                 while (hi - lo > 1) {
                     const long long step = (hi - lo + 63) / 64;
                     const long long idx = lo + (long long)tid * step;

@@ -79,6 +79,28 @@ hipError_t launch_compact(hipStream_t s, const Batch &b, int level, int ranks_pe
     return hipGetLastError();
 }
 
+// Order in which the queue hands out a level's items. Items are numbered row by row, so when rows
+// have many items each (long rows of a dense G'), handing them out in that order would set every
+// resident work-group on the same few rows at once: all of them would test those rows against the
+// same still-live candidates, and race to remove the same edges. With several items per row on
+// average, pop g takes item (g * s) mod total instead, s about the number of rows and coprime to
+// the total (a permutation): consecutive pops fall on different rows, and a row's items are spread
+// over the whole launch, so its later items see the removals of its earlier ones.
+__device__ inline unsigned long long item_stride(long long total, long long rows) {
+    if (rows < 2 || total < 4 * rows) return 1ull;
+    unsigned long long s = (unsigned long long)rows;
+    for (;;) {
+        unsigned long long a = s, c = (unsigned long long)total;
+        while (c) {
+            const unsigned long long t = a % c;
+            a = c;
+            c = t;
+        }
+        if (a == 1ull) return s;
+        ++s;
+    }
+}
+
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanLdsProbs = 4096;     // problems whose max degree is reduced in LDS
 
@@ -102,6 +124,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level, int w
         b.item_off[N] = total;
         st->total_items = (unsigned long long)total;
         st->next_item = 0ull;
+        st->item_stride = item_stride(total, N);
         if (!window && total == 0) st->done = 1;
     }
     if (window) return;   // a window of a planned level: its statistics and stop flag stand
