@@ -212,9 +212,14 @@ def headline(args, torch, pc, semgen, out):
             recs, count = ctx.sepsets(n * (n - 1) // 2)
             probs = ctx.problems([(Xd, alpha, -1, adj, recs, count)])
             ws = ctx.batch_workspace(probs)
+            # Per-level launch shapes tuned on this workload and order, then recorded in the graph.
+            progress(f"headline: tuning {mode}")
+            t0 = time.perf_counter()
+            tuning = ctx.pc_tune(probs, ws, order)
+            tune_s = time.perf_counter() - t0
             graph = ctx.pc_batch_capture(probs, ws, order)
             modes[mode] = dict(ctx=ctx, order=order, adj=adj, recs=recs, count=count, graph=graph, ws=ws,
-                               probs=probs)
+                               probs=probs, tuning=tuning, tune_s=tune_s)
 
     def results(mode):
         st = (pc.pc_run_stats * 1)()
@@ -242,6 +247,7 @@ def headline(args, torch, pc, semgen, out):
             # The level-1 pass (the same kernels on the same stream), timed with HIP events around
             # it in eager runs of the same skeleton (a captured graph holds no timing events).
             tctx = pc.Context(stream=stream, precision="fp32", timing=32)
+            tctx.pc_set_tuning(modes[mode]["tuning"])
             tadj = tctx.adjacency(n)
             trecs, tcount = tctx.sepsets(n * (n - 1) // 2)
             tws = tctx.workspace(n, m)
@@ -255,9 +261,15 @@ def headline(args, torch, pc, semgen, out):
                     tctx.pc_skeleton_ordered(Xd, alpha, tadj, trecs, tcount, tws, torder, stats=st)
                 l1.append(st.level_ms[1])
             del tws, trecs
+            td = modes[mode]["tuning"].as_dict()
             res[mode] = {"ms_per_step": sec * 1e3, "tests": last["tests"], "probe_tests": last["probe_tests"],
                          "rechecks": last["rechecks"], "levels_run": last["levels_run"],
-                         "level1_pass_ms": float(np.mean(l1)), "adj": modes[mode]["adj"].cpu().numpy()}
+                         "level1_pass_ms": float(np.mean(l1)), "adj": modes[mode]["adj"].cpu().numpy(),
+                         "tuning": {"tests_per_lane": td["tests_per_lane"], "ranks_per_lane": td["ranks_per_lane"],
+                                    "lds_budget": td["lds_budget"], "runs": td["runs"],
+                                    "seconds": modes[mode]["tune_s"],
+                                    "level_ms_tuned": [round(x, 4) for x in td["level_ms"]],
+                                    "level_ms_default": [round(x, 4) for x in td["default_ms"]]}}
     G = {mode: pc.bits_to_dense(res[mode].pop("adj"), n) for mode in names}
     sec = res["learned"]["ms_per_step"] * 1e-3
     out.update({
@@ -270,6 +282,7 @@ def headline(args, torch, pc, semgen, out):
                              "weights": "paper_1812_08491_amd/weights/order_row_mlp_n200.npy",
                              "trained_on": "2000 generated SEMs, n=200, degree~U[2,10], m=1000"},
                    "step": "one replay of the whole skeleton captured as a hipGraph (pc_batch_capture_ordered)",
+                   "launch_shapes": "per level, autotuned on this workload before capture (pc_tune)",
                    "graph_levels": graph_levels},
         "gpu_tests_per_step": int(sum(res["learned"]["tests"])),
         "orders": {mode: {k: v for k, v in r.items()} for mode, r in res.items()},
@@ -331,6 +344,11 @@ def leg_c2_graph(args, torch, pc, semgen, out):
     ws = ctx.workspace(n, m)
     adj = ctx.adjacency(n)
     recs, count = ctx.sepsets(n * (n - 1) // 2)
+    # launch shapes autotuned on this workload (applied to the eager runs and the graph below)
+    tprobs = ctx.problems([(Xd, alpha, -1, adj, recs, count)])
+    tws = ctx.batch_workspace(tprobs)
+    tuning = ctx.pc_tune(tprobs, tws)
+    del tws
     sts = []
     for _ in range(max(3, args.warmup)):
         st = pc.pc_run_stats()
@@ -345,6 +363,7 @@ def leg_c2_graph(args, torch, pc, semgen, out):
     gstream = torch.cuda.Stream()
     with torch.cuda.stream(gstream):
         gctx = pc.Context(stream=gstream, precision="fp32", graph_levels=graph_levels, tail_tests=1 << 30)
+        gctx.pc_set_tuning(tuning)
         gadj = gctx.adjacency(n)
         grecs, gcount = gctx.sepsets(n * (n - 1) // 2)
         probs = gctx.problems([(Xd, alpha, -1, gadj, grecs, gcount)])
@@ -366,7 +385,10 @@ def leg_c2_graph(args, torch, pc, semgen, out):
     gd = gst[0].as_dict()
     assert gd["levels_run"] - 1 <= max(graph_levels, TAIL_MAX_LEVEL), "the graph did not cover every level"
     G = pc.bits_to_dense(gadj.cpu().numpy(), n)
+    td = tuning.as_dict()
     leg = {"workload": "n=1000, degree 4, m=500, alpha 0.01, fp32 + fp64 re-check; one hipGraph replay",
+           "launch_shapes": {"tests_per_lane": td["tests_per_lane"], "ranks_per_lane": td["ranks_per_lane"],
+                             "lds_budget": td["lds_budget"]},
            "ms_per_skeleton": sec * 1e3, "graph_levels": graph_levels, "levels_run": gd["levels_run"],
            "gpu_tests": int(sum(gd["tests"])), "edges": int(G.sum()) // 2,
            "level1_ms_events": float(np.mean([s["level_ms"][1] for s in sts[1:]])),
@@ -403,9 +425,14 @@ def leg_c3(args, torch, pc, semgen, out):
     for prec in ("bf16x3", "fp32"):
         progress(f"c3: {prec}")
         ctx = pc.Context(precision=prec, timing=1 | 2 | 8)
-        ws = ctx.workspace(n, m)
         adj = ctx.adjacency(n)
         recs, count = ctx.sepsets(4 * n * n // 8)
+        # launch shapes autotuned on this workload, levels 1-3
+        tprobs = ctx.problems([(Xd, alpha, 3, adj, recs, count)])
+        ws = ctx.batch_workspace(tprobs)
+        t0 = time.perf_counter()
+        tuning = ctx.pc_tune(tprobs, ws).as_dict()
+        tune_s = time.perf_counter() - t0
         walls, sts = [], []
         for r in range(3):
             st = pc.pc_run_stats()
@@ -422,7 +449,11 @@ def leg_c3(args, torch, pc, semgen, out):
         e = {"ms_per_skeleton": float(np.median(walls)) * 1e3, "corr_ms": corr_ms,
              "level_ms": [float(np.mean([s["level_ms"][l] for s in sts])) for l in range(4)],
              "recheck_ms": [float(np.mean([s["recheck_ms"][l] for s in sts])) for l in range(4)],
-             "gpu_tests": d["tests"], "rechecks": d["rechecks"], "edges": int(G.sum()) // 2}
+             "gpu_tests": d["tests"], "rechecks": d["rechecks"], "edges": int(G.sum()) // 2,
+             "launch_shapes": {"tests_per_lane": tuning["tests_per_lane"][:4],
+                               "ranks_per_lane": tuning["ranks_per_lane"][:4],
+                               "lds_budget": tuning["lds_budget"][:4], "tune_s": tune_s,
+                               "level_ms_untuned": [round(x, 4) for x in tuning["default_ms"][:4]]}}
         flops = float(m) * n * (n - 1)
         if prec == "bf16x3":
             ach = 3 * flops / (corr_ms * 1e-3) / 1e12
@@ -453,7 +484,7 @@ def leg_c3(args, torch, pc, semgen, out):
                                         "algorithmic_bytes": lb,
                                         "executed_over_canonical": d["tests"][1] / int(g["tests"][1])}
         leg[prec] = e
-        del ws
+        del ws, tprobs
     out["c3_n8000"] = leg
 
 
@@ -470,27 +501,41 @@ def leg_batch(args, torch, pc, semgen, out):
             items.append((torch.from_numpy(np.ascontiguousarray(Xb)).cuda(), ab, -1, bctx.adjacency(nb), rb, cb))
         bprobs = bctx.problems(items)
         bws = bctx.batch_workspace(bprobs)
-        bgraph = bctx.pc_batch_capture(bprobs, bws)
         bst = (pc.pc_run_stats * len(items))()
-        for _ in range(2):
-            bgraph.pc_graph_launch()
-            bgraph.pc_graph_results(bst)
-        torch.cuda.synchronize()
-        reps = max(3, args.steps // 5)
-        b0 = time.perf_counter()
-        for _ in range(reps):
-            # a replay and its results: levels some datasets need beyond the recorded ones run
-            # inside pc_graph_results, so both are timed
-            bgraph.pc_graph_launch()
-            br, bstatus = bgraph.pc_graph_results(bst)
-        torch.cuda.synchronize()
-        bms = (time.perf_counter() - b0) / reps * 1e3
-        bgraph.close()
-    assert br == 0 and all(s == 0 for s in bstatus), (br, bstatus)
+
+        def timed_graph():
+            bgraph = bctx.pc_batch_capture(bprobs, bws)
+            for _ in range(2):
+                bgraph.pc_graph_launch()
+                bgraph.pc_graph_results(bst)
+            torch.cuda.synchronize()
+            reps = max(3, args.steps // 5)
+            b0 = time.perf_counter()
+            for _ in range(reps):
+                # a replay and its results: levels some datasets need beyond the recorded ones run
+                # inside pc_graph_results, so both are timed
+                bgraph.pc_graph_launch()
+                br, bstatus = bgraph.pc_graph_results(bst)
+            torch.cuda.synchronize()
+            bms = (time.perf_counter() - b0) / reps * 1e3
+            bgraph.close()
+            assert br == 0 and all(s == 0 for s in bstatus), (br, bstatus)
+            return bms
+
+        ms_default = timed_graph()
+        progress("batch: tuning")
+        t0 = time.perf_counter()
+        tuning = bctx.pc_tune(bprobs, bws).as_dict()
+        tune_s = time.perf_counter() - t0
+        bms = timed_graph()
     tests = int(sum(sum(s.as_dict()["tests"]) for s in bst))
     out["batch256_graph"] = {"workload": "256 datasets, n~U[20,400], degree~U[2,8], m~U[200,5000], alpha 0.01, fp32",
-                             "ms_per_batch": bms, "status": br, "gpu_tests": tests,
-                             "gpu_tests_per_s": tests / (bms * 1e-3)}
+                             "ms_per_batch": bms, "ms_per_batch_untuned": ms_default, "status": 0,
+                             "gpu_tests": tests, "gpu_tests_per_s": tests / (bms * 1e-3),
+                             "launch_shapes": {"tests_per_lane": tuning["tests_per_lane"],
+                                               "ranks_per_lane": tuning["ranks_per_lane"],
+                                               "lds_budget": tuning["lds_budget"], "tune_s": tune_s,
+                                               "runs": tuning["runs"]}}
 
 
 def leg_orient(args, torch, pc, out, c2):
@@ -537,28 +582,38 @@ def leg_scalability(args, torch, pc, semgen, out):
         for prec in ("fp64", "fp32") if (n, p, m) in fp32_at else ("fp64",):
             progress(f"paper scalability n={n} d={p} m={m}: {prec}")
             sctx = pc.Context(precision=prec)
-            sws = sctx.workspace(n, m)
             sadj = sctx.adjacency(n)
             srecs, scount = sctx.sepsets(n * (n - 1) // 2)
-            walls = []
-            for r in range(3):
-                sst = pc.pc_run_stats()
-                torch.cuda.synchronize()
-                s0 = time.perf_counter()
-                try:
-                    sstatus = sctx.pc_skeleton(Xd, alpha, sadj, srecs, scount, sws, stats=sst)
-                except pc.PCError as e:
-                    sstatus = e.status
-                torch.cuda.synchronize()
-                if r:
-                    walls.append(time.perf_counter() - s0)
-            sd = sst.as_dict()
-            point[prec] = {"ms": float(np.median(walls)) * 1e3, "status": sstatus,
-                           "levels_run": sd["levels_run"], "gpu_tests": int(sum(sd["tests"])),
-                           "rechecks": int(sum(sd["rechecks"])), "fp64_from": sd["fp64_from"],
+            sprobs = sctx.problems([(Xd, alpha, -1, sadj, srecs, scount)])
+            sws = sctx.batch_workspace(sprobs)
+            sst = (pc.pc_run_stats * 1)()
+
+            def wall_ms():
+                walls = []
+                for r in range(3):
+                    torch.cuda.synchronize()
+                    s0 = time.perf_counter()
+                    sr, sstatus = sctx.pc_batch_skeleton(sprobs, sws, sst)
+                    torch.cuda.synchronize()
+                    assert sr == 0 and sstatus == [0], (n, p, m, prec, sr, sstatus)
+                    if r:
+                        walls.append(time.perf_counter() - s0)
+                return float(np.median(walls)) * 1e3
+
+            ms = wall_ms()
+            sd = sst[0].as_dict()
+            point[prec] = {"ms": ms, "status": 0, "levels_run": sd["levels_run"],
+                           "gpu_tests": int(sum(sd["tests"])), "rechecks": int(sum(sd["rechecks"])),
+                           "fp64_from": sd["fp64_from"],
                            "edges": int(pc.bits_to_dense(sadj.cpu().numpy(), n).sum()) // 2}
-            assert sstatus == 0, (n, p, m, prec, sstatus)
-            del sws, sadj, srecs, scount
+            if prec == "fp64":
+                # the same skeleton with launch shapes autotuned on it
+                t0 = time.perf_counter()
+                tuning = sctx.pc_tune(sprobs, sws).as_dict()
+                point[prec]["tune_s"] = time.perf_counter() - t0
+                point[prec]["ms_tuned"] = wall_ms()
+                point[prec]["tests_per_lane"] = tuning["tests_per_lane"]
+            del sws, sadj, srecs, scount, sprobs
             sctx.close()
         points.append(point)
         del Xd

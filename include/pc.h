@@ -348,6 +348,41 @@ pc_status pc_skeleton_ordered(pc_ctx *ctx, const double *X, int64_t m, int64_t n
 pc_status pc_batch_capture_ordered(pc_ctx *ctx, const pc_problem *probs, int count, const pc_order *order,
                                    void *ws, size_t ws_bytes, pc_graph **out);
 
+/* ---------------------------------------------------------------------------------------------
+ * Autotuned launch shapes.
+ *
+ * How fast a level runs depends on how its conditioning sets are cut into work items and staged:
+ * the paper tunes its kernels' shapes per dataset (Sec. 5.4, the configuration study). Because
+ * the skeleton does not depend on these shapes (nor on the order of work, Sec. 2.4), every level
+ * can be timed under each candidate shape on the real workload and take its own best.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t tests_per_lane[PC_MAX_LEVEL + 1]; /* item size bound of level l (as pc_options;
+                                                 0 = the context's option or rule) */
+    int32_t ranks_per_lane[PC_MAX_LEVEL + 1]; /* sets per lane in an item (0 = context's) */
+    int32_t lds_budget[PC_MAX_LEVEL + 1];     /* LDS staging budget in bytes (-1 = context's;
+                                                 0 = the global-memory gather path) */
+    float level_ms[PC_MAX_LEVEL + 1];         /* pc_tune: best level-kernel time of level l */
+    float default_ms[PC_MAX_LEVEL + 1];       /* pc_tune: the same with the context's shapes */
+    int32_t levels;                           /* levels 1 .. levels - 1 were timed */
+    int32_t runs;                             /* skeleton runs the search took */
+} pc_tuning;
+
+/* Measures the level kernels of the batch `probs` (or, with count = 1 and order non-NULL, of
+ * pc_skeleton_ordered on it) under candidate shapes, one parameter at a time for all levels
+ * together: tests_per_lane in {16 .. 2048}, then lds_budget in {0, 8 KiB, 16 KiB, 32 KiB}, then
+ * ranks_per_lane in {1, 2, 4, 8} for levels >= 2. Each level keeps the value with its shortest
+ * time (HIP events; the faster of two runs). Writes the result to *out and applies it to the
+ * context (as pc_set_tuning). Runs the skeleton about 30 times, so the problems' outputs hold a
+ * complete, correct result afterwards; ws as for pc_batch_skeleton (or pc_skeleton_ordered).
+ * Returns the first error of a run, or PC_ERR_INVALID_ARG (order with count > 1). */
+pc_status pc_tune(pc_ctx *ctx, const pc_problem *probs, int count, const pc_order *order, void *ws,
+                  size_t ws_bytes, pc_tuning *out);
+/* Applies per-level shapes to later launches on ctx (graphs capture them as they are when
+ * captured); NULL returns to the context's options. A copy is kept. Values out of range are
+ * PC_ERR_INVALID_ARG. */
+pc_status pc_set_tuning(pc_ctx *ctx, const pc_tuning *t);
+
 /* Candidate features of level `level` for the snapshot adj (device bit matrix, not modified), for
  * training data: rows ordered by i, then j = N_i[p], then k in N_i\{j}, as the ordered run uses them.
  *   feats    device rows x 8 FP32; meta device rows x 3 int32 (i, j, k); cap = rows they hold.
@@ -432,8 +467,8 @@ pc_status pc_comb_unrank(int32_t d, int32_t l, uint64_t t, int32_t skip, int32_t
 double pc_threshold(double alpha, double m, int level);
 
 /* Host-only helper: sizeof of the ABI structs, so bindings can check their layouts.
- * which: 0 pc_options, 1 pc_sep_rec, 2 pc_sepset, 3 pc_run_stats, 4 pc_problem, 5 pc_order;
- * other values return 0. */
+ * which: 0 pc_options, 1 pc_sep_rec, 2 pc_sepset, 3 pc_run_stats, 4 pc_problem, 5 pc_order,
+ * 6 pc_tuning; other values return 0. */
 size_t pc_abi_size(int which);
 
 /* Text of a status code (static storage). */

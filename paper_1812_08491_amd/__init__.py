@@ -7,11 +7,11 @@ from __future__ import annotations
 
 from ._lib import (PC_MAX_LEVEL, PC_MLP_PARAMS, PCError, Context, bits_to_dense, decode_sepsets,
                    default_options, dense_to_bits, lib, pc_comb_unrank, pc_run_stats, pc_threshold,
-                   pc_workspace_bytes, status_str)
+                   pc_tuning, pc_workspace_bytes, status_str)
 
 __all__ = ["PC_MAX_LEVEL", "PC_MLP_PARAMS", "PCError", "Context", "bits_to_dense", "decode_sepsets",
            "default_options", "dense_to_bits", "lib", "pc_comb_unrank", "pc_run_stats",
-           "pc_threshold", "pc_workspace_bytes", "status_str", "skeleton"]
+           "pc_threshold", "pc_tuning", "pc_workspace_bytes", "status_str", "skeleton"]
 
 
 def skeleton(X, alpha: float, max_level: int = -1, precision: str = "fp32", **options):

@@ -104,6 +104,29 @@ class pc_run_stats(ct.Structure):
         }
 
 
+class pc_tuning(ct.Structure):
+    _fields_ = [("tests_per_lane", ct.c_int32 * _NL), ("ranks_per_lane", ct.c_int32 * _NL),
+                ("lds_budget", ct.c_int32 * _NL), ("level_ms", ct.c_float * _NL),
+                ("default_ms", ct.c_float * _NL), ("levels", ct.c_int32), ("runs", ct.c_int32)]
+
+    def as_dict(self) -> dict:
+        k = max(1, self.levels)
+        return {"levels": self.levels, "runs": self.runs,
+                "tests_per_lane": list(self.tests_per_lane[:k]), "ranks_per_lane": list(self.ranks_per_lane[:k]),
+                "lds_budget": list(self.lds_budget[:k]), "level_ms": list(self.level_ms[:k]),
+                "default_ms": list(self.default_ms[:k])}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "pc_tuning":
+        t = cls()
+        for l in range(_NL):
+            t.lds_budget[l] = -1
+        for key in ("tests_per_lane", "ranks_per_lane", "lds_budget"):
+            for l, v in enumerate(d.get(key, [])):
+                getattr(t, key)[l] = int(v)
+        return t
+
+
 class PCError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -166,6 +189,11 @@ def lib() -> ct.CDLL:
         L.pc_batch_capture_ordered.argtypes = [vp, ct.POINTER(pc_problem), ct.c_int, ct.POINTER(pc_order), vp,
                                                ct.c_size_t, ct.POINTER(vp)]
         L.pc_batch_capture_ordered.restype = ct.c_int
+        L.pc_tune.argtypes = [vp, ct.POINTER(pc_problem), ct.c_int, ct.POINTER(pc_order), vp, ct.c_size_t,
+                              ct.POINTER(pc_tuning)]
+        L.pc_tune.restype = ct.c_int
+        L.pc_set_tuning.argtypes = [vp, ct.POINTER(pc_tuning)]
+        L.pc_set_tuning.restype = ct.c_int
         L.pc_graph_launch.argtypes = [vp]
         L.pc_graph_launch.restype = ct.c_int
         L.pc_graph_results.argtypes = [vp, ct.POINTER(pc_run_stats), ct.POINTER(ct.c_int)]
@@ -214,14 +242,14 @@ EXPORTED = ["pc_create", "pc_destroy", "pc_default_options", "pc_workspace_bytes
             "pc_ordered_workspace_bytes", "pc_skeleton_ordered", "pc_features", "pc_row_features", "pc_mlp_forward",
             "pc_mlp_backward", "pc_mlp_bce", "pc_mlp_adam", "pc_orient_workspace_bytes", "pc_orient",
             "pc_corr_workspace_bytes", "pc_level_corr", "pc_skeleton_corr", "pc_row_scores",
-            "pc_batch_capture_ordered",
+            "pc_batch_capture_ordered", "pc_tune", "pc_set_tuning",
             "pc_skeleton_noalloc"]
 
 
 def _check_abi(L: ct.CDLL) -> None:
     # A library built from a different include/pc.h than these structs would write past the
     # caller's buffers (statistics arrays are filled with the library's stride), so refuse it.
-    for k, cls in enumerate([pc_options, pc_sep_rec, pc_sepset, pc_run_stats, pc_problem, pc_order]):
+    for k, cls in enumerate([pc_options, pc_sep_rec, pc_sepset, pc_run_stats, pc_problem, pc_order, pc_tuning]):
         want = int(L.pc_abi_size(k))
         if ct.sizeof(cls) != want:
             raise ImportError(f"{LIB_PATH}: {cls.__name__} is {want} bytes in the library but "
@@ -419,6 +447,18 @@ class Context:
         r = lib().pc_batch_skeleton(self.h, probs, count, stats, status, ct.c_void_p(ws.data_ptr()),
                                     ws.numel())
         return r, [int(x) for x in status]
+
+    def pc_tune(self, probs, ws, order: "pc_order | None" = None) -> pc_tuning:
+        """Times the level kernels of the problems under candidate shapes and applies the fastest per
+        level (pc_tune); returns the tuning."""
+        t = pc_tuning()
+        _check(lib().pc_tune(self.h, probs, len(probs), ct.byref(order) if order is not None else None,
+                             ct.c_void_p(ws.data_ptr()), ws.numel(), ct.byref(t)), "pc_tune", allow_warn=False)
+        return t
+
+    def pc_set_tuning(self, tuning: "pc_tuning | None") -> None:
+        _check(lib().pc_set_tuning(self.h, ct.byref(tuning) if tuning is not None else None), "pc_set_tuning",
+               allow_warn=False)
 
     def pc_batch_capture(self, probs, ws, order: "pc_order | None" = None) -> "Graph":
         g = ct.c_void_p()

@@ -41,6 +41,8 @@ struct pc_ctx {
     int recheck_grid;               // work-groups of the re-check kernel: at most 4 per CU, all resident
     bool tail_enqueued;             // the last enqueue_skeletons ended its levels with the tail kernel
     void *scratch;                  // this device's address of the no-allocation workspace array
+    bool tuned;                     // per-level shapes of pc_set_tuning / pc_tune apply
+    pc_tuning tuning;
 };
 
 struct pc_graph {
@@ -375,31 +377,51 @@ pc_status upload_table(pc_ctx *ctx, const Plan &L, unsigned char *ws, const std:
     return PC_OK;
 }
 
-int auto_grid(const pc_ctx *ctx, int level) {
-    if (ctx->opt.grid > 0) return ctx->opt.grid;
-    const int g = ctx->level_grid[level];
-    return g > 0 ? g : 2 * ctx->num_cu;
+// A tuned per-level value, or 0 (lds_budget: -1) when the level keeps the context's.
+int tuned_at(const pc_ctx *ctx, const int32_t (&v)[PC_MAX_LEVEL + 1], int level, int none) {
+    return ctx->tuned && level >= 1 && level <= PC_MAX_LEVEL ? v[level] : none;
 }
 
 // Conditioning-set ranks per work item. Levels up to kFastLevels give every thread its own sets;
 // deeper levels give every wavefront one set at a time, so their items are much smaller.
 int ranks_per_item(const pc_ctx *ctx, int level) {
-    if (level > kFastLevels) return 4 * (ctx->opt.ranks_per_lane > 0 ? ctx->opt.ranks_per_lane : 4);
+    const int t = tuned_at(ctx, ctx->tuning.ranks_per_lane, level, 0);
+    const int o = t > 0 ? t : ctx->opt.ranks_per_lane;
+    if (level > kFastLevels) return 4 * (o > 0 ? o : 4);
     // Sets per lane: one at level 1 (a set there is a single division), several while a set's
     // factor is cheap, one again once it is long (l^3 work per set at deep levels).
-    const int q = ctx->opt.ranks_per_lane > 0 ? ctx->opt.ranks_per_lane
-                                               : (level == 1 ? 1 : (level <= 3 ? 4 : (level <= 7 ? 2 : 1)));
+    const int q = o > 0 ? o : (level == 1 ? 1 : (level <= 3 ? 4 : (level <= 7 ? 2 : 1)));
     return q * kLevelThreads;
 }
 
+// The batch of one level's launches: its item size bound (planning and level kernels must agree).
+Batch at_level(const pc_ctx *ctx, Batch b, int level) {
+    const int t = tuned_at(ctx, ctx->tuning.tests_per_lane, level, 0);
+    if (t > 0) b.lane_tests = t;
+    return b;
+}
+
 // Dynamic LDS of a level launch: the kernel's fixed part for its precision (the context's, or
-// FP64 for a promoted level) and the row-staging budget.
-int level_lds_bytes(const pc_ctx *ctx, int prec = -1) {
+// FP64 for a promoted level) and the row-staging budget (the level's tuned one, if any).
+int level_lds_bytes(const pc_ctx *ctx, int prec = -1, int level = 0) {
     const size_t fixed = level_lds_fixed(prec >= 0 ? prec : ctx->opt.precision);
-    size_t budget = (size_t)ctx->opt.lds_budget;
+    const int tb = tuned_at(ctx, ctx->tuning.lds_budget, level, -1);
+    size_t budget = (size_t)(tb >= 0 ? tb : ctx->opt.lds_budget);
     const size_t limit = 60 * 1024 - fixed;  // with the kernel's static staging, within 64 KiB
     if (budget > limit) budget = limit;
     return (int)(fixed + budget);
+}
+
+// Work-groups of a level launch: the option, else all that fit at once with the launch's LDS.
+int auto_grid(const pc_ctx *ctx, int level, int prec = -1) {
+    if (ctx->opt.grid > 0) return ctx->opt.grid;
+    const int p = prec >= 0 ? prec : ctx->opt.precision;
+    int g = ctx->level_grid[level];
+    if (p != ctx->opt.precision || tuned_at(ctx, ctx->tuning.lds_budget, level, -1) >= 0) {
+        const int nb = level_blocks_per_cu(p, level, level_lds_bytes(ctx, p, level));
+        g = nb > 0 ? nb * ctx->num_cu : 0;
+    }
+    return g > 0 ? g : 2 * ctx->num_cu;
 }
 
 bool timed(const pc_ctx *ctx, int bit, bool capturing) { return !capturing && (ctx->opt.timing & bit); }
@@ -453,8 +475,9 @@ bool tail_allowed(const pc_ctx *ctx, const OrderRun *ord, int level) {
 // Compaction and planning of one level: the snapshot G' and the work plan (and the stop rule's
 // maximum degree) of every problem. Level PC_MAX_LEVEL + 1 is planned only, to tell whether the
 // level cap stopped a run.
-pc_status enqueue_plan(pc_ctx *ctx, const Batch &b, int level, bool capturing) {
+pc_status enqueue_plan(pc_ctx *ctx, const Batch &b_in, int level, bool capturing) {
     hipStream_t s = ctx->stream;
+    const Batch b = at_level(ctx, b_in, level);
     const int R = ranks_per_item(ctx, level <= PC_MAX_LEVEL ? level : PC_MAX_LEVEL);
     if (timed(ctx, 4, capturing)) PC_HIP(hipEventRecord(ctx->ev_compact[level][0], s));
     PC_HIP(launch_compact(s, b, level, R));
@@ -464,8 +487,9 @@ pc_status enqueue_plan(pc_ctx *ctx, const Batch &b, int level, bool capturing) {
 }
 
 // (Probe pass,) CI tests and FP64 re-check of a planned level.
-pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, const OrderRun *ord) {
+pc_status enqueue_run(pc_ctx *ctx, const Batch &b_in, int level, bool capturing, const OrderRun *ord) {
     hipStream_t s = ctx->stream;
+    const Batch b = at_level(ctx, b_in, level);
     const int R = ranks_per_item(ctx, level);
     // Probe pass of the learned ordering: the best-scored subsets of every edge, before the plain
     // enumeration of the same level.
@@ -488,14 +512,14 @@ pc_status enqueue_run(pc_ctx *ctx, const Batch &b, int level, bool capturing, co
         if (split > T) {
             bm.rank_hi = (unsigned long long)split;
             PC_HIP(launch_window(s, bm, level, R));
-            PC_HIP(launch_level(s, bm, level, R, level_lds_bytes(ctx, b.prec), auto_grid(ctx, level)));
+            PC_HIP(launch_level(s, bm, level, R, level_lds_bytes(ctx, b.prec, level), auto_grid(ctx, level, b.prec)));
             bm.rank_lo = (unsigned long long)split;
             bm.rank_hi = ~0ull;
         }
         PC_HIP(launch_window(s, bm, level, R));
-        PC_HIP(launch_level(s, bm, level, R, level_lds_bytes(ctx, b.prec), auto_grid(ctx, level)));
+        PC_HIP(launch_level(s, bm, level, R, level_lds_bytes(ctx, b.prec, level), auto_grid(ctx, level, b.prec)));
     } else {
-        PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx, b.prec), auto_grid(ctx, level)));
+        PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx, b.prec, level), auto_grid(ctx, level, b.prec)));
     }
     if (timed_level(ctx, level, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][1], s));
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][0], s));
@@ -739,8 +763,9 @@ pc_status promote_fp64(pc_ctx *ctx, const Plan &L, unsigned char *ws, std::vecto
     PC_HIP(launch_corr(s, bc, L.tiles, ctx->num_cu));
     PC_HIP(launch_rearm(s, b));
     const int R = ranks_per_item(ctx, level);
-    PC_HIP(launch_window(s, b, level, R));
-    PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx, PC_PREC_FP64), auto_grid(ctx, level)));
+    const Batch bl = at_level(ctx, b, level);
+    PC_HIP(launch_window(s, bl, level, R));
+    PC_HIP(launch_level(s, bl, level, R, level_lds_bytes(ctx, PC_PREC_FP64, level), auto_grid(ctx, level, PC_PREC_FP64)));
     PC_HIP(launch_recheck(s, b, level, ctx->recheck_grid));
     ctx->top_run = std::max(ctx->top_run, level);
     if (level >= top) return PC_OK;
@@ -1114,7 +1139,10 @@ pc_status pc_batch_skeleton(pc_ctx *ctx, const pc_problem *probs, int count, pc_
     const pc_status r = collect_promoting(ctx, L, w, levels_to_enqueue(probs, count), st, status, host);
     if (st) {
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        for (int d = 0; d < count; ++d) st[d].wall_ms = ms;
+        for (int d = 0; d < count; ++d) {
+            fill_times(ctx, &st[d], ctx->top_run);   // the phases are timed per launch: the batch's
+            st[d].wall_ms = ms;
+        }
     }
     return r;
 }
@@ -1453,6 +1481,102 @@ double pc_threshold(double alpha, double m, int level) {
     return tau_of(z_of_alpha(alpha), m, level);
 }
 
+pc_status pc_set_tuning(pc_ctx *ctx, const pc_tuning *t) {
+    if (!ctx) return PC_ERR_INVALID_ARG;
+    if (!t) {
+        ctx->tuned = false;
+        return PC_OK;
+    }
+    for (int l = 0; l <= PC_MAX_LEVEL; ++l)
+        if (t->tests_per_lane[l] < 0 || t->ranks_per_lane[l] < 0 || t->ranks_per_lane[l] > 64 ||
+            t->lds_budget[l] < -1)
+            return PC_ERR_INVALID_ARG;
+    ctx->tuning = *t;
+    ctx->tuned = true;
+    return PC_OK;
+}
+
+// Coordinate search over the level kernels' shapes: each pass varies one parameter for every
+// level at once, and each level keeps its fastest value (levels are timed independently: the
+// skeleton, and so the work of every level, does not depend on the shapes).
+pc_status pc_tune(pc_ctx *ctx, const pc_problem *probs, int count, const pc_order *order, void *ws,
+                  size_t ws_bytes, pc_tuning *out) {
+    if (!ctx || !probs || count < 1 || !out || (order && count != 1)) return PC_ERR_INVALID_ARG;
+    constexpr int NL = PC_MAX_LEVEL + 1;
+    const int saved_timing = ctx->opt.timing;
+    const bool saved_tuned = ctx->tuned;
+    const pc_tuning saved = ctx->tuning;
+    std::vector<pc_run_stats> st((size_t)count);
+    std::vector<pc_status> status((size_t)count);
+    int levels = 0, runs = 0;
+    ctx->opt.timing = 2;   // the level kernels, HIP events around each level
+    auto run = [&](const pc_tuning &t, float (&ms)[NL]) -> pc_status {
+        ctx->tuning = t;
+        ctx->tuned = true;
+        for (float &x : ms) x = INFINITY;
+        for (int rep = 0; rep < 2; ++rep) {
+            pc_status r;
+            if (order) {
+                const pc_problem &p = probs[0];
+                r = pc_skeleton_ordered(ctx, p.X, p.m, p.n, p.alpha, p.max_level, order, p.adj_out, &p.sep,
+                                        st.data(), ws, ws_bytes);
+            } else {
+                r = pc_batch_skeleton(ctx, probs, count, st.data(), status.data(), ws, ws_bytes);
+            }
+            ++runs;
+            if (r < 0) return r;
+            int lr = st[0].levels_run;
+            if (!order)
+                for (int d = 1; d < count; ++d) lr = std::max(lr, st[d].levels_run);
+            levels = std::max(levels, lr);
+            for (int l = 1; l < std::min(lr, NL); ++l)
+                if (st[0].level_ms[l] > 0.f) ms[l] = std::min(ms[l], st[0].level_ms[l]);
+        }
+        return PC_OK;
+    };
+    pc_tuning cur{};
+    for (int l = 0; l < NL; ++l) cur.lds_budget[l] = -1;
+    float base[NL], best[NL], ms[NL];
+    pc_status r = run(cur, base);
+    for (int l = 0; l < NL; ++l) best[l] = base[l];
+    // One pass: every level tries each value of one field and keeps a value that is at least 1%
+    // faster than its current one.
+    auto pass = [&](int32_t (pc_tuning::*field)[NL], std::initializer_list<int> values, int from_level) {
+        pc_tuning next = cur;
+        for (int v : values) {
+            if (r < 0) return;
+            pc_tuning t = cur;
+            for (int l = from_level; l < NL; ++l) (t.*field)[l] = v;
+            if ((r = run(t, ms)) < 0) return;
+            for (int l = from_level; l < NL; ++l)
+                if (ms[l] < 0.99f * best[l]) {
+                    best[l] = ms[l];
+                    (next.*field)[l] = v;
+                }
+        }
+        cur = next;
+    };
+    if (r >= 0) pass(&pc_tuning::tests_per_lane, {16, 32, 64, 128, 256, 512, 1024, 2048}, 1);
+    if (r >= 0) pass(&pc_tuning::lds_budget, {0, 8192, 16384, 32768}, 1);
+    if (r >= 0) pass(&pc_tuning::ranks_per_lane, {1, 2, 4, 8}, 1);
+    ctx->opt.timing = saved_timing;
+    if (r < 0) {
+        ctx->tuning = saved;
+        ctx->tuned = saved_tuned;
+        return r;
+    }
+    for (int l = 0; l < NL; ++l) {
+        cur.level_ms[l] = std::isfinite(best[l]) ? best[l] : 0.f;
+        cur.default_ms[l] = std::isfinite(base[l]) ? base[l] : 0.f;
+    }
+    cur.levels = levels;
+    cur.runs = runs;
+    *out = cur;
+    ctx->tuning = cur;
+    ctx->tuned = true;
+    return PC_OK;
+}
+
 size_t pc_abi_size(int which) {
     switch (which) {
         case 0: return sizeof(pc_options);
@@ -1461,6 +1585,7 @@ size_t pc_abi_size(int which) {
         case 3: return sizeof(pc_run_stats);
         case 4: return sizeof(pc_problem);
         case 5: return sizeof(pc_order);
+        case 6: return sizeof(pc_tuning);
         default: return 0;
     }
 }

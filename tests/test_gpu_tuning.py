@@ -1,0 +1,128 @@
+"""Autotuned launch shapes (pc_tune, pc_set_tuning; marked gpu).
+
+The skeleton of PC-stable does not depend on how the work of a level is cut into items or staged
+(Sec. 2.4), so any per-level shapes must give the oracle's skeleton; the tuner keeps, per level,
+the fastest shapes it timed, never slower than the context's own (it starts from them).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import semgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1812_08491_amd as pc  # noqa: E402
+
+
+def _problem(ctx, X, alpha, max_level=-1):
+    m, n = X.shape
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    adj = ctx.adjacency(n)
+    recs, count = ctx.sepsets(n * (n - 1) // 2)
+    return (Xd, alpha, max_level, adj, recs, count)
+
+
+def _check(item, X, alpha, ref):
+    Xd, a, ml, adj, recs, count = item
+    m, n = X.shape
+    G = pc.bits_to_dense(adj.cpu().numpy(), n)
+    assert np.array_equal(G, ref.G), np.argwhere(G != ref.G)[:8]
+    k = int(count.item())
+    seps = pc.decode_sepsets(recs[:k].cpu().numpy(), k)
+    assert set(seps) == set(ref.sepsets.as_dict())
+    C = oracle.corr(X)
+    for (i, j), (l, S) in list(seps.items())[:400]:
+        assert oracle.ci_test(C, i, j, list(S), m, alpha)[0], (i, j, S)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_tune_keeps_the_oracle_skeleton(prec):
+    X, sem, alpha = semgen.workload("n1000_d4_m500_fp32")
+    ref = oracle.skeleton_corr(oracle.corr(X), X.shape[0], alpha)
+    ctx = pc.Context(precision=prec)
+    item = _problem(ctx, X, alpha)
+    probs = ctx.problems([item])
+    ws = ctx.batch_workspace(probs)
+    print(f"tune n1000 {prec}", flush=True)
+    t = ctx.pc_tune(probs, ws)
+    d = t.as_dict()
+    assert d["levels"] == ref.levels_run and d["runs"] >= 30
+    for l in range(1, ref.levels_run):
+        assert 0 < d["level_ms"][l] <= d["default_ms"][l], (l, d)
+    _check(item, X, alpha, ref)               # the outputs of the last tuning run
+    r, status = ctx.pc_batch_skeleton(probs, ws)
+    assert r == 0 and status == [0]
+    _check(item, X, alpha, ref)               # a run with the tuning applied
+
+
+def test_extreme_shapes_and_graph_capture_keep_the_skeleton():
+    """Items of one test per lane, the global-memory gather path and 8 sets per lane at every level
+    (planning and level kernels must agree on the item size level by level), eager and captured."""
+    X, sem, alpha = semgen.workload("n1000_d4_m500_fp32")
+    ref = oracle.skeleton_corr(oracle.corr(X), X.shape[0], alpha)
+    ext = pc.pc_tuning.from_dict({"tests_per_lane": [1] * (pc.PC_MAX_LEVEL + 1),
+                                   "ranks_per_lane": [8] * (pc.PC_MAX_LEVEL + 1),
+                                   "lds_budget": [0] * (pc.PC_MAX_LEVEL + 1)})
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = pc.Context(stream=stream, precision="fp32")
+        ctx.pc_set_tuning(ext)
+        item = _problem(ctx, X, alpha)
+        probs = ctx.problems([item])
+        ws = ctx.batch_workspace(probs)
+        r, status = ctx.pc_batch_skeleton(probs, ws)
+        assert r == 0 and status == [0]
+        _check(item, X, alpha, ref)
+        g = ctx.pc_batch_capture(probs, ws)
+        for replay in range(2):
+            g.pc_graph_launch()
+            r, status = g.pc_graph_results()
+            torch.cuda.synchronize()
+            assert r == 0 and status == [0]
+            _check(item, X, alpha, ref)
+        g.close()
+        ctx.pc_set_tuning(None)
+        bad = pc.pc_tuning.from_dict({"lds_budget": [-2]})
+        with pytest.raises(pc.PCError):
+            ctx.pc_set_tuning(bad)
+
+
+def test_tune_ordered_and_dense_rows():
+    """The ordered form (count 1 with an order) on the n = 2000 workload, and the paper's dense
+    family at n = 1000, where item size matters most (long rows)."""
+    from paper_1812_08491_amd import learn
+
+    X, sem, alpha = semgen.workload("n2000_d10_m1000_apply")
+    ref = oracle.skeleton_corr(oracle.corr(X), X.shape[0], alpha)
+    ctx = pc.Context(precision="fp32")
+    item = _problem(ctx, X, alpha)
+    probs = ctx.problems([item])
+    ws = ctx.batch_workspace(probs)
+    params = learn.load_weights(learn.ROW_WEIGHTS)
+    order = ctx.order(None, row_params=params, row_top=2, row_short=learn.ROW_SHORT, row_sort=True,
+                      row_split=32)
+    print("tune ordered n2000", flush=True)
+    t = ctx.pc_tune(probs, ws, order=order)
+    _check(item, X, alpha, ref)
+    print("tuned n2000 level ms", [round(x, 3) for x in t.as_dict()["level_ms"][:4]],
+          "default", [round(x, 3) for x in t.as_dict()["default_ms"][:4]], flush=True)
+    Xs, _, alpha_s = semgen.scalability(1000, 0.1, 10000)
+    C = oracle.corr(Xs)
+    refs = oracle.skeleton_corr(C, Xs.shape[0], alpha_s)
+    sctx = pc.Context(precision="fp64")
+    sitem = _problem(sctx, Xs, alpha_s)
+    sprobs = sctx.problems([sitem])
+    sws = sctx.batch_workspace(sprobs)
+    print("tune paper scalability n1000", flush=True)
+    ts = sctx.pc_tune(sprobs, sws).as_dict()
+    print("tuned level ms", [round(x, 3) for x in ts["level_ms"][:4]], "default",
+          [round(x, 3) for x in ts["default_ms"][:4]], "tests_per_lane", ts["tests_per_lane"][:4], flush=True)
+    assert ts["level_ms"][1] <= ts["default_ms"][1]
+    G = pc.bits_to_dense(sitem[3].cpu().numpy(), 1000)
+    # near-collinear data: the same pairs as the pc_skeleton path may differ from the oracle
+    assert int((G != refs.G).sum()) // 2 <= 50
