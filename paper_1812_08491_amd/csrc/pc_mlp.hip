@@ -758,6 +758,7 @@ struct __align__(16) RowSmem {
     int slist[kRowShortMax];     // short list: positions of the largest |C_ik|, in that order
     float sshort[kRowShortMax];  // model scores of the short list
     int scn[kRowShortMax];       // |N_i & N_k| of the short list
+    int sel_n, tie_n, sel_b, sel_above;   // short-list selection: counts, bucket B, members before B
     float bestv[4];
     int besti[4];
 };
@@ -765,6 +766,33 @@ struct __align__(16) RowSmem {
 // Loads the MLP parameters into LDS (BF16 weights, FP32 biases).
 template <class Smem>
 __device__ inline void load_mlp_bf16(Smem &sm, const float *params, int tid, int nthreads) {
+    // The parameters come through a generic pointer, which the compiler cannot tell apart from
+    // LDS: a load-convert-store loop would wait for every load before its store. With 256 threads
+    // every value a thread needs is loaded first (W2: 16 consecutive values, W1: 2), then stored.
+    if (nthreads == kHid * kHid / 16) {
+        float w2[16], w1[2], bb[3] = {0.f, 0.f, 0.f}, b3 = 0.f;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) w2[u] = params[oW2 + 16 * tid + u];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) w1[u] = params[oW1 + 2 * tid + u];
+        if (tid < kHid) {
+            bb[0] = params[oB1 + tid];
+            bb[1] = params[oB2 + tid];
+            bb[2] = params[oW3 + tid];
+        }
+        if (tid == 0) b3 = params[oB3];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) sm.W2[(16 * tid + u) / kHid][(16 * tid + u) % kHid] = bf16_rne(w2[u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) sm.W1[(2 * tid + u) / kIn][(2 * tid + u) % kIn] = bf16_rne(w1[u]);
+        if (tid < kHid) {
+            sm.b1[tid] = bb[0];
+            sm.b2[tid] = bb[1];
+            sm.W3[tid] = bb[2];
+        }
+        if (tid == 0) sm.b3 = b3;
+        return;
+    }
     for (int e = tid; e < kHid * kIn; e += nthreads) sm.W1[e / kIn][e % kIn] = bf16_rne(params[oW1 + e]);
     for (int e = tid; e < kHid * kHid; e += nthreads) sm.W2[e / kHid][e % kHid] = bf16_rne(params[oW2 + e]);
     if (tid < kHid) {
@@ -979,23 +1007,85 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
                 // |C_ik| alone ranks the candidates (no model).
                 for (int p = tid; p < d; p += 256) sm.sc[p] = sm.ac[p];
             } else if (short_k > 0 && d > short_k) {
-                // Only the short_k candidates of largest |C_ik| are scored by the model; the others
-                // cannot be chosen. A candidate's place in that order is the number of candidates
-                // before it (larger |C_ik|, or equal at a lower position).
-                for (int p = tid; p < d; p += 256) {
+                // Only the short_k candidates of largest |C_ik| (ties: lower position) are scored by
+                // the model; the others cannot be chosen. slist[r] is the candidate of place r in that
+                // order. A histogram of |C_ik| in 256 buckets (largest first) gives the bucket B that
+                // holds the short_k-th candidate: the buckets before it are all in, and only B's few
+                // members are ranked exactly.
+                int *hist = sm.stage;            // free until the tests
+                int *tie = sm.taken;             // free until the argmax rounds
+                hist[tid] = 0;
+                if (tid == 0) { sm.sel_n = 0; sm.tie_n = 0; }
+                __syncthreads();
+                int bk[kRowCap / 256];
+#pragma unroll
+                for (int c = 0; c < kRowCap / 256; ++c) {
+                    const int p = tid + 256 * c;
+                    bk[c] = -1;
+                    if (p < d) {
+                        const int key = (int)(sm.ac[p] * 256.0f);
+                        bk[c] = 255 - (key < 0 ? 0 : (key > 255 ? 255 : key));
+                        atomicAdd(&hist[bk[c]], 1);
+                    }
+                }
+                __syncthreads();
+                if (tid < 64) {   // exclusive scan of the buckets, four per lane; B and the count before it
+                    int v[4], tot = 0;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) { v[c] = hist[4 * tid + c]; tot += v[c]; }
+                    int incl = tot;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int t = __shfl_up(incl, o, 64);
+                        if (tid >= o) incl += t;
+                    }
+                    int run = incl - tot;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (run < short_k && run + v[c] >= short_k) { sm.sel_b = 4 * tid + c; sm.sel_above = run; }
+                        run += v[c];
+                    }
+                }
+                __syncthreads();
+                const int B = sm.sel_b;
+#pragma unroll
+                for (int c = 0; c < kRowCap / 256; ++c) {
+                    const int p = tid + 256 * c;
+                    if (bk[c] >= 0 && bk[c] < B) sm.slist[atomicAdd(&sm.sel_n, 1)] = p;
+                    else if (bk[c] == B) tie[atomicAdd(&sm.tie_n, 1)] = p;
+                }
+                __syncthreads();
+                // B's members by place (|C_ik| descending, then position); the first short_k - above
+                // of them complete the list
+                const int above = sm.sel_above, nt = sm.tie_n;
+                for (int t = tid; t < nt; t += 256) {
+                    const int p = tie[t];
                     const float a = sm.ac[p];
                     int r = 0;
-#pragma unroll 8
-                    for (int q = 0; q < d; q += 4) {   // entries past d hold -1
-                        const float4 c = *reinterpret_cast<const float4 *>(&sm.ac[q]);
-                        r += (c.x > a || (c.x == a && q < p)) ? 1 : 0;
-                        r += (c.y > a || (c.y == a && q + 1 < p)) ? 1 : 0;
-                        r += (c.z > a || (c.z == a && q + 2 < p)) ? 1 : 0;
-                        r += (c.w > a || (c.w == a && q + 3 < p)) ? 1 : 0;
+                    for (int u = 0; u < nt; ++u) {
+                        const int q = tie[u];
+                        const float aq = sm.ac[q];
+                        r += (aq > a || (aq == a && q < p)) ? 1 : 0;
                     }
-                    sm.sc[p] = -INFINITY;
-                    if (r < short_k) sm.slist[r] = p;
+                    if (r < short_k - above) sm.slist[above + r] = p;
                 }
+                __syncthreads();
+                // places among the chosen short_k (they are all in slist, unordered before `above`)
+                {
+                    int p = -1, r = 0;
+                    if (tid < short_k) {
+                        p = sm.slist[tid];
+                        const float a = sm.ac[p];
+                        for (int u = 0; u < short_k; ++u) {
+                            const int q = sm.slist[u];
+                            const float aq = sm.ac[q];
+                            r += (aq > a || (aq == a && q < p)) ? 1 : 0;
+                        }
+                    }
+                    __syncthreads();
+                    if (tid < short_k) sm.slist[r] = p;
+                }
+                for (int p = tid; p < d; p += 256) sm.sc[p] = -INFINITY;
                 // |N_i & N_k| of the short list, all threads at once: one (candidate, word) pair
                 // each, so the adjacency rows of the K candidates are read in one round.
                 if (tid < short_k) sm.scn[tid] = 0;
