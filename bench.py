@@ -62,10 +62,8 @@ TAIL_TESTS = 2048     # c2 graph: levels with more CI tests than this run as lev
 TAIL_MAX_LEVEL = 8    # deepest level the tail kernel runs
 TRAFFIC = {
     "headline": os.path.join(ROOT, "profiles", "traffic_level1_n2000_d10_m1000.json"),
-    "c2": os.path.join(ROOT, "profiles", "traffic_k_level1_n1000_d4_m500.json"),
 }
-LEVEL1_KERNELS = {"headline": ["k_row_order<float>", "k_window", "k_level<float, 1>"],
-                  "c2": ["k_level<float, 1>"]}
+LEVEL1_KERNELS = {"headline": ["k_row_order<float>", "k_window", "k_level<float, 1>"]}
 LEVEL_SOURCES = ["paper_1812_08491_amd/csrc/pc_level.h", "paper_1812_08491_amd/csrc/pc_level_f32.hip",
                  "paper_1812_08491_amd/csrc/pc_level.hip", "paper_1812_08491_amd/csrc/pc_citest.h",
                  "paper_1812_08491_amd/csrc/pc_dev.h", "paper_1812_08491_amd/csrc/pc_comb.h",
@@ -94,7 +92,7 @@ def measured_traffic(leg: str):
     try:
         with open(TRAFFIC[leg]) as f:
             t = json.load(f)
-    except (OSError, ValueError):
+    except (KeyError, OSError, ValueError):
         return None
     if t.get("source_hash") != level_source_hash():
         return None
@@ -213,9 +211,15 @@ def headline(args, torch, pc, semgen, out):
             probs = ctx.problems([(Xd, alpha, -1, adj, recs, count)])
             ws = ctx.batch_workspace(probs)
             # Per-level launch shapes tuned on this workload and order, then recorded in the graph.
-            progress(f"headline: tuning {mode}")
             t0 = time.perf_counter()
-            tuning = ctx.pc_tune(probs, ws, order)
+            if args.load_tuning:
+                # shapes a previous run tuned (profiling runs time exactly that configuration)
+                with open(args.load_tuning) as f:
+                    tuning = pc.pc_tuning.from_dict(json.load(f)[mode])
+                ctx.pc_set_tuning(tuning)
+            else:
+                progress(f"headline: tuning {mode}")
+                tuning = ctx.pc_tune(probs, ws, order)
             tune_s = time.perf_counter() - t0
             graph = ctx.pc_batch_capture(probs, ws, order)
             modes[mode] = dict(ctx=ctx, order=order, adj=adj, recs=recs, count=count, graph=graph, ws=ws,
@@ -270,6 +274,9 @@ def headline(args, torch, pc, semgen, out):
                                     "seconds": modes[mode]["tune_s"],
                                     "level_ms_tuned": [round(x, 4) for x in td["level_ms"]],
                                     "level_ms_default": [round(x, 4) for x in td["default_ms"]]}}
+    if args.save_tuning:
+        with open(args.save_tuning, "w") as f:
+            json.dump({mode: modes[mode]["tuning"].as_dict() for mode in modes}, f)
     G = {mode: pc.bits_to_dense(res[mode].pop("adj"), n) for mode in names}
     sec = res["learned"]["ms_per_step"] * 1e-3
     out.update({
@@ -405,7 +412,7 @@ def leg_c2_graph(args, torch, pc, semgen, out):
         lb = level1_bytes(ref, n)
         ach = lb / (leg["level1_ms_events"] * 1e-3) / 1e9
         leg["roofline_level1"] = {"kernel": "k_level<float,1>", "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
-                                  "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic("c2"),
+                                  "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
                                   "algorithmic_bytes": lb,
                                   "executed_over_canonical": last["tests"][1] / max(1, ref.tests[1])}
         leg["cpu_oracle_s"] = t1
@@ -633,6 +640,8 @@ def main() -> int:
     ap.add_argument("--headline-only", action="store_true",
                     help="only the learned-order steps of the headline (for profiling; no value)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--save-tuning", metavar="JSON", help="write the headline's tuned launch shapes")
+    ap.add_argument("--load-tuning", metavar="JSON", help="use these launch shapes instead of tuning")
     ap.add_argument("--write-traffic", nargs=5, metavar=("LEG", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                          "COPY_WRITE_CSV"))
     args = ap.parse_args()
