@@ -1,10 +1,12 @@
 """GPU parity of libpc.so against the FP64 CPU oracle (runs on an MI355X; marked gpu).
 
 Every call goes through the C ABI (ctypes binding). Inputs are seeded synthetic SEM data. The bar:
-  * C within the stated bound of the FP64 correlation (FP32: (mp+4) 2^-24; BF16x3: 3 2^-18 +
-    (3 mp + 8) 2^-24, mp = m rounded up to 64; FP64: 1e-12);
+  * C within the stated bound of the FP64 correlation (blocked accumulation with compensated block
+    sums, so the bound does not grow with m; u = 2^-24: FP32 37u; BF16x3 (3 + 2^-7) 2^-16 + 195u;
+    FP64 1e-12);
   * the adjacency after level 0, after every level and at the end bit-identical to the oracle's;
-  * every GPU SepSet passes the oracle's FP64 test at its level, drawn from G' of that level.
+  * every GPU SepSet passes the oracle's FP64 test at its level, drawn from G' of that level;
+  * a re-check queue that overflows completes the level in FP64 with the same skeleton.
 """
 import math
 
