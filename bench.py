@@ -640,6 +640,8 @@ def main() -> int:
     ap.add_argument("--headline-only", action="store_true",
                     help="only the learned-order steps of the headline (for profiling; no value)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--leg", choices=["c2", "c3", "batch", "scalability"],
+                    help="run only this leg (for profiling; no headline value)")
     ap.add_argument("--save-tuning", metavar="JSON", help="write the headline's tuned launch shapes")
     ap.add_argument("--load-tuning", metavar="JSON", help="use these launch shapes instead of tuning")
     ap.add_argument("--write-traffic", nargs=5, metavar=("LEG", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
@@ -672,6 +674,11 @@ def main() -> int:
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic linear-Gaussian SEM (seeded), resident in HBM",
     }
+    if args.leg:
+        {"c2": leg_c2_graph, "c3": leg_c3, "batch": leg_batch, "scalability": leg_scalability}[args.leg](
+            args, torch, pc, semgen, out)
+        print(json.dumps(out))
+        return 0
     headline(args, torch, pc, semgen, out)
     if not args.no_extras:
         c2 = leg_c2_graph(args, torch, pc, semgen, out)
