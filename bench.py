@@ -270,7 +270,8 @@ def headline(args, torch, pc, semgen, out):
                          "rechecks": last["rechecks"], "levels_run": last["levels_run"],
                          "level1_pass_ms": float(np.mean(l1)), "adj": modes[mode]["adj"].cpu().numpy(),
                          "tuning": {"tests_per_lane": td["tests_per_lane"], "ranks_per_lane": td["ranks_per_lane"],
-                                    "lds_budget": td["lds_budget"], "runs": td["runs"],
+                                    "lds_budget": td["lds_budget"], "grid": td["grid"],
+                                    "recheck_grid": td["recheck_grid"], "runs": td["runs"],
                                     "seconds": modes[mode]["tune_s"],
                                     "level_ms_tuned": [round(x, 4) for x in td["level_ms"]],
                                     "level_ms_default": [round(x, 4) for x in td["default_ms"]]}}

@@ -362,20 +362,25 @@ typedef struct {
     int32_t ranks_per_lane[PC_MAX_LEVEL + 1]; /* sets per lane in an item (0 = context's) */
     int32_t lds_budget[PC_MAX_LEVEL + 1];     /* LDS staging budget in bytes (-1 = context's;
                                                  0 = the global-memory gather path) */
-    float level_ms[PC_MAX_LEVEL + 1];         /* pc_tune: best level-kernel time of level l */
+    int32_t grid[PC_MAX_LEVEL + 1];           /* work-groups of the level kernels (0 = all that
+                                                 fit at once) */
+    int32_t recheck_grid[PC_MAX_LEVEL + 1];   /* work-groups of the FP64 re-check (0 = 4 per CU) */
+    float level_ms[PC_MAX_LEVEL + 1];         /* pc_tune: best time of level l's test and re-check
+                                                 kernels */
     float default_ms[PC_MAX_LEVEL + 1];       /* pc_tune: the same with the context's shapes */
     int32_t levels;                           /* levels 1 .. levels - 1 were timed */
     int32_t runs;                             /* skeleton runs the search took */
 } pc_tuning;
 
-/* Measures the level kernels of the batch `probs` (or, with count = 1 and order non-NULL, of
- * pc_skeleton_ordered on it) under candidate shapes, one parameter at a time for all levels
- * together: tests_per_lane in {16 .. 2048}, then lds_budget in {0, 8 KiB, 16 KiB, 32 KiB}, then
- * ranks_per_lane in {1, 2, 4, 8} for levels >= 2. Each level keeps the value with its shortest
- * time (HIP events; the faster of two runs). Writes the result to *out and applies it to the
- * context (as pc_set_tuning). Runs the skeleton about 30 times, so the problems' outputs hold a
- * complete, correct result afterwards; ws as for pc_batch_skeleton (or pc_skeleton_ordered).
- * Returns the first error of a run, or PC_ERR_INVALID_ARG (order with count > 1). */
+/* Measures the level and re-check kernels of the batch `probs` (or, with count = 1 and order
+ * non-NULL, of pc_skeleton_ordered on it) under candidate shapes, one parameter at a time for all
+ * levels together: tests_per_lane in {16 .. 2048}, lds_budget in {0, 8 KiB, 16 KiB, 32 KiB},
+ * ranks_per_lane in {1, 2, 4, 8}, grid in {64, 256} work-groups and recheck_grid in {64, 256}.
+ * Each level keeps a value at least 1% faster than its current one (HIP events; the faster of two
+ * runs). Writes the result to *out and applies it to the context (as pc_set_tuning). Runs the
+ * skeleton about 40 times, so the problems' outputs hold a complete, correct result afterwards; ws
+ * as for pc_batch_skeleton (or pc_skeleton_ordered). Returns the first error of a run, or
+ * PC_ERR_INVALID_ARG (order with count > 1). */
 pc_status pc_tune(pc_ctx *ctx, const pc_problem *probs, int count, const pc_order *order, void *ws,
                   size_t ws_bytes, pc_tuning *out);
 /* Applies per-level shapes to later launches on ctx (graphs capture them as they are when

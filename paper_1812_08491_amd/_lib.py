@@ -106,14 +106,16 @@ class pc_run_stats(ct.Structure):
 
 class pc_tuning(ct.Structure):
     _fields_ = [("tests_per_lane", ct.c_int32 * _NL), ("ranks_per_lane", ct.c_int32 * _NL),
-                ("lds_budget", ct.c_int32 * _NL), ("level_ms", ct.c_float * _NL),
+                ("lds_budget", ct.c_int32 * _NL), ("grid", ct.c_int32 * _NL),
+                ("recheck_grid", ct.c_int32 * _NL), ("level_ms", ct.c_float * _NL),
                 ("default_ms", ct.c_float * _NL), ("levels", ct.c_int32), ("runs", ct.c_int32)]
 
     def as_dict(self) -> dict:
         k = max(1, self.levels)
         return {"levels": self.levels, "runs": self.runs,
                 "tests_per_lane": list(self.tests_per_lane[:k]), "ranks_per_lane": list(self.ranks_per_lane[:k]),
-                "lds_budget": list(self.lds_budget[:k]), "level_ms": list(self.level_ms[:k]),
+                "lds_budget": list(self.lds_budget[:k]), "grid": list(self.grid[:k]),
+                "recheck_grid": list(self.recheck_grid[:k]), "level_ms": list(self.level_ms[:k]),
                 "default_ms": list(self.default_ms[:k])}
 
     @classmethod
@@ -121,7 +123,7 @@ class pc_tuning(ct.Structure):
         t = cls()
         for l in range(_NL):
             t.lds_budget[l] = -1
-        for key in ("tests_per_lane", "ranks_per_lane", "lds_budget"):
+        for key in ("tests_per_lane", "ranks_per_lane", "lds_budget", "grid", "recheck_grid"):
             for l, v in enumerate(d.get(key, [])):
                 getattr(t, key)[l] = int(v)
         return t

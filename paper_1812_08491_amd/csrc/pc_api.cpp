@@ -415,6 +415,8 @@ int level_lds_bytes(const pc_ctx *ctx, int prec = -1, int level = 0) {
 // Work-groups of a level launch: the option, else all that fit at once with the launch's LDS.
 int auto_grid(const pc_ctx *ctx, int level, int prec = -1) {
     if (ctx->opt.grid > 0) return ctx->opt.grid;
+    const int tg = tuned_at(ctx, ctx->tuning.grid, level, 0);
+    if (tg > 0) return tg;
     const int p = prec >= 0 ? prec : ctx->opt.precision;
     int g = ctx->level_grid[level];
     if (p != ctx->opt.precision || tuned_at(ctx, ctx->tuning.lds_budget, level, -1) >= 0) {
@@ -422,6 +424,12 @@ int auto_grid(const pc_ctx *ctx, int level, int prec = -1) {
         g = nb > 0 ? nb * ctx->num_cu : 0;
     }
     return g > 0 ? g : 2 * ctx->num_cu;
+}
+
+// Work-groups of a level's re-check launch: the tuned number, else 4 per CU.
+int recheck_grid_at(const pc_ctx *ctx, int level) {
+    const int t = tuned_at(ctx, ctx->tuning.recheck_grid, level, 0);
+    return t > 0 ? t : ctx->recheck_grid;
 }
 
 bool timed(const pc_ctx *ctx, int bit, bool capturing) { return !capturing && (ctx->opt.timing & bit); }
@@ -523,7 +531,7 @@ pc_status enqueue_run(pc_ctx *ctx, const Batch &b_in, int level, bool capturing,
     }
     if (timed_level(ctx, level, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][1], s));
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][0], s));
-    PC_HIP(launch_recheck(s, b, level, ctx->recheck_grid));
+    PC_HIP(launch_recheck(s, b, level, recheck_grid_at(ctx, level)));
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][1], s));
     ctx->top_run = std::max(ctx->top_run, level);
     return PC_OK;
@@ -766,7 +774,7 @@ pc_status promote_fp64(pc_ctx *ctx, const Plan &L, unsigned char *ws, std::vecto
     const Batch bl = at_level(ctx, b, level);
     PC_HIP(launch_window(s, bl, level, R));
     PC_HIP(launch_level(s, bl, level, R, level_lds_bytes(ctx, PC_PREC_FP64, level), auto_grid(ctx, level, PC_PREC_FP64)));
-    PC_HIP(launch_recheck(s, b, level, ctx->recheck_grid));
+    PC_HIP(launch_recheck(s, b, level, recheck_grid_at(ctx, level)));
     ctx->top_run = std::max(ctx->top_run, level);
     if (level >= top) return PC_OK;
     if ((st = enqueue_plan(ctx, b, level + 1, false)) != PC_OK) return st;
@@ -1489,7 +1497,8 @@ pc_status pc_set_tuning(pc_ctx *ctx, const pc_tuning *t) {
     }
     for (int l = 0; l <= PC_MAX_LEVEL; ++l)
         if (t->tests_per_lane[l] < 0 || t->ranks_per_lane[l] < 0 || t->ranks_per_lane[l] > 64 ||
-            t->lds_budget[l] < -1)
+            t->lds_budget[l] < -1 || t->grid[l] < 0 || t->grid[l] > (1 << 20) || t->recheck_grid[l] < 0 ||
+            t->recheck_grid[l] > (1 << 20))
             return PC_ERR_INVALID_ARG;
     ctx->tuning = *t;
     ctx->tuned = true;
@@ -1509,7 +1518,7 @@ pc_status pc_tune(pc_ctx *ctx, const pc_problem *probs, int count, const pc_orde
     std::vector<pc_run_stats> st((size_t)count);
     std::vector<pc_status> status((size_t)count);
     int levels = 0, runs = 0;
-    ctx->opt.timing = 2;   // the level kernels, HIP events around each level
+    ctx->opt.timing = 2 | 8;   // the level and re-check kernels, HIP events around each
     auto run = [&](const pc_tuning &t, float (&ms)[NL]) -> pc_status {
         ctx->tuning = t;
         ctx->tuned = true;
@@ -1530,7 +1539,7 @@ pc_status pc_tune(pc_ctx *ctx, const pc_problem *probs, int count, const pc_orde
                 for (int d = 1; d < count; ++d) lr = std::max(lr, st[d].levels_run);
             levels = std::max(levels, lr);
             for (int l = 1; l < std::min(lr, NL); ++l)
-                if (st[0].level_ms[l] > 0.f) ms[l] = std::min(ms[l], st[0].level_ms[l]);
+                if (st[0].level_ms[l] > 0.f) ms[l] = std::min(ms[l], st[0].level_ms[l] + st[0].recheck_ms[l]);
         }
         return PC_OK;
     };
@@ -1559,6 +1568,8 @@ pc_status pc_tune(pc_ctx *ctx, const pc_problem *probs, int count, const pc_orde
     if (r >= 0) pass(&pc_tuning::tests_per_lane, {16, 32, 64, 128, 256, 512, 1024, 2048}, 1);
     if (r >= 0) pass(&pc_tuning::lds_budget, {0, 8192, 16384, 32768}, 1);
     if (r >= 0) pass(&pc_tuning::ranks_per_lane, {1, 2, 4, 8}, 1);
+    if (r >= 0) pass(&pc_tuning::grid, {64, 256}, 1);
+    if (r >= 0) pass(&pc_tuning::recheck_grid, {64, 256}, 1);
     ctx->opt.timing = saved_timing;
     if (r < 0) {
         ctx->tuning = saved;
