@@ -113,12 +113,22 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level, int w
     const long long chunk = (N + kPlanThreads - 1) / kPlanThreads;
     const long long lo = tid * chunk, hi = lo + chunk < N ? lo + chunk : N;
     long long s = 0;
+#pragma unroll 8
     for (long long k = lo; k < hi; ++k) s += b.nitems[k];
     long long total = 0;
     long long run = block_exclusive_scan<kPlanThreads>(s, part, total);
-    for (long long k = lo; k < hi; ++k) {
-        b.item_off[k] = run;
-        run += b.nitems[k];
+    // Eight counts are loaded before their offsets are stored (the stores could alias the next
+    // loads as far as the compiler knows, which would serialise one load per row).
+    for (long long k0 = lo; k0 < hi; k0 += 8) {
+        long long v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = k0 + u < hi ? b.nitems[k0 + u] : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k0 + u < hi) {
+                b.item_off[k0 + u] = run;
+                run += v[u];
+            }
     }
     if (tid == 0) {
         b.item_off[N] = total;
@@ -143,23 +153,22 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level, int w
         for (int d = tid; d < b.count; d += kPlanThreads) s_maxdeg[d] = 0;
     __syncthreads();
     if (lo < hi) {
+        // The chunk's rows problem by problem: within a problem the degree loads are independent of
+        // each other (one table lookup per problem, not per row), so they are issued together.
         int d = find_base(b.row_base, b.count, lo);
-        int best = 0;
-        for (long long k = lo; k < hi; ++k) {
-            while (k >= b.row_base[d + 1]) {
-                if (best > 0) {
-                    if (in_lds) atomicMax(&s_maxdeg[d], best);
-                    else if (level > b.probs[d].tail_done) atomicMax(&b.probs[d].maxdeg[level], best);
-                }
-                best = 0;
-                ++d;
+        for (long long k = lo; k < hi;) {
+            while (k >= b.row_base[d + 1]) ++d;
+            const long long base = b.row_base[d], end = b.row_base[d + 1] < hi ? b.row_base[d + 1] : hi;
+            const int *deg = b.probs[d].deg + (k - base);
+            const int cnt = (int)(end - k);
+            int best = 0;
+#pragma unroll 8
+            for (int q = 0; q < cnt; ++q) best = deg[q] > best ? deg[q] : best;
+            if (best > 0) {
+                if (in_lds) atomicMax(&s_maxdeg[d], best);
+                else if (level > b.probs[d].tail_done) atomicMax(&b.probs[d].maxdeg[level], best);
             }
-            const int dg = b.probs[d].deg[k - b.row_base[d]];
-            best = dg > best ? dg : best;
-        }
-        if (best > 0) {
-            if (in_lds) atomicMax(&s_maxdeg[d], best);
-            else if (level > b.probs[d].tail_done) atomicMax(&b.probs[d].maxdeg[level], best);
+            k = end;
         }
     }
     if (in_lds) {
