@@ -274,6 +274,32 @@ class NodeRowCollector:
         mi, mk = self.meta[:rows].long().unbind(1)
         return self.feats[:rows].clone(), self.labels[:rows].clone(), mi, mk, C
 
+    def plain_level1_records(self, X, alpha: float):
+        """(i, j, k) of every edge the plain skeleton removes at level 1 on X, with its SepSet {k}."""
+        torch = _torch()
+        n = self.n
+        Xd = X if torch.is_tensor(X) else torch.from_numpy(np.ascontiguousarray(X)).cuda()
+        adj = self.ctx.adjacency(n)
+        recs, count = self.ctx.sepsets(n * (n - 1) // 2)
+        self.ctx.pc_skeleton(Xd, alpha, adj, recs, count, self.ws, max_level=1)
+        r = recs[:int(count.item())].long()
+        r = r[r[:, 2] == 1]
+        return r[:, [0, 1, 3]]
+
+    def sepset_labels(self, X, alpha: float, mi, mk, records=None):
+        """Labels from the SepSets the plain method finds: for row (i, k), the fraction of the level-1
+        removals of edges at i whose recorded SepSet is {k} (records: plain_level1_records of X, run
+        here when not given)."""
+        torch = _torch()
+        n = self.n
+        r = self.plain_level1_records(X, alpha) if records is None else records
+        i, j, s = r[:, 0], r[:, 1], r[:, 2]
+        hits = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+        hits.index_put_((torch.cat([i, j]), torch.cat([s, s])), torch.ones(2 * i.numel(), device="cuda"),
+                        accumulate=True)
+        per_node = hits.sum(1)
+        return hits[mi, mk] / per_node[mi].clamp(min=1.0)
+
     def close(self):
         self.ctx.close()
 
@@ -347,7 +373,10 @@ def short_list_mask(absc, node, K: int):
 
 def train_rows(args, log) -> None:
     """Shared-set (row) model: level-1 rows of generated n = 200 SEMs, restricted to each node's
-    short list (the ROW_SHORT candidates of largest |C_ik|), soft-label cross-entropy, Adam. With
+    short list (the ROW_SHORT candidates of largest |C_ik|), soft-label cross-entropy, Adam. Labels
+    (--labels): by default the SepSets the plain method records at level 1 (the fraction of node i's
+    level-1 removals whose SepSet is {k}); or the fraction of i's edges {k} separates (k*) or
+    separates and k* does not (the others). With
     --eval, the edge coverage of its top-T candidates per node is reported against the |C_ik| order
     and a random order on held-out SEMs (tests/ref/coverage.py; run from the repository root)."""
     torch = _torch()
@@ -358,7 +387,9 @@ def train_rows(args, log) -> None:
     coll = NodeRowCollector(200, 1000)
     feats, labels = [], []
     for k, (X, _, a) in enumerate(semgen.training_sems(args.sems, instance=0)):
-        f, y, mi, _, _ = coll.run(X, a)
+        f, y, mi, mk, _ = coll.run(X, a)
+        if args.labels == "sepsets":
+            y = coll.sepset_labels(X, a, mi, mk)
         keep = short_list_mask(f[:, 0], mi, K)
         feats.append(f[keep])
         labels.append(y[keep])
@@ -373,6 +404,8 @@ def train_rows(args, log) -> None:
     val = []
     for Xv, _, a in semgen.training_sems(args.val_sems, instance=1):
         f, yv, mi, mk, C = coll.run(Xv, a)
+        if args.labels == "sepsets":
+            yv = coll.sepset_labels(Xv, a, mi, mk)
         G = torch.from_numpy(bits_to_dense(coll.adj.cpu().numpy(), 200).astype(bool)).cuda()
         val.append((f, yv, mi, mk, C, G, a, short_list_mask(f[:, 0], mi, K)))
     trainer = Trainer(seed=args.seed, lr=args.lr)
@@ -419,8 +452,10 @@ def train_rows(args, log) -> None:
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     np.save(out, trainer.params.cpu().numpy().astype(np.float32), allow_pickle=False)
     meta = {"model": "row", "sems": args.sems, "n": 200, "m": 1000, "degree": "U[2,10]", "alpha": 0.01,
-            "row_short": K, "label": "k*: fraction of the row's edges it separates; others: fraction they "
-                                     "separate and k* does not",
+            "row_short": K,
+            "label": ("fraction of the row's level-1 removals whose SepSet (plain method) is {k}"
+                      if args.labels == "sepsets" else
+                      "k*: fraction of the row's edges it separates; others: fraction they separate and k* does not"),
             "features": ["|C_ik|", "|C_ik|/max_q|C_iq|", "min(n|N_i&N_k|/(d_i d_k), 8)/8", "d_k/(d_i+d_k)",
                          "|C_kk*|", "|rho_ik.k*|", "mean_j|C_ij|/max_q|C_iq|", "|N_i&N_k|/d_i"],
             "order": "k* (largest |C_ik|) first; the model picks the next from the row_short candidates of "
@@ -447,6 +482,9 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--short", type=int, default=ROW_SHORT, help="row model: candidates per node it scores")
     ap.add_argument("--eval", action="store_true", help="row model: report held-out edge coverage")
+    ap.add_argument("--labels", choices=("separated", "sepsets"), default="sepsets",
+                    help="row model labels: the fraction of the row's edges a candidate separates (and k* "
+                         "does not), or the fraction of the row's removals whose plain-method SepSet it is")
     args = ap.parse_args(argv)
     import semgen  # the project's seeded SEM generator (repository root)
     torch = _torch()

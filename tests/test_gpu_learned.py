@@ -490,3 +490,39 @@ def test_sorted_and_split_level1_equals_oracle(seed, prec, rank, sort, split):
         assert oracle.ci_test(C, e[0], e[1], list(S), X.shape[0], alpha)[0], (e, S)
     Gp = ref.G_after[0]
     assert (2 * Gp.sum(1) > n).any() and (2 * Gp.sum(1) <= n).any()
+
+
+def test_row_labels_from_plain_sepsets():
+    """Labels from the SepSets of the plain method (the default training labels of the row model):
+    for node i and candidate k, the fraction of the level-1 removals at i whose recorded SepSet is
+    {k}. Checked against the records decoded on the host, and every positive label rests on a test
+    that the oracle's FP64 test confirms (the record's edge is separated by {k})."""
+    from paper_1812_08491_amd import learn
+
+    rng = np.random.default_rng(71)
+    sem = semgen.random_dag(100, 6.0 / 99, rng)
+    X = semgen.sample(sem, 600, rng)
+    alpha = 0.01
+    coll = learn.NodeRowCollector(100, 600)
+    f, y, mi, mk, C = coll.run(X, alpha)
+    rec = coll.plain_level1_records(X, alpha)
+    lab = coll.sepset_labels(X, alpha, mi, mk, records=rec).cpu().numpy()
+    mi_h, mk_h = mi.cpu().numpy(), mk.cpu().numpy()
+    # host recount from the same records
+    hits = np.zeros((100, 100))
+    by_k = {}
+    for i, j, k in rec.cpu().numpy().tolist():
+        hits[i, k] += 1
+        hits[j, k] += 1
+        by_k.setdefault((i, k), []).append(j)
+        by_k.setdefault((j, k), []).append(i)
+    per = np.maximum(hits.sum(1), 1.0)
+    assert np.allclose(lab, hits[mi_h, mk_h] / per[mi_h])
+    C64 = oracle.corr(X)
+    pos = np.nonzero(lab > 0)[0]
+    assert pos.size > 0
+    for r in pos[:300]:
+        i, k = int(mi_h[r]), int(mk_h[r])
+        for j in by_k[(i, k)]:
+            assert oracle.ci_test(C64, i, j, [k], 600, alpha)[0], (i, j, k)
+    coll.close()
