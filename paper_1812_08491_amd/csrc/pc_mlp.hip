@@ -1244,7 +1244,9 @@ __global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const flo
             auto CI1 = [&](int a) -> T { return CIv(a); };
             SetFactor<T, 1> f;
             f.build(P1, CS1, CI1);
-            const T col[1] = {C[(int64_t)j * n + k]};
+            // C[k, j] from the row of the set element (C is exactly symmetric): the threads of a set
+            // read ascending columns of one row instead of one row each
+            const T col[1] = {C[(int64_t)k * n + j]};
             ++my_tests;
             const int dec = f.test_vals(col, CIv(q), tau, tl, band);
             if (dec == 2) {

@@ -113,8 +113,10 @@ __device__ void tail_tests(const Batch &b, Prob &P, int pd, TailSmem &sm, RqEntr
             for (int u = 0; u < kB; ++u) {
                 const int j = jb[u];
                 go[u] = go[u] && ((live_word(arow + (j >> 6)) >> (j & 63)) & 1ull);
+                // C[S_r, j] from the rows of the set (C is exactly symmetric): the threads sharing a
+                // set read ascending columns of the same rows
 #pragma unroll
-                for (int r = 0; r < L; ++r) col[u][r] = go[u] ? C[(int64_t)j * n + sid[r]] : (T)0;
+                for (int r = 0; r < L; ++r) col[u][r] = go[u] ? C[(int64_t)sid[r] * n + j] : (T)0;
                 cij[u] = go[u] ? C[(int64_t)row * n + j] : (T)0;
             }
 #pragma unroll
