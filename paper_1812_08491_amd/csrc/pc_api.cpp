@@ -43,6 +43,10 @@ struct pc_ctx {
     void *scratch;                  // this device's address of the no-allocation workspace array
     bool tuned;                     // per-level shapes of pc_set_tuning / pc_tune apply
     pc_tuning tuning;
+    // Phases whose events the current call recorded (bit l: level l), so that only those are read
+    // back: a level the tail kernel ran has none, and events of an earlier call are stale.
+    unsigned long long rec_compact, rec_level, rec_recheck;
+    bool rec_prep, rec_corr;
 };
 
 struct pc_graph {
@@ -432,6 +436,22 @@ int recheck_grid_at(const pc_ctx *ctx, int level) {
     return t > 0 ? t : ctx->recheck_grid;
 }
 
+void reset_timed(pc_ctx *ctx) {
+    ctx->rec_compact = ctx->rec_level = ctx->rec_recheck = 0ull;
+    ctx->rec_prep = ctx->rec_corr = false;
+}
+
+// Milliseconds between two events recorded by the current call (0 if the query fails; its error is
+// cleared, so that the next launch's hipGetLastError does not report it).
+float event_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        ms = 0.f;
+    }
+    return ms;
+}
+
 bool timed(const pc_ctx *ctx, int bit, bool capturing) { return !capturing && (ctx->opt.timing & bit); }
 
 // Level kernels of level l are timed: every level (bit 2) or level 1 alone (bit 32). Not inside a
@@ -448,10 +468,16 @@ pc_status enqueue_corr(pc_ctx *ctx, const Batch &b, const Plan &L, bool capturin
     if (timed(ctx, 16, capturing)) PC_HIP(hipEventRecord(ctx->ev_prep[0], s));
     PC_HIP(launch_colstats(s, b, L.cs_blocks));
     PC_HIP(launch_standardize(s, b, L.st_blocks));
-    if (timed(ctx, 16, capturing)) PC_HIP(hipEventRecord(ctx->ev_prep[1], s));
+    if (timed(ctx, 16, capturing)) {
+        PC_HIP(hipEventRecord(ctx->ev_prep[1], s));
+        ctx->rec_prep = true;
+    }
     if (timed(ctx, 1, capturing)) PC_HIP(hipEventRecord(ctx->ev_corr[0], s));
     PC_HIP(launch_corr(s, b, L.tiles, ctx->num_cu));
-    if (timed(ctx, 1, capturing)) PC_HIP(hipEventRecord(ctx->ev_corr[1], s));
+    if (timed(ctx, 1, capturing)) {
+        PC_HIP(hipEventRecord(ctx->ev_corr[1], s));
+        ctx->rec_corr = true;
+    }
     return PC_OK;
 }
 
@@ -490,7 +516,10 @@ pc_status enqueue_plan(pc_ctx *ctx, const Batch &b_in, int level, bool capturing
     if (timed(ctx, 4, capturing)) PC_HIP(hipEventRecord(ctx->ev_compact[level][0], s));
     PC_HIP(launch_compact(s, b, level, R));
     PC_HIP(launch_plan(s, b, level));
-    if (timed(ctx, 4, capturing)) PC_HIP(hipEventRecord(ctx->ev_compact[level][1], s));
+    if (timed(ctx, 4, capturing)) {
+        PC_HIP(hipEventRecord(ctx->ev_compact[level][1], s));
+        ctx->rec_compact |= 1ull << level;
+    }
     return PC_OK;
 }
 
@@ -529,10 +558,16 @@ pc_status enqueue_run(pc_ctx *ctx, const Batch &b_in, int level, bool capturing,
     } else {
         PC_HIP(launch_level(s, b, level, R, level_lds_bytes(ctx, b.prec, level), auto_grid(ctx, level, b.prec)));
     }
-    if (timed_level(ctx, level, capturing)) PC_HIP(hipEventRecord(ctx->ev_level[level][1], s));
+    if (timed_level(ctx, level, capturing)) {
+        PC_HIP(hipEventRecord(ctx->ev_level[level][1], s));
+        ctx->rec_level |= 1ull << level;
+    }
     if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][0], s));
     PC_HIP(launch_recheck(s, b, level, recheck_grid_at(ctx, level)));
-    if (timed(ctx, 8, capturing)) PC_HIP(hipEventRecord(ctx->ev_recheck[level][1], s));
+    if (timed(ctx, 8, capturing)) {
+        PC_HIP(hipEventRecord(ctx->ev_recheck[level][1], s));
+        ctx->rec_recheck |= 1ull << level;
+    }
     ctx->top_run = std::max(ctx->top_run, level);
     return PC_OK;
 }
@@ -680,13 +715,14 @@ pc_status collect(pc_ctx *ctx, size_t table_off, size_t st_off, int count, unsig
 void fill_times(pc_ctx *ctx, pc_run_stats *st, int top_level) {
     if (!st || !ctx->opt.timing) return;
     const int tm = ctx->opt.timing;
-    if (tm & 16) (void)hipEventElapsedTime(&st->prep_ms, ctx->ev_prep[0], ctx->ev_prep[1]);
-    if (tm & 1) (void)hipEventElapsedTime(&st->corr_ms, ctx->ev_corr[0], ctx->ev_corr[1]);
+    if ((tm & 16) && ctx->rec_prep) st->prep_ms = event_ms(ctx->ev_prep[0], ctx->ev_prep[1]);
+    if ((tm & 1) && ctx->rec_corr) st->corr_ms = event_ms(ctx->ev_corr[0], ctx->ev_corr[1]);
     for (int l = 1; l <= std::min(top_level, PC_MAX_LEVEL); ++l) {
-        if (tm & 4) (void)hipEventElapsedTime(&st->compact_ms[l], ctx->ev_compact[l][0], ctx->ev_compact[l][1]);
-        if ((tm & 2) || ((tm & 32) && l == 1))
-            (void)hipEventElapsedTime(&st->level_ms[l], ctx->ev_level[l][0], ctx->ev_level[l][1]);
-        if (tm & 8) (void)hipEventElapsedTime(&st->recheck_ms[l], ctx->ev_recheck[l][0], ctx->ev_recheck[l][1]);
+        const unsigned long long bit = 1ull << l;
+        if ((tm & 4) && (ctx->rec_compact & bit)) st->compact_ms[l] = event_ms(ctx->ev_compact[l][0], ctx->ev_compact[l][1]);
+        if (((tm & 2) || ((tm & 32) && l == 1)) && (ctx->rec_level & bit))
+            st->level_ms[l] = event_ms(ctx->ev_level[l][0], ctx->ev_level[l][1]);
+        if ((tm & 8) && (ctx->rec_recheck & bit)) st->recheck_ms[l] = event_ms(ctx->ev_recheck[l][0], ctx->ev_recheck[l][1]);
     }
 }
 
@@ -715,12 +751,16 @@ pc_status enqueue_skeletons(pc_ctx *ctx, const pc_problem *pp, int count, const 
                             bool given_c = false) {
     const Batch b = make_batch(ctx, L, ws);
     pc_status s = PC_OK;
+    reset_timed(ctx);
     if (given_c) {
         // C is already in the workspace: level 0 reads it directly.
         PC_HIP(launch_init(ctx->stream, b));
         if (timed(ctx, 1, capturing)) PC_HIP(hipEventRecord(ctx->ev_corr[0], ctx->stream));
         PC_HIP(launch_level0_given(ctx->stream, b));
-        if (timed(ctx, 1, capturing)) PC_HIP(hipEventRecord(ctx->ev_corr[1], ctx->stream));
+        if (timed(ctx, 1, capturing)) {
+            PC_HIP(hipEventRecord(ctx->ev_corr[1], ctx->stream));
+            ctx->rec_corr = true;
+        }
     } else if ((s = enqueue_corr(ctx, b, L, capturing)) != PC_OK) {
         return s;
     }
@@ -997,6 +1037,7 @@ pc_status level_common(pc_ctx *ctx, int level, int64_t n, int64_t m, double alph
         PC_HIP(hipMemcpyAsync(w + L.reg[0].c, C_given, sizeof(double) * (size_t)n * (size_t)n,
                               hipMemcpyDeviceToDevice, ctx->stream));
     const Batch b = make_batch(ctx, L, w);
+    reset_timed(ctx);
     PC_HIP(launch_rearm(ctx->stream, b));
     if ((s = enqueue_level(ctx, b, level, false)) != PC_OK) return s;
     std::vector<Prob> host;
@@ -1014,9 +1055,12 @@ pc_status level_common(pc_ctx *ctx, int level, int64_t n, int64_t m, double alph
         st->max_degree[level] = P.maxdeg[level];
         st->fp64_from = promoted;
         const int tm = ctx->opt.timing;
-        if (tm & 4) (void)hipEventElapsedTime(&st->compact_ms[level], ctx->ev_compact[level][0], ctx->ev_compact[level][1]);
-        if (tm & 2) (void)hipEventElapsedTime(&st->level_ms[level], ctx->ev_level[level][0], ctx->ev_level[level][1]);
-        if (tm & 8) (void)hipEventElapsedTime(&st->recheck_ms[level], ctx->ev_recheck[level][0], ctx->ev_recheck[level][1]);
+        const unsigned long long bit = 1ull << level;
+        if ((tm & 4) && (ctx->rec_compact & bit))
+            st->compact_ms[level] = event_ms(ctx->ev_compact[level][0], ctx->ev_compact[level][1]);
+        if ((tm & 2) && (ctx->rec_level & bit)) st->level_ms[level] = event_ms(ctx->ev_level[level][0], ctx->ev_level[level][1]);
+        if ((tm & 8) && (ctx->rec_recheck & bit))
+            st->recheck_ms[level] = event_ms(ctx->ev_recheck[level][0], ctx->ev_recheck[level][1]);
         st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     if (r == PC_ERR_SEPSET_CAPACITY) return r;

@@ -126,3 +126,34 @@ def test_tune_ordered_and_dense_rows():
     G = pc.bits_to_dense(sitem[3].cpu().numpy(), 1000)
     # near-collinear data: the same pairs as the pc_skeleton path may differ from the oracle
     assert int((G != refs.G).sum()) // 2 <= 50
+
+
+def test_timed_runs_with_the_tail_kernel():
+    """Levels the tail kernel runs record no timing events: a timed call must read back only the
+    events it recorded, and leave no error behind for the next call (pc_tune makes 42 timed calls
+    in a row; a captured graph with the tail follows)."""
+    X, sem, alpha = semgen.workload("n1000_d4_m500_fp32")
+    ref = oracle.skeleton_corr(oracle.corr(X), X.shape[0], alpha)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = pc.Context(stream=stream, precision="fp32", timing=1 | 2 | 4 | 8, tail_tests=1 << 30, graph_levels=3)
+        item = _problem(ctx, X, alpha)
+        probs = ctx.problems([item])
+        ws = ctx.batch_workspace(probs)
+        for _ in range(2):
+            st = (pc.pc_run_stats * 1)()
+            r, status = ctx.pc_batch_skeleton(probs, ws, st)
+            assert r == 0 and status == [0]
+            _check(item, X, alpha, ref)
+            d = st[0].as_dict()
+            assert d["level_ms"][1] > 0 and d["corr_ms"] > 0
+        t = ctx.pc_tune(probs, ws).as_dict()
+        assert t["runs"] >= 30
+        _check(item, X, alpha, ref)
+        g = ctx.pc_batch_capture(probs, ws)
+        g.pc_graph_launch()
+        r, status = g.pc_graph_results()
+        torch.cuda.synchronize()
+        assert r == 0 and status == [0]
+        _check(item, X, alpha, ref)
+        g.close()
