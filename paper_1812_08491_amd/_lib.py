@@ -107,7 +107,7 @@ class pc_run_stats(ct.Structure):
 class pc_tuning(ct.Structure):
     _fields_ = [("tests_per_lane", ct.c_int32 * _NL), ("ranks_per_lane", ct.c_int32 * _NL),
                 ("lds_budget", ct.c_int32 * _NL), ("grid", ct.c_int32 * _NL),
-                ("recheck_grid", ct.c_int32 * _NL), ("level_ms", ct.c_float * _NL),
+                ("recheck_grid", ct.c_int32 * _NL), ("set_lanes", ct.c_int32 * _NL), ("level_ms", ct.c_float * _NL),
                 ("default_ms", ct.c_float * _NL), ("levels", ct.c_int32), ("runs", ct.c_int32)]
 
     def as_dict(self) -> dict:
@@ -115,7 +115,8 @@ class pc_tuning(ct.Structure):
         return {"levels": self.levels, "runs": self.runs,
                 "tests_per_lane": list(self.tests_per_lane[:k]), "ranks_per_lane": list(self.ranks_per_lane[:k]),
                 "lds_budget": list(self.lds_budget[:k]), "grid": list(self.grid[:k]),
-                "recheck_grid": list(self.recheck_grid[:k]), "level_ms": list(self.level_ms[:k]),
+                "recheck_grid": list(self.recheck_grid[:k]), "set_lanes": list(self.set_lanes[:k]),
+                "level_ms": list(self.level_ms[:k]),
                 "default_ms": list(self.default_ms[:k])}
 
     @classmethod
@@ -123,7 +124,7 @@ class pc_tuning(ct.Structure):
         t = cls()
         for l in range(_NL):
             t.lds_budget[l] = -1
-        for key in ("tests_per_lane", "ranks_per_lane", "lds_budget", "grid", "recheck_grid"):
+        for key in ("tests_per_lane", "ranks_per_lane", "lds_budget", "grid", "recheck_grid", "set_lanes"):
             for l, v in enumerate(d.get(key, [])):
                 getattr(t, key)[l] = int(v)
         return t

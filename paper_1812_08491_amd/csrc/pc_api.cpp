@@ -325,6 +325,7 @@ Batch make_batch(const pc_ctx *ctx, const Plan &L, unsigned char *ws) {
     const long long groups = ctx->level_grid[1] > 0 ? ctx->level_grid[1] : 4 * ctx->num_cu;
     b.lane_tests = ctx->opt.tests_per_lane > 0 ? ctx->opt.tests_per_lane
                                                : (L.total_rows <= groups ? kAutoLaneTestsSmall : kAutoLaneTests);
+    b.set_lanes = 4;
     const long long *bases = reinterpret_cast<const long long *>(ws + L.table + sizeof(Prob) * L.count);
     b.row_base = bases;
     b.cs_base = bases + (L.count + 1);
@@ -402,6 +403,8 @@ int ranks_per_item(const pc_ctx *ctx, int level) {
 Batch at_level(const pc_ctx *ctx, Batch b, int level) {
     const int t = tuned_at(ctx, ctx->tuning.tests_per_lane, level, 0);
     if (t > 0) b.lane_tests = t;
+    const int sl = tuned_at(ctx, ctx->tuning.set_lanes, level, 0);
+    b.set_lanes = sl > 0 ? sl : 4;
     return b;
 }
 
@@ -1542,7 +1545,9 @@ pc_status pc_set_tuning(pc_ctx *ctx, const pc_tuning *t) {
     for (int l = 0; l <= PC_MAX_LEVEL; ++l)
         if (t->tests_per_lane[l] < 0 || t->ranks_per_lane[l] < 0 || t->ranks_per_lane[l] > 64 ||
             t->lds_budget[l] < -1 || t->grid[l] < 0 || t->grid[l] > (1 << 20) || t->recheck_grid[l] < 0 ||
-            t->recheck_grid[l] > (1 << 20))
+            t->recheck_grid[l] > (1 << 20) ||
+            (t->set_lanes[l] != 0 && (t->set_lanes[l] < 4 || t->set_lanes[l] > 64 ||
+                                      (t->set_lanes[l] & (t->set_lanes[l] - 1)) != 0)))
             return PC_ERR_INVALID_ARG;
     ctx->tuning = *t;
     ctx->tuned = true;
@@ -1563,10 +1568,11 @@ pc_status pc_tune(pc_ctx *ctx, const pc_problem *probs, int count, const pc_orde
     std::vector<pc_status> status((size_t)count);
     int levels = 0, runs = 0;
     ctx->opt.timing = 2 | 8;   // the level and re-check kernels, HIP events around each
-    auto run = [&](const pc_tuning &t, float (&ms)[NL]) -> pc_status {
+    auto run = [&](const pc_tuning &t, float (&ms)[NL], double (&tests)[NL]) -> pc_status {
         ctx->tuning = t;
         ctx->tuned = true;
         for (float &x : ms) x = INFINITY;
+        for (double &x : tests) x = INFINITY;
         for (int rep = 0; rep < 2; ++rep) {
             pc_status r;
             if (order) {
@@ -1582,38 +1588,55 @@ pc_status pc_tune(pc_ctx *ctx, const pc_problem *probs, int count, const pc_orde
             if (!order)
                 for (int d = 1; d < count; ++d) lr = std::max(lr, st[d].levels_run);
             levels = std::max(levels, lr);
-            for (int l = 1; l < std::min(lr, NL); ++l)
+            for (int l = 1; l < std::min(lr, NL); ++l) {
                 if (st[0].level_ms[l] > 0.f) ms[l] = std::min(ms[l], st[0].level_ms[l] + st[0].recheck_ms[l]);
+                double tl = 0.0;
+                for (int d = 0; d < (order ? 1 : count); ++d) tl += (double)st[d].tests[l];
+                tests[l] = std::min(tests[l], tl);
+            }
         }
         return PC_OK;
     };
     pc_tuning cur{};
     for (int l = 0; l < NL; ++l) cur.lds_budget[l] = -1;
-    float base[NL], best[NL], ms[NL];
-    pc_status r = run(cur, base);
-    for (int l = 0; l < NL; ++l) best[l] = base[l];
+    float base[NL], best[NL], fastest[NL], ms[NL];
+    double base_tests[NL], best_tests[NL], tests[NL];
+    pc_status r = run(cur, base, base_tests);
+    for (int l = 0; l < NL; ++l) {
+        best[l] = fastest[l] = base[l];
+        best_tests[l] = base_tests[l];
+    }
     // One pass: every level tries each value of one field and keeps a value that is at least 1%
-    // faster than its current one.
-    auto pass = [&](int32_t (pc_tuning::*field)[NL], std::initializer_list<int> values, int from_level) {
+    // faster than its current one, or within 2% of the fastest time seen at that level while
+    // running at least 10% fewer CI tests (latency-bound launches take about as long with more
+    // speculative tests; the shape that wastes fewer of them is kept).
+    auto pass = [&](int32_t (pc_tuning::*field)[NL], std::initializer_list<int> values, int from_level,
+                    int to_level) {
         pc_tuning next = cur;
         for (int v : values) {
             if (r < 0) return;
             pc_tuning t = cur;
-            for (int l = from_level; l < NL; ++l) (t.*field)[l] = v;
-            if ((r = run(t, ms)) < 0) return;
-            for (int l = from_level; l < NL; ++l)
-                if (ms[l] < 0.99f * best[l]) {
+            for (int l = from_level; l <= to_level; ++l) (t.*field)[l] = v;
+            if ((r = run(t, ms, tests)) < 0) return;
+            for (int l = from_level; l <= to_level; ++l) {
+                const bool faster = ms[l] < 0.99f * best[l];
+                const bool leaner = ms[l] <= 1.02f * fastest[l] && tests[l] <= 0.9 * best_tests[l];
+                fastest[l] = std::min(fastest[l], ms[l]);
+                if (faster || leaner) {
                     best[l] = ms[l];
+                    best_tests[l] = tests[l];
                     (next.*field)[l] = v;
                 }
+            }
         }
         cur = next;
     };
-    if (r >= 0) pass(&pc_tuning::tests_per_lane, {16, 32, 64, 128, 256, 512, 1024, 2048}, 1);
-    if (r >= 0) pass(&pc_tuning::lds_budget, {0, 8192, 16384, 32768}, 1);
-    if (r >= 0) pass(&pc_tuning::ranks_per_lane, {1, 2, 4, 8}, 1);
-    if (r >= 0) pass(&pc_tuning::grid, {64, 256}, 1);
-    if (r >= 0) pass(&pc_tuning::recheck_grid, {64, 256}, 1);
+    if (r >= 0) pass(&pc_tuning::tests_per_lane, {16, 32, 64, 128, 256, 512, 1024, 2048}, 1, NL - 1);
+    if (r >= 0) pass(&pc_tuning::lds_budget, {0, 8192, 16384, 32768}, 1, NL - 1);
+    if (r >= 0) pass(&pc_tuning::ranks_per_lane, {1, 2, 4, 8}, 1, NL - 1);
+    if (r >= 0) pass(&pc_tuning::set_lanes, {16, 64}, 1, 1);
+    if (r >= 0) pass(&pc_tuning::grid, {64, 256}, 1, NL - 1);
+    if (r >= 0) pass(&pc_tuning::recheck_grid, {64, 256}, 1, NL - 1);
     ctx->opt.timing = saved_timing;
     if (r < 0) {
         ctx->tuning = saved;

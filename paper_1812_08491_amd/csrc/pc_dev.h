@@ -120,6 +120,7 @@ struct Batch {
     int prec;
     int force_recheck;
     int lane_tests;                // bound on the CI tests one lane runs per work item (0: none)
+    int set_lanes;                 // level 1: fewest lanes that share one conditioning set
     const long long *row_base;     // count + 1: first flattened row of each problem
     const long long *cs_base;      // count + 1: first k_colstats block
     const long long *st_base;      // count + 1: first k_standardize block

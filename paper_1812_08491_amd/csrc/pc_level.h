@@ -638,7 +638,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
             // several sets at once, and its lanes still carry about kBatch candidates each.
             split = 64;
             if ((mode & 5) == 5 || compact)
-                while (split > 4 && (split / 2) * 8 >= nlive) split >>= 1;
+                while (split > b.set_lanes && (split / 2) * 8 >= nlive) split >>= 1;
         } else if (nr < kLevelThreads) {
             while (split * 2 * nr <= kLevelThreads) split *= 2;
         }

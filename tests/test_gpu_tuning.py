@@ -67,7 +67,8 @@ def test_extreme_shapes_and_graph_capture_keep_the_skeleton():
     ref = oracle.skeleton_corr(oracle.corr(X), X.shape[0], alpha)
     ext = pc.pc_tuning.from_dict({"tests_per_lane": [1] * (pc.PC_MAX_LEVEL + 1),
                                    "ranks_per_lane": [8] * (pc.PC_MAX_LEVEL + 1),
-                                   "lds_budget": [0] * (pc.PC_MAX_LEVEL + 1)})
+                                   "lds_budget": [0] * (pc.PC_MAX_LEVEL + 1),
+                                   "set_lanes": [64] * (pc.PC_MAX_LEVEL + 1)})
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         ctx = pc.Context(stream=stream, precision="fp32")
@@ -87,9 +88,32 @@ def test_extreme_shapes_and_graph_capture_keep_the_skeleton():
             _check(item, X, alpha, ref)
         g.close()
         ctx.pc_set_tuning(None)
-        bad = pc.pc_tuning.from_dict({"lds_budget": [-2]})
-        with pytest.raises(pc.PCError):
-            ctx.pc_set_tuning(bad)
+        for bad in ({"lds_budget": [-2]}, {"set_lanes": [0, 3]}, {"set_lanes": [0, 128]}):
+            with pytest.raises(pc.PCError):
+                ctx.pc_set_tuning(pc.pc_tuning.from_dict(bad))
+
+
+def test_level1_set_lanes_keep_the_skeleton():
+    """Fewer or more lanes per level-1 conditioning set change how many of a short row's sets run
+    at once (and so how many speculative tests run), never the skeleton; a whole wavefront per set
+    runs fewer level-1 tests than four lanes per set on this short-row workload."""
+    X, sem, alpha = semgen.workload("n1000_d4_m500_fp32")
+    ref = oracle.skeleton_corr(oracle.corr(X), X.shape[0], alpha)
+    tests1 = {}
+    for lanes in (4, 16, 64):
+        ctx = pc.Context(precision="fp32")
+        ctx.pc_set_tuning(pc.pc_tuning.from_dict({"set_lanes": [0, lanes]}))
+        item = _problem(ctx, X, alpha)
+        probs = ctx.problems([item])
+        ws = ctx.batch_workspace(probs)
+        stats = (pc.pc_run_stats * 1)()
+        print(f"set_lanes {lanes}", flush=True)
+        r, status = ctx.pc_batch_skeleton(probs, ws, stats)
+        assert r == 0 and status == [0]
+        _check(item, X, alpha, ref)
+        tests1[lanes] = int(stats[0].tests[1])
+    print("level-1 tests by set_lanes", tests1, flush=True)
+    assert tests1[64] < tests1[4]
 
 
 def test_tune_ordered_and_dense_rows():
