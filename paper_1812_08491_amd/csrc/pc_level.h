@@ -510,16 +510,20 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
         const int row = (int)(grow - b.row_base[pd]);
         const glb_ptr<const T> C = (glb_ptr<const T>)(P.C);
         unsigned long long *adj_row = P.adj + (int64_t)row * W;
+        // Live bits of row i, refreshed at every item (other rows remove edges meanwhile); the load
+        // is issued here so that it overlaps the staging below (one word per thread).
+        static_assert(kWcap <= kLevelThreads, "one live-bit word per thread");
+        unsigned long long live_w = 0ull;
+        if (W <= kWcap && tid < W) live_w = live_word(adj_row + tid);
         if (grow != staged) {
+            // The staging is a chain of dependent loads (degree, neighbour ids, then the entries of
+            // C at those ids); loads that do not depend on each other are issued together: the
+            // thread's first neighbour id with the binomials, and C[i, N_i] with the block
+            // C[N_i, N_i] when the block is staged.
             d = __builtin_amdgcn_readfirstlane(P.deg[row]);
             const bool nb_lds = d <= kDcap;
             const bool blk_lds = nb_lds && (long long)d * d <= blk_cap;
-            if (nb_lds)
-                for (int p = tid; p < d; p += kLevelThreads) {
-                    const int k = P.nbr[(int64_t)row * n + p];
-                    lds_nb[p] = k;
-                    lds_ci[p] = C[(int64_t)row * n + k];
-                }
+            const int k_first = nb_lds && tid < d ? P.nbr[(int64_t)row * n + tid] : 0;
             if constexpr (L >= 2) {
                 // The binomials this row's unranking reads, after the block when they fit.
                 const long long off = (long long)lds_fixed_bytes<T>() +
@@ -532,11 +536,18 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                 }
                 if (tid == 0) s_binoff = bin_lds ? (int)off : -1;
             }
+            if (nb_lds)
+                for (int p = tid; p < d; p += kLevelThreads) {
+                    const int k = p == tid ? k_first : P.nbr[(int64_t)row * n + p];
+                    lds_nb[p] = k;
+                    if (!blk_lds) lds_ci[p] = C[(int64_t)row * n + k];
+                }
             __syncthreads();
             if (blk_lds) {
-                // C[N_i, N_i]: each thread issues 8 independent gathers before storing any.
-                const int dd = d * d;
-                for (int e0 = tid; e0 < dd; e0 += 8 * kLevelThreads) {
+                // C[N_i, N_i], then C[i, N_i]: each thread issues 8 independent gathers before
+                // storing any.
+                const int dd = d * d, de = dd + d;
+                for (int e0 = tid; e0 < de; e0 += 8 * kLevelThreads) {
                     T v[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
@@ -545,21 +556,22 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds
                         if (e < dd) {
                             const int p = e / d, q = e - p * d;
                             v[u] = C[(int64_t)lds_nb[p] * n + lds_nb[q]];
+                        } else if (e < de) {
+                            v[u] = C[(int64_t)row * n + lds_nb[e - dd]];
                         }
                     }
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
                         const int e = e0 + u * kLevelThreads;
                         if (e < dd) lds_blk[e] = v[u];
+                        else if (e < de) lds_ci[e - dd] = v[u];
                     }
                 }
             }
             if (tid == 0) s_mode = (nb_lds ? 1 : 0) | (blk_lds ? 2 : 0) | (W <= kWcap ? 4 : 0);
             staged = grow;
         }
-        // Live bits of row i, refreshed at every item (other rows remove edges meanwhile).
-        if (W <= kWcap)
-            for (int w = tid; w < W; w += kLevelThreads) lds_live[w] = live_word(adj_row + w);
+        if (W <= kWcap && tid < W) lds_live[tid] = live_w;
         __syncthreads();
         const int mode = __builtin_amdgcn_readfirstlane(s_mode);
         const glb_ptr<const int> nbg = (glb_ptr<const int>)(P.nbr + (int64_t)row * n);
