@@ -208,7 +208,7 @@ struct Region {
 struct Plan {
     int count = 0;
     int prec = PC_PREC_FP32;
-    size_t st = 0, table = 0, table_bytes = 0, nitems = 0, item_off = 0, rq = 0, total = 0;
+    size_t st = 0, table = 0, table_bytes = 0, nitems = 0, item_off = 0, rowdeg = 0, rq = 0, total = 0;
     int64_t rq_cap = 0;
     long long total_rows = 0, cs_blocks = 0, st_blocks = 0, tiles = 0;
     int64_t max_n = 0;
@@ -247,6 +247,7 @@ Plan make_plan(const int64_t *ns, const int64_t *ms, int count, const pc_options
     L.rq_cap = rq_cap_of(o, sum_n2);
     L.nitems = take(sizeof(long long) * (size_t)L.total_rows);
     L.item_off = take(sizeof(long long) * (size_t)(L.total_rows + 1));
+    L.rowdeg = take(2 * sizeof(int) * (size_t)L.total_rows);
     L.rq = take(sizeof(RqEntry) * (size_t)L.rq_cap);
     L.reg.resize(count);
     for (int d = 0; d < count; ++d) {
@@ -333,6 +334,7 @@ Batch make_batch(const pc_ctx *ctx, const Plan &L, unsigned char *ws) {
     b.tile_base = bases + 3 * (L.count + 1);
     b.nitems = reinterpret_cast<long long *>(ws + L.nitems);
     b.item_off = reinterpret_cast<long long *>(ws + L.item_off);
+    b.rowdeg = reinterpret_cast<int *>(ws + L.rowdeg);
     b.binom = ctx->binom;
     b.st = reinterpret_cast<DevState *>(ws + L.st);
     b.rq = reinterpret_cast<RqEntry *>(ws + L.rq);

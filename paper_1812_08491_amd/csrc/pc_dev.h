@@ -127,6 +127,8 @@ struct Batch {
     const long long *tile_base;    // count + 1: first k_corr tile
     long long *nitems;             // per flattened row: work items of the level
     long long *item_off;           // total_rows + 1 exclusive offsets
+    int *rowdeg;                   // per flattened row: its degree in G' and its problem (2 x
+                                   // total_rows ints, written by the compaction for the planner)
     const unsigned long long *binom;
     DevState *st;
     RqEntry *rq;

@@ -60,6 +60,8 @@ __global__ __launch_bounds__(256) void k_compact(Batch b, int level, int R) {
     if (lane == 0) {
         P.deg[i] = count;
         b.nitems[grow] = row_items(b, P, count, level, R);
+        b.rowdeg[grow] = count;
+        b.rowdeg[b.total_rows + grow] = d;
     }
 }
 
@@ -102,34 +104,96 @@ __device__ inline unsigned long long item_stride(long long total, long long rows
 }
 
 constexpr int kPlanThreads = 1024;
+constexpr int kPlanPer = 4;                           // rows per thread in a tile
+constexpr int kPlanTile = kPlanThreads * kPlanPer;    // rows per tile
 constexpr int kPlanLdsProbs = 4096;     // problems whose max degree is reduced in LDS
 
+// One work-group plans the level for the whole batch. The per-row values are read a tile of
+// kPlanTile rows at a time with coalesced loads into LDS (a wavefront reads consecutive rows), and
+// each thread then works on kPlanPer consecutive rows of the tile from LDS: with one thread per
+// contiguous chunk of rows in global memory instead, every load instruction of a wavefront would
+// touch 64 different cache lines of the one CU that runs the plan. The loads of the next tile are
+// in flight while the current one is scanned.
 __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level, int window) {
     __shared__ long long part[kPlanThreads / 64];
+    __shared__ long long t_items[kPlanTile];   // work items, then their offsets
+    __shared__ int t_deg[kPlanTile], t_prob[kPlanTile];
+    __shared__ int s_maxdeg[kPlanLdsProbs];
     DevState *st = b.st;
     if (st->done) return;
     const int tid = threadIdx.x;
     const long long N = b.total_rows;
-    const long long chunk = (N + kPlanThreads - 1) / kPlanThreads;
-    const long long lo = tid * chunk, hi = lo + chunk < N ? lo + chunk : N;
-    long long s = 0;
-#pragma unroll 8
-    for (long long k = lo; k < hi; ++k) s += b.nitems[k];
-    long long total = 0;
-    long long run = block_exclusive_scan<kPlanThreads>(s, part, total);
-    // Eight counts are loaded before their offsets are stored (the stores could alias the next
-    // loads as far as the compiler knows, which would serialise one load per row).
-    for (long long k0 = lo; k0 < hi; k0 += 8) {
-        long long v[8];
+    // Max degree of G' per problem (what the stop rule of Algorithm 1 looks at): segment maxima of
+    // a thread's rows meet in LDS (one slot per problem) when the batch is small enough, so no
+    // global address sees more than one write per problem.
+    const bool in_lds = b.count <= kPlanLdsProbs;
+    const bool degrees = !window;
+    if (degrees && in_lds)
+        for (int d = tid; d < b.count; d += kPlanThreads) s_maxdeg[d] = 0;
+    auto flush = [&](int d, int best) {
+        if (d < 0 || best <= 0) return;
+        if (in_lds) atomicMax(&s_maxdeg[d], best);
+        else if (level > b.probs[d].tail_done) atomicMax(&b.probs[d].maxdeg[level], best);
+    };
+    long long v[kPlanPer];
+    int dg[kPlanPer], pr[kPlanPer];
+    auto fetch = [&](long long t0) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = k0 + u < hi ? b.nitems[k0 + u] : 0;
+        for (int u = 0; u < kPlanPer; ++u) {
+            const long long r = t0 + (long long)u * kPlanThreads + tid;
+            v[u] = r < N ? b.nitems[r] : 0;
+            dg[u] = degrees && r < N ? b.rowdeg[r] : 0;
+            pr[u] = degrees && r < N ? b.rowdeg[N + r] : -1;
+        }
+    };
+    fetch(0);
+    long long carry = 0;
+    for (long long t0 = 0; t0 < N; t0 += kPlanTile) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (k0 + u < hi) {
-                b.item_off[k0 + u] = run;
-                run += v[u];
+        for (int u = 0; u < kPlanPer; ++u) {
+            t_items[u * kPlanThreads + tid] = v[u];
+            t_deg[u * kPlanThreads + tid] = dg[u];
+            t_prob[u * kPlanThreads + tid] = pr[u];
+        }
+        if (t0 + kPlanTile < N) fetch(t0 + kPlanTile);
+        __syncthreads();
+        long long a[kPlanPer], s = 0;
+#pragma unroll
+        for (int u = 0; u < kPlanPer; ++u) {
+            a[u] = t_items[kPlanPer * tid + u];
+            s += a[u];
+        }
+        if (degrees) {
+            int cur = -1, best = 0;
+#pragma unroll
+            for (int u = 0; u < kPlanPer; ++u) {
+                const int p = t_prob[kPlanPer * tid + u], x = t_deg[kPlanPer * tid + u];
+                if (p != cur) {
+                    flush(cur, best);
+                    cur = p;
+                    best = 0;
+                }
+                best = x > best ? x : best;
             }
+            flush(cur, best);
+        }
+        long long tot = 0;
+        long long run = carry + block_exclusive_scan<kPlanThreads>(s, part, tot);
+#pragma unroll
+        for (int u = 0; u < kPlanPer; ++u) {
+            t_items[kPlanPer * tid + u] = run;
+            run += a[u];
+        }
+        carry += tot;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPlanPer; ++u) {
+            const long long r = t0 + (long long)u * kPlanThreads + tid;
+            if (r < N) b.item_off[r] = t_items[u * kPlanThreads + tid];
+        }
+        __syncthreads();   // the tiles and the scan's LDS are refilled next
     }
+    const long long total = carry;
     if (tid == 0) {
         b.item_off[N] = total;
         st->total_items = (unsigned long long)total;
@@ -142,40 +206,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Batch b, int level, int w
     __syncthreads();
     // Levels the tail kernel already ran keep the statistics it recorded.
     for (int d = tid; d < b.count; d += kPlanThreads)
-        if (level > b.probs[d].tail_done)
+        if (level > b.probs[d].tail_done) {
             b.probs[d].items[level] = b.item_off[b.row_base[d + 1]] - b.item_off[b.row_base[d]];
-    // Max degree of G' per problem (what the stop rule of Algorithm 1 looks at). Each thread scans
-    // its chunk of rows segment by segment; segment maxima meet in LDS (one slot per problem) when
-    // the batch is small enough, so no global address sees more than one write per problem.
-    const bool in_lds = b.count <= kPlanLdsProbs;
-    __shared__ int s_maxdeg[kPlanLdsProbs];
-    if (in_lds)
-        for (int d = tid; d < b.count; d += kPlanThreads) s_maxdeg[d] = 0;
-    __syncthreads();
-    if (lo < hi) {
-        // The chunk's rows problem by problem: within a problem the degree loads are independent of
-        // each other (one table lookup per problem, not per row), so they are issued together.
-        int d = find_base(b.row_base, b.count, lo);
-        for (long long k = lo; k < hi;) {
-            while (k >= b.row_base[d + 1]) ++d;
-            const long long base = b.row_base[d], end = b.row_base[d + 1] < hi ? b.row_base[d + 1] : hi;
-            const int *deg = b.probs[d].deg + (k - base);
-            const int cnt = (int)(end - k);
-            int best = 0;
-#pragma unroll 8
-            for (int q = 0; q < cnt; ++q) best = deg[q] > best ? deg[q] : best;
-            if (best > 0) {
-                if (in_lds) atomicMax(&s_maxdeg[d], best);
-                else if (level > b.probs[d].tail_done) atomicMax(&b.probs[d].maxdeg[level], best);
-            }
-            k = end;
+            if (in_lds) b.probs[d].maxdeg[level] = s_maxdeg[d];
         }
-    }
-    if (in_lds) {
-        __syncthreads();
-        for (int d = tid; d < b.count; d += kPlanThreads)
-            if (level > b.probs[d].tail_done) b.probs[d].maxdeg[level] = s_maxdeg[d];
-    }
 }
 
 hipError_t launch_plan(hipStream_t s, const Batch &b, int level) {
