@@ -159,13 +159,19 @@ __global__ __launch_bounds__(256) void k_standardize(Batch b) {
     const int64_t a0 = (k / rblocks) * 64, r0 = (k % rblocks) * 64;
     const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t a = a0 + c;
+    // The tile's 16 loads per thread are issued together with the column's mean and scale.
+    double xv[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int64_t r = r0 + g + 4 * t;
+        xv[t] = a < n && r < m ? P.X[r * n + a] : 0.0;
+    }
     double mua = 0.0, inva = 0.0;
     if (a < n) { mua = P.mu[a]; inva = P.inv[a]; }
-    for (int rr = g; rr < 64; rr += 4) {
-        const int64_t r = r0 + rr;
-        double z = 0.0;
-        if (a < n && r < m) z = (P.X[r * n + a] - mua) * inva;
-        tile[rr][c] = z;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int64_t r = r0 + g + 4 * t;
+        tile[g + 4 * t][c] = a < n && r < m ? (xv[t] - mua) * inva : 0.0;
     }
     __syncthreads();
     for (int aa = g; aa < 64; aa += 4) {
