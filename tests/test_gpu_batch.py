@@ -217,3 +217,28 @@ def test_ordered_graph_replays_match_oracle(rank):
         check_one(X, a, ml, items[d], status[d])
         if st[d].levels_run > 1:
             assert st[d].probe_tests[1] > 0
+
+
+def test_batch_of_more_problems_than_the_planner_reduces_in_lds():
+    """4200 small datasets: past 4096 problems the planning pass folds each problem's maximum
+    degree (the stop rule of Algorithm 2) with device atomics instead of in LDS; every dataset must
+    still get the oracle's skeleton, SepSets and level count."""
+    rng = np.random.default_rng(4200)
+    batch = []
+    for _ in range(4200):
+        n = int(rng.integers(3, 13))
+        m = int(rng.integers(40, 201))
+        sem = semgen.random_dag(n, semgen.expected_degree_p(n, float(rng.uniform(1.5, 4))), rng)
+        batch.append((semgen.sample(sem, m, rng), 0.05, -1))
+    ctx = pc.Context(precision="fp32")
+    items = [device_problem(ctx, X, a, ml) for X, a, ml in batch]
+    probs = ctx.problems(items)
+    ws = ctx.batch_workspace(probs)
+    stats = (pc.pc_run_stats * len(items))()
+    print("batch of 4200 problems", flush=True)
+    r, status = ctx.pc_batch_skeleton(probs, ws, stats)
+    assert r >= 0
+    for (X, a, ml), item, st, s in zip(batch, items, status, stats):
+        check_one(X, a, ml, item, st)
+        ref = oracle.skeleton(X, a, max_level=ml)
+        assert s.levels_run == ref.levels_run
