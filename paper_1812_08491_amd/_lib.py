@@ -127,7 +127,42 @@ class pc_tuning(ct.Structure):
         for key in ("tests_per_lane", "ranks_per_lane", "lds_budget", "grid", "recheck_grid", "set_lanes"):
             for l, v in enumerate(d.get(key, [])):
                 getattr(t, key)[l] = int(v)
+        for key in ("level_ms", "default_ms"):
+            for l, v in enumerate(d.get(key, [])):
+                getattr(t, key)[l] = float(v)
+        t.levels = int(d.get("levels", 0))
+        t.runs = int(d.get("runs", 0))
         return t
+
+
+_LIB_DIGEST = None
+
+
+def _lib_digest() -> str:
+    """Digest of the built library (a stored tuning belongs to the build that measured it)."""
+    global _LIB_DIGEST
+    if _LIB_DIGEST is None:
+        import hashlib
+        with open(LIB_PATH, "rb") as f:
+            _LIB_DIGEST = hashlib.sha1(f.read()).hexdigest()[:16]
+    return _LIB_DIGEST
+
+
+def _read_tuning_cache(path: str) -> dict:
+    import json
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        data = json.load(f)
+    return data if isinstance(data, dict) else {}
+
+
+def _write_tuning_cache(path: str, entries: dict) -> None:
+    import json
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(entries, f, indent=1)
+    os.replace(tmp, path)
 
 
 class PCError(RuntimeError):
@@ -451,12 +486,41 @@ class Context:
                                     ws.numel())
         return r, [int(x) for x in status]
 
-    def pc_tune(self, probs, ws, order: "pc_order | None" = None) -> pc_tuning:
+    def tuning_key(self, probs, order: "pc_order | None" = None) -> str:
+        """Key of a tuning in a cache file: the problems' shapes, alphas and level caps, the
+        context's options, the order's form and the library build."""
+        import hashlib
+        import json
+        shapes = [(int(p.n), int(p.m), float(p.alpha), int(p.max_level)) for p in probs]
+        opt = ct.string_at(ct.addressof(self.opt), ct.sizeof(self.opt)).hex()
+        form = None
+        if order is not None:
+            form = [int(order.min_level), int(order.max_level), int(order.top), int(order.row_top),
+                    int(order.row_rank), int(order.row_short), int(order.row_sort), int(order.row_split),
+                    bool(order.params), bool(order.row_params)]
+        blob = json.dumps({"shapes": shapes, "opt": opt, "order": form, "lib": _lib_digest()})
+        return hashlib.sha1(blob.encode()).hexdigest()[:20]
+
+    def pc_tune(self, probs, ws, order: "pc_order | None" = None, cache: "str | None" = None) -> pc_tuning:
         """Times the level kernels of the problems under candidate shapes and applies the fastest per
-        level (pc_tune); returns the tuning."""
+        level (pc_tune); returns the tuning. With `cache` (a JSON file): a tuning stored there under
+        this workload's key (tuning_key) is applied without a search (no skeleton runs, the outputs
+        are left as they are); otherwise the search runs and its result is added to the file."""
+        key = None
+        if cache is not None:
+            key = self.tuning_key(probs, order)
+            stored = _read_tuning_cache(cache).get(key)
+            if stored is not None:
+                t = pc_tuning.from_dict(stored)
+                self.pc_set_tuning(t)
+                return t
         t = pc_tuning()
         _check(lib().pc_tune(self.h, probs, len(probs), ct.byref(order) if order is not None else None,
                              ct.c_void_p(ws.data_ptr()), ws.numel(), ct.byref(t)), "pc_tune", allow_warn=False)
+        if cache is not None:
+            entries = _read_tuning_cache(cache)
+            entries[key] = t.as_dict()
+            _write_tuning_cache(cache, entries)
         return t
 
     def pc_set_tuning(self, tuning: "pc_tuning | None") -> None:

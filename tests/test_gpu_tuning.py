@@ -116,6 +116,39 @@ def test_level1_set_lanes_keep_the_skeleton():
     assert tests1[64] < tests1[4]
 
 
+def test_tuning_cache_round_trip(tmp_path):
+    """A tuning stored in a cache file under its workload key is applied by the next pc_tune on the
+    same workload without a search (no skeleton runs), and keeps the oracle's skeleton; another
+    precision gets a key of its own."""
+    import json
+
+    X, sem, alpha = semgen.workload("n1000_d4_m500_fp32")
+    ref = oracle.skeleton_corr(oracle.corr(X), X.shape[0], alpha)
+    cache = str(tmp_path / "tuning.json")
+    ctx = pc.Context(precision="fp32")
+    item = _problem(ctx, X, alpha)
+    probs = ctx.problems([item])
+    ws = ctx.batch_workspace(probs)
+    print("tune with a cache file", flush=True)
+    t1 = ctx.pc_tune(probs, ws, cache=cache)
+    with open(cache) as f:
+        assert list(json.load(f)) == [ctx.tuning_key(probs)]
+    ctx2 = pc.Context(precision="fp32")
+    item2 = _problem(ctx2, X, alpha)
+    probs2 = ctx2.problems([item2])
+    ws2 = ctx2.batch_workspace(probs2)
+    assert ctx2.tuning_key(probs2) == ctx.tuning_key(probs)
+    t2 = ctx2.pc_tune(probs2, ws2, cache=cache)
+    assert t2.as_dict() == t1.as_dict()
+    assert int(item2[5].item()) == 0          # nothing ran: the SepSet counter is untouched
+    r, status = ctx2.pc_batch_skeleton(probs2, ws2)
+    assert r == 0 and status == [0]
+    _check(item2, X, alpha, ref)
+    ctx3 = pc.Context(precision="fp64")
+    probs3 = ctx3.problems([_problem(ctx3, X, alpha)])
+    assert ctx3.tuning_key(probs3) != ctx.tuning_key(probs)
+
+
 def test_tune_ordered_and_dense_rows():
     """The ordered form (count 1 with an order) on the n = 2000 workload, and the paper's dense
     family at n = 1000, where item size matters most (long rows)."""
