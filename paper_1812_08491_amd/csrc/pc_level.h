@@ -418,8 +418,19 @@ __host__ __device__ constexpr size_t lds_fixed_bytes() {
            sizeof(unsigned long long) * kWcap;
 }
 
+// Wavefronts per SIMD the register allocation of k_level<T, L> is held to. A level there is a few
+// rounds of work items of similar latency across all resident work-groups, so one more resident
+// work-group per CU shortens it: FP32 levels 3 and 4 (129-139 registers otherwise) get four, and 6
+// and 7 (162-183) three, at up to 4 spilled registers; levels 5 and 8 would spill 9-10 and are
+// slower held to the next step.
 template <typename T, int L>
-__global__ __launch_bounds__(kLevelThreads) void k_level(Batch b, int R, int lds_bytes) {
+constexpr int level_waves_per_simd() {
+    if (sizeof(T) != 4) return 1;
+    return (L == 3 || L == 4) ? 4 : ((L == 6 || L == 7) ? 3 : 1);
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(kLevelThreads, (level_waves_per_simd<T, L>())) void k_level(Batch b, int R, int lds_bytes) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long s_grow, s_item;
     __shared__ int s_mode;  // bit 0: nb/ci in LDS, bit 1: C[N_i,N_i] in LDS, bit 2: live bits in LDS
