@@ -170,7 +170,7 @@ struct RqView {
 
 // Rows the level-1 shared-set order ranks: degree up to kRowOrderCap and at most kRowOrderWords
 // adjacency words (both staged in LDS by the ordering kernel).
-constexpr int kRowOrderCap = 1024;
+constexpr int kRowOrderCap = 512;
 constexpr int kRowOrderWords = 256;
 __host__ __device__ inline bool l1_ranked(int64_t d, int64_t W) { return d <= kRowOrderCap && W <= kRowOrderWords; }
 // The rank permutation fits after the neighbour list of a row of degree d when 2 d <= n.

@@ -962,7 +962,7 @@ template <typename T>
 // With scores_out (n x n, problem 0 only) the kernel only ranks: it writes each scored candidate's
 // score at [i][k] (-inf for candidates outside the short list) and the chosen candidates at
 // top_out[i][0 .. top) (best first, -1 past the row's choices), and runs no test.
-__global__ __launch_bounds__(256) void k_row_order(Batch b, int level, const float *params, int top, int by_abs,
+__global__ __launch_bounds__(256, 4) void k_row_order(Batch b, int level, const float *params, int top, int by_abs,
                                                     int short_k, int sort_rest, float *scores_out, int *top_out) {
     __shared__ RowSmem<T> sm;
     if (b.st->done) return;

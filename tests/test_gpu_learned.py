@@ -284,7 +284,7 @@ def test_row_order_skeleton_equals_oracle_for_any_weights(seed, prec, row_top, w
 
 
 def test_row_order_rows_beyond_scorer_capacity():
-    """Rows of more than 1024 neighbours are not scored: they keep their order, the ordering pass
+    """Rows of more than 512 neighbours are not scored: they keep their order, the ordering pass
     tests their first sets and the level kernel the rest, so the skeleton is still the oracle's."""
     rng = np.random.default_rng(41)
     F = rng.standard_normal(300)
