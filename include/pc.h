@@ -379,8 +379,8 @@ typedef struct {
 /* Measures the level and re-check kernels of the batch `probs` (or, with count = 1 and order
  * non-NULL, of pc_skeleton_ordered on it) under candidate shapes, one parameter at a time for all
  * levels together: tests_per_lane in {16 .. 2048}, lds_budget in {0, 8 KiB, 16 KiB, 32 KiB},
- * ranks_per_lane in {1, 2, 4, 8}, grid in {64, 256} work-groups, recheck_grid in {64, 256} and
- * (level 1) set_lanes in {16, 64}.
+ * ranks_per_lane in {1, 2, 4, 8}, grid in {16, 64, 256} work-groups, recheck_grid in {16, 64, 256}
+ * and (level 1) set_lanes in {16, 64}.
  * Each level keeps a value at least 1% faster than its current one (HIP events; the faster of two
  * runs), or one within 2% of the fastest time seen at that level that runs at least 10% fewer CI
  * tests than its current one. level_ms is the time of the kept shape. Writes the result to *out and applies it to the context (as pc_set_tuning). Runs the
