@@ -271,7 +271,7 @@ def headline(args, torch, pc, semgen, out):
                          "level1_pass_ms": float(np.mean(l1)), "adj": modes[mode]["adj"].cpu().numpy(),
                          "tuning": {"tests_per_lane": td["tests_per_lane"], "ranks_per_lane": td["ranks_per_lane"],
                                     "lds_budget": td["lds_budget"], "grid": td["grid"],
-                                    "recheck_grid": td["recheck_grid"], "set_lanes": td["set_lanes"][:2],
+                                    "recheck_grid": td["recheck_grid"], "set_lanes": td["set_lanes"][:3],
                                     "runs": td["runs"],
                                     "seconds": modes[mode]["tune_s"],
                                     "level_ms_tuned": [round(x, 4) for x in td["level_ms"]],
@@ -397,7 +397,7 @@ def leg_c2_graph(args, torch, pc, semgen, out):
     td = tuning.as_dict()
     leg = {"workload": "n=1000, degree 4, m=500, alpha 0.01, fp32 + fp64 re-check; one hipGraph replay",
            "launch_shapes": {"tests_per_lane": td["tests_per_lane"], "ranks_per_lane": td["ranks_per_lane"],
-                             "lds_budget": td["lds_budget"], "set_lanes": td["set_lanes"][:2]},
+                             "lds_budget": td["lds_budget"], "set_lanes": td["set_lanes"][:3]},
            "ms_per_skeleton": sec * 1e3, "graph_levels": graph_levels, "levels_run": gd["levels_run"],
            "gpu_tests": int(sum(gd["tests"])), "edges": int(G.sum()) // 2,
            "level1_ms_events": float(np.mean([s["level_ms"][1] for s in sts[1:]])),
@@ -461,7 +461,7 @@ def leg_c3(args, torch, pc, semgen, out):
              "gpu_tests": d["tests"], "rechecks": d["rechecks"], "edges": int(G.sum()) // 2,
              "launch_shapes": {"tests_per_lane": tuning["tests_per_lane"][:4],
                                "ranks_per_lane": tuning["ranks_per_lane"][:4],
-                               "lds_budget": tuning["lds_budget"][:4], "set_lanes": tuning["set_lanes"][:2],
+                               "lds_budget": tuning["lds_budget"][:4], "set_lanes": tuning["set_lanes"][:3],
                                "tune_s": tune_s, "level_ms_untuned": [round(x, 4) for x in tuning["default_ms"][:4]]}}
         flops = float(m) * n * (n - 1)
         if prec == "bf16x3":
@@ -544,7 +544,7 @@ def leg_batch(args, torch, pc, semgen, out):
                              "launch_shapes": {"tests_per_lane": tuning["tests_per_lane"],
                                                "ranks_per_lane": tuning["ranks_per_lane"],
                                                "lds_budget": tuning["lds_budget"],
-                                               "set_lanes": tuning["set_lanes"][:2], "tune_s": tune_s,
+                                               "set_lanes": tuning["set_lanes"][:3], "tune_s": tune_s,
                                                "runs": tuning["runs"]}}
 
 

@@ -365,7 +365,7 @@ typedef struct {
     int32_t grid[PC_MAX_LEVEL + 1];           /* work-groups of the level kernels (0 = all that
                                                  fit at once) */
     int32_t recheck_grid[PC_MAX_LEVEL + 1];   /* work-groups of the FP64 re-check (0 = 4 per CU) */
-    int32_t set_lanes[PC_MAX_LEVEL + 1];      /* level 1 only: fewest lanes that share one
+    int32_t set_lanes[PC_MAX_LEVEL + 1];      /* levels 1 and 2 only: fewest lanes that share one
                                                  conditioning set, a power of two in 4 .. 64
                                                  (0 = 4); fewer lanes per set run more of a short
                                                  row's sets at once */
@@ -380,7 +380,7 @@ typedef struct {
  * non-NULL, of pc_skeleton_ordered on it) under candidate shapes, one parameter at a time for all
  * levels together: tests_per_lane in {16 .. 2048}, lds_budget in {0, 8 KiB, 16 KiB, 32 KiB},
  * ranks_per_lane in {1, 2, 4, 8}, grid in {16, 64, 256} work-groups, recheck_grid in {16, 64, 256}
- * and (level 1) set_lanes in {16, 64}.
+ * and (levels 1 and 2) set_lanes in {16, 64}.
  * Each level keeps a value at least 1% faster than its current one (HIP events; the faster of two
  * runs), or one within 2% of the fastest time seen at that level that runs at least 10% fewer CI
  * tests than its current one. level_ms is the time of the kept shape. Writes the result to *out and applies it to the context (as pc_set_tuning). Runs the

@@ -1636,7 +1636,7 @@ pc_status pc_tune(pc_ctx *ctx, const pc_problem *probs, int count, const pc_orde
     if (r >= 0) pass(&pc_tuning::tests_per_lane, {16, 32, 64, 128, 256, 512, 1024, 2048}, 1, NL - 1);
     if (r >= 0) pass(&pc_tuning::lds_budget, {0, 8192, 16384, 32768}, 1, NL - 1);
     if (r >= 0) pass(&pc_tuning::ranks_per_lane, {1, 2, 4, 8}, 1, NL - 1);
-    if (r >= 0) pass(&pc_tuning::set_lanes, {16, 64}, 1, 1);
+    if (r >= 0) pass(&pc_tuning::set_lanes, {16, 64}, 1, kWaveSetLevels);
     if (r >= 0) pass(&pc_tuning::grid, {16, 64, 256}, 1, NL - 1);
     if (r >= 0) pass(&pc_tuning::recheck_grid, {16, 64, 256}, 1, NL - 1);
     ctx->opt.timing = saved_timing;

@@ -20,6 +20,8 @@ constexpr int kLevelThreads = 256;                    // threads of a level work
 constexpr int kGramLd = PC_MAX_LEVEL + 2;             // leading dimension of an FP64 Gram block
 constexpr int kFastLevels = 13;    // levels whose per-set factor lives in registers (k_level);
                                    // deeper levels factor each set across a wavefront
+constexpr int kWaveSetLevels = 2;  // levels whose conditioning sets are shared by a group of lanes
+                                   // (up to a whole wavefront) that divide the set's candidates
 
 // 64-bit signed counter add (two's complement, so the unsigned atomic is exact).
 __device__ inline void add_ll(long long *p, long long v) {

@@ -389,7 +389,6 @@ __device__ inline void lds_and(lds_ptr<unsigned long long> p, unsigned long long
 // Level kernel
 // ---------------------------------------------------------------------------------------------
 constexpr int kStageCap = kLevelThreads;   // removals staged per item (one settling thread each)
-constexpr int kWaveSetLevels = 1;   // levels whose conditioning sets are shared by a whole wavefront
 constexpr int kDcap = 1024;   // neighbour lists up to this degree are staged in LDS
 constexpr int kWcap = 256;    // live-bit words of a row staged in LDS (n <= 16384)
 
@@ -649,11 +648,12 @@ __global__ __launch_bounds__(kLevelThreads, (level_waves_per_simd<T, L>())) void
         const long long r1 = (long long)whi < r0 + Rr ? (long long)whi : r0 + Rr;
         const long long nr = r1 - r0;
         // `split` threads share each conditioning set and divide its j loop; each group of them
-        // takes qn sets. At level 1 a set needs no factor, so up to a whole wavefront shares it: its
-        // lanes then read one row of C (or of the staged block) at consecutive neighbour positions,
-        // instead of 64 rows at once, and a group's later sets skip the edges its earlier ones
-        // removed. Above (where sets are many and their j loops short), one thread per set, unless
-        // the item has fewer sets than threads.
+        // takes qn sets. At levels 1 and 2 a set needs no factor or a 2 x 2 one, so up to a whole
+        // wavefront shares it: its lanes then read rows of C (or of the staged block) at
+        // consecutive neighbour positions, instead of 64 rows at once, and a group's later sets skip
+        // the edges its earlier ones removed (at level 2 that cuts the tests run by a fifth). Above
+        // (where a set's factor costs more than its j loop), one thread per set, unless the item has
+        // fewer sets than threads.
         int split = 1;
         if (L <= kWaveSetLevels) {
             // A set's lanes are sized to the live list: when few edges of the row are still live

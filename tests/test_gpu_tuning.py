@@ -93,16 +93,16 @@ def test_extreme_shapes_and_graph_capture_keep_the_skeleton():
                 ctx.pc_set_tuning(pc.pc_tuning.from_dict(bad))
 
 
-def test_level1_set_lanes_keep_the_skeleton():
-    """Fewer or more lanes per level-1 conditioning set change how many of a short row's sets run
-    at once (and so how many speculative tests run), never the skeleton; a whole wavefront per set
-    runs fewer level-1 tests than four lanes per set on this short-row workload."""
+def test_set_lanes_keep_the_skeleton():
+    """Fewer or more lanes per level-1 and level-2 conditioning set change how many of a short row's
+    sets run at once (and so how many speculative tests run), never the skeleton; a whole wavefront
+    per set runs fewer level-1 tests than four lanes per set on this short-row workload."""
     X, sem, alpha = semgen.workload("n1000_d4_m500_fp32")
     ref = oracle.skeleton_corr(oracle.corr(X), X.shape[0], alpha)
     tests1 = {}
     for lanes in (4, 16, 64):
         ctx = pc.Context(precision="fp32")
-        ctx.pc_set_tuning(pc.pc_tuning.from_dict({"set_lanes": [0, lanes]}))
+        ctx.pc_set_tuning(pc.pc_tuning.from_dict({"set_lanes": [0, lanes, lanes]}))
         item = _problem(ctx, X, alpha)
         probs = ctx.problems([item])
         ws = ctx.batch_workspace(probs)
