@@ -110,8 +110,16 @@ class pc_tuning(ct.Structure):
                 ("recheck_grid", ct.c_int32 * _NL), ("set_lanes", ct.c_int32 * _NL), ("level_ms", ct.c_float * _NL),
                 ("default_ms", ct.c_float * _NL), ("levels", ct.c_int32), ("runs", ct.c_int32)]
 
+    _SHAPES = ("tests_per_lane", "ranks_per_lane", "lds_budget", "grid", "recheck_grid", "set_lanes")
+
     def as_dict(self) -> dict:
+        # the timed levels, and any level further on whose shape differs from the default
         k = max(1, self.levels)
+        for key in self._SHAPES:
+            arr, dflt = getattr(self, key), (-1 if key == "lds_budget" else 0)
+            for l in range(k, _NL):
+                if arr[l] != dflt:
+                    k = l + 1
         return {"levels": self.levels, "runs": self.runs,
                 "tests_per_lane": list(self.tests_per_lane[:k]), "ranks_per_lane": list(self.ranks_per_lane[:k]),
                 "lds_budget": list(self.lds_budget[:k]), "grid": list(self.grid[:k]),
@@ -124,7 +132,7 @@ class pc_tuning(ct.Structure):
         t = cls()
         for l in range(_NL):
             t.lds_budget[l] = -1
-        for key in ("tests_per_lane", "ranks_per_lane", "lds_budget", "grid", "recheck_grid", "set_lanes"):
+        for key in cls._SHAPES:
             for l, v in enumerate(d.get(key, [])):
                 getattr(t, key)[l] = int(v)
         for key in ("level_ms", "default_ms"):
@@ -146,6 +154,16 @@ def _lib_digest() -> str:
         with open(LIB_PATH, "rb") as f:
             _LIB_DIGEST = hashlib.sha1(f.read()).hexdigest()[:16]
     return _LIB_DIGEST
+
+
+TUNING_CACHE_ENV = "PC_TUNING_CACHE"
+
+
+def default_tuning_cache() -> "str | None":
+    """The tuning cache file that pc_tune reads and extends when a call names none: the path in the
+    environment variable PC_TUNING_CACHE, if it is set and not empty; else None (no file)."""
+    path = os.environ.get(TUNING_CACHE_ENV, "").strip()
+    return path or None
 
 
 def _read_tuning_cache(path: str) -> dict:
@@ -501,11 +519,16 @@ class Context:
         blob = json.dumps({"shapes": shapes, "opt": opt, "order": form, "lib": _lib_digest()})
         return hashlib.sha1(blob.encode()).hexdigest()[:20]
 
-    def pc_tune(self, probs, ws, order: "pc_order | None" = None, cache: "str | None" = None) -> pc_tuning:
+    def pc_tune(self, probs, ws, order: "pc_order | None" = None, cache: "str | bool | None" = None) -> pc_tuning:
         """Times the level kernels of the problems under candidate shapes and applies the fastest per
-        level (pc_tune); returns the tuning. With `cache` (a JSON file): a tuning stored there under
-        this workload's key (tuning_key) is applied without a search (no skeleton runs, the outputs
-        are left as they are); otherwise the search runs and its result is added to the file."""
+        level (pc_tune); returns the tuning. With a cache (a JSON file: `cache`, or when it is None
+        the file that PC_TUNING_CACHE names; False for none): a tuning stored there under this
+        workload's key (tuning_key) is applied without a search (no skeleton runs, the outputs are
+        left as they are); otherwise the search runs and its result is added to the file."""
+        if cache is None:
+            cache = default_tuning_cache()
+        elif cache is False:
+            cache = None
         key = None
         if cache is not None:
             key = self.tuning_key(probs, order)

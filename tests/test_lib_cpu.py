@@ -157,3 +157,25 @@ def test_abi_mismatch_is_refused_at_load():
     with pytest.raises(ImportError, match="pc_run_stats"):
         _lib._check_abi(FakeLib())
     _lib._check_abi(_lib.lib())
+
+
+def test_tuning_cache_file_and_its_environment_default(tmp_path, monkeypatch):
+    """pc_tune's cache: the file named by PC_TUNING_CACHE is the default (unset or empty: none), and
+    a tuning written under a key reads back field by field (launch shapes of every level)."""
+    monkeypatch.delenv(_lib.TUNING_CACHE_ENV, raising=False)
+    assert _lib.default_tuning_cache() is None
+    monkeypatch.setenv(_lib.TUNING_CACHE_ENV, "  ")
+    assert _lib.default_tuning_cache() is None
+    path = str(tmp_path / "tuning.json")
+    monkeypatch.setenv(_lib.TUNING_CACHE_ENV, path)
+    assert _lib.default_tuning_cache() == path
+    nl = pc.PC_MAX_LEVEL + 1
+    shapes = {"tests_per_lane": [16 * (l % 5) for l in range(nl)], "lds_budget": [-1, 0, 8192] + [-1] * (nl - 3),
+              "ranks_per_lane": [l % 3 for l in range(nl)], "grid": [0, 64, 256] + [0] * (nl - 3),
+              "recheck_grid": [16] * nl, "set_lanes": [0, 16, 64] + [0] * (nl - 3)}
+    t = _lib.pc_tuning.from_dict(shapes)
+    assert _lib._read_tuning_cache(path) == {}
+    _lib._write_tuning_cache(path, {"k1": t.as_dict()})
+    back = _lib.pc_tuning.from_dict(_lib._read_tuning_cache(path)["k1"]).as_dict()
+    for field, values in shapes.items():
+        assert back[field][:nl] == values, field
